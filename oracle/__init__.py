@@ -1,0 +1,271 @@
+"""Plain FP64 CPU oracle for the batched EMRI log-likelihood (arXiv:2311.17174).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
+with the HIP library under ``paper_2311_17174_amd``; the two meet only through
+the seeded input generators of ``paper_2311_17174_amd.workloads``, which hold
+none of the method's arithmetic.
+
+The numerics live in ``emri_oracle.c`` (plain C, FP64, OpenMP over walkers);
+this module compiles it with gcc and marshals numpy arrays through ctypes.
+
+Layouts (all float64, C order):
+  params  [B][17]                 parameter rows, see ``PARAM_NAMES``
+  orbit   [B][K+1][10]            node values Y_k then dY/dt at t_k = k h_c
+  waveform[B][2][N]               channels I and II, unit distance, GR
+  spectrum[B][2][N/2+1] complex   dt * DFT of each channel, bins 0..N/2
+  data    [2][N/2+1] complex      frequency-domain data
+  psd     [N/2+1]                 one-sided noise PSD
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "emri_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+PARAM_NAMES = ("M", "mu", "a", "e0", "nu0", "Phi0", "gamma0", "alpha0", "cos_lambda",
+               "theta_S", "phi_S", "theta_K", "phi_K", "d_L", "Xi0", "n_Xi", "alpha_T")
+NPAR = 17
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [("T_obs", ctypes.c_double), ("dt", ctypes.c_double), ("N", ctypes.c_int64),
+                ("n_harm", ctypes.c_int32), ("coarse_log2", ctypes.c_int32),
+                ("lo_only", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+@dataclass(frozen=True)
+class OracleConfig:
+    T_obs: float
+    dt: float
+    N: int
+    n_harm: int
+    coarse_log2: int = 10
+    lo_only: bool = False
+
+    @property
+    def n_valid(self) -> int:
+        return int(round(self.T_obs / self.dt))
+
+    @property
+    def n_intervals(self) -> int:
+        m = 1 << self.coarse_log2
+        return (self.n_valid + m - 1) // m
+
+    def c(self) -> _Cfg:
+        return _Cfg(self.T_obs, self.dt, self.N, self.n_harm, self.coarse_log2,
+                    1 if self.lo_only else 0, 0)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-Wall", "-Wno-unknown-pragmas", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        cp = ctypes.POINTER(_Cfg)
+        i64 = ctypes.c_int64
+        sig = {
+            "oracle_scalars": ([dp, i64, dp], ctypes.c_int),
+            "oracle_rhs": ([dp, dp, ctypes.c_int, dp], ctypes.c_int),
+            "oracle_orbit": ([dp, i64, cp, dp, ip], ctypes.c_int),
+            "oracle_waveform": ([dp, i64, cp, dp], ctypes.c_int),
+            "oracle_waveform_diag": ([dp, cp, dp, dp], ctypes.c_int),
+            "oracle_rfft": ([dp, i64, i64, ctypes.c_double, dp], ctypes.c_int),
+            "oracle_loglike": ([dp, i64, dp, dp, cp, dp], ctypes.c_int),
+            "oracle_psd_bc04": ([dp, i64, dp], ctypes.c_int),
+            "oracle_make_data": ([dp, dp, dp, dp, i64, ctypes.c_double, dp], ctypes.c_int),
+            "oracle_besselj": ([ctypes.c_int, ctypes.c_double], ctypes.c_double),
+            "oracle_pm_coeffs": ([ctypes.c_int, ctypes.c_double, dp], ctypes.c_int),
+            "oracle_antenna": ([ctypes.c_double, ctypes.c_double, ctypes.c_double, dp], ctypes.c_int),
+            "oracle_hermite": ([ctypes.c_double] * 6, ctypes.c_double),
+            "oracle_dl_of_z": ([ctypes.c_double], ctypes.c_double),
+            "oracle_z_of_dl": ([ctypes.c_double], ctypes.c_double),
+            "oracle_num_threads": ([], ctypes.c_int),
+        }
+        for name, (argt, rest) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = argt
+            f.restype = rest
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise ValueError(f"oracle {what} failed with status {rc}")
+
+
+# --------------------------------------------------------------------------
+# step wrappers
+# --------------------------------------------------------------------------
+def scalars(params) -> np.ndarray:
+    """[B][8] = valid, z, Xi, chi[s], DeltaT[s], g=1/(Xi D), D[s], 0."""
+    p = _f64(params).reshape(-1, NPAR)
+    out = np.zeros((p.shape[0], 8))
+    _check(lib().oracle_scalars(_p(p), p.shape[0], _p(out)), "scalars")
+    return out
+
+
+def rhs(y5, prow, lo_only: bool = False) -> np.ndarray:
+    y = _f64(y5)
+    pr = _f64(prow)
+    dy = np.zeros(5)
+    lib().oracle_rhs(_p(y), _p(pr), 1 if lo_only else 0, _p(dy))
+    return dy
+
+
+def orbit(params, cfg: OracleConfig):
+    p = _f64(params).reshape(-1, NPAR)
+    B = p.shape[0]
+    orb = np.zeros((B, cfg.n_intervals + 1, 10))
+    kw = np.zeros(B, dtype=np.int32)
+    c = cfg.c()
+    _check(lib().oracle_orbit(_p(p), B, ctypes.byref(c), _p(orb),
+                              kw.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), "orbit")
+    return orb, kw
+
+
+def waveform(params, cfg: OracleConfig) -> np.ndarray:
+    p = _f64(params).reshape(-1, NPAR)
+    B = p.shape[0]
+    x = np.zeros((B, 2, cfg.N))
+    c = cfg.c()
+    _check(lib().oracle_waveform(_p(p), B, ctypes.byref(c), _p(x)), "waveform")
+    return x
+
+
+def waveform_diag(prow, cfg: OracleConfig):
+    """One walker: channels [2][N] and per-sample diagnostics [N][8] =
+    (h+, hx, A, c_iota, Phi', gamma, cos theta_d, 0)."""
+    p = _f64(prow).reshape(NPAR)
+    x = np.zeros((2, cfg.N))
+    d = np.zeros((cfg.N, 8))
+    c = cfg.c()
+    _check(lib().oracle_waveform_diag(_p(p), ctypes.byref(c), _p(x), _p(d)), "waveform_diag")
+    return x, d
+
+
+def rfft(x, dt: float) -> np.ndarray:
+    """dt * DFT of each real row (last axis), bins 0..N/2, complex128."""
+    a = _f64(x)
+    N = a.shape[-1]
+    rows = a.reshape(-1, N)
+    out = np.zeros((rows.shape[0], N // 2 + 1, 2))
+    _check(lib().oracle_rfft(_p(rows), rows.shape[0], N, dt, _p(out)), "rfft")
+    return (out[..., 0] + 1j * out[..., 1]).reshape(a.shape[:-1] + (N // 2 + 1,))
+
+
+def spectrum(params, cfg: OracleConfig) -> np.ndarray:
+    """[B][2][N/2+1] complex: unit-distance GR spectrum of each walker."""
+    return rfft(waveform(params, cfg), cfg.dt)
+
+
+def _cplx_pairs(z) -> np.ndarray:
+    z = np.asarray(z)
+    out = np.empty(z.shape + (2,))
+    out[..., 0] = z.real
+    out[..., 1] = z.imag
+    return np.ascontiguousarray(out)
+
+
+def loglike(params, data, psd, cfg: OracleConfig) -> np.ndarray:
+    p = _f64(params).reshape(-1, NPAR)
+    d = _cplx_pairs(data)
+    s = _f64(psd)
+    H = cfg.N // 2 + 1
+    assert d.shape == (2, H, 2) and s.shape == (H,)
+    out = np.zeros(p.shape[0])
+    c = cfg.c()
+    _check(lib().oracle_loglike(_p(p), p.shape[0], _p(d), _p(s), ctypes.byref(c), _p(out)),
+           "loglike")
+    return out
+
+
+def psd_bc04(f) -> np.ndarray:
+    f = _f64(f)
+    S = np.zeros_like(f)
+    lib().oracle_psd_bc04(_p(f), f.size, _p(S))
+    return S
+
+
+def frequency_grid(N: int, dt: float) -> np.ndarray:
+    return np.arange(N // 2 + 1) / (N * dt)
+
+
+def make_data(hinj, pinj, psd, gauss, N: int, dt: float) -> np.ndarray:
+    """data[2][N/2+1] complex = propagated injection + coloured noise."""
+    h = _cplx_pairs(hinj)
+    pi = _f64(pinj).reshape(NPAR)
+    s = _f64(psd)
+    out = np.zeros((2, N // 2 + 1, 2))
+    gp = None
+    if gauss is not None:
+        g = _f64(gauss)
+        assert g.shape == (2, N // 2 + 1, 2)
+        gp = _p(g)
+    _check(lib().oracle_make_data(_p(h), _p(pi), _p(s), gp, N, dt, _p(out)), "make_data")
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def besselj(n: int, x: float) -> float:
+    return lib().oracle_besselj(int(n), float(x))
+
+
+def pm_coeffs(n: int, e: float):
+    out = np.zeros(3)
+    _check(lib().oracle_pm_coeffs(int(n), float(e), _p(out)), "pm_coeffs")
+    return out
+
+
+def antenna(cth: float, phi: float, psi: float):
+    out = np.zeros(2)
+    lib().oracle_antenna(float(cth), float(phi), float(psi), _p(out))
+    return out
+
+
+def hermite(y0, d0, y1, d1, h, u) -> float:
+    return lib().oracle_hermite(y0, d0, y1, d1, h, u)
+
+
+def dl_of_z(z: float) -> float:
+    """luminosity distance in light-seconds"""
+    return lib().oracle_dl_of_z(float(z))
+
+
+def z_of_dl(D_seconds: float) -> float:
+    return lib().oracle_z_of_dl(float(D_seconds))
+
+
+def num_threads() -> int:
+    return lib().oracle_num_threads()

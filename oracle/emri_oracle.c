@@ -1,0 +1,760 @@
+/*
+ * emri_oracle.c -- plain FP64 CPU oracle for the batched EMRI log-likelihood
+ * of Saltas & Oliveri, "emri_mc: A GPU-based Python code for Bayesian
+ * inference of EMRI waveforms" (arXiv:2311.17174).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the HIP product
+ * path.  Only the test suite, the smoke check and the CPU-baseline leg of
+ * the benchmark load it.  It shares no code, header, table or constant with
+ * the HIP library; its constants are written out here on purpose.
+ *
+ * Everything is FP64, written for a reader to check against the paper and
+ * against the Analytic Kludge (AK) formulas of Barack & Cutler 2004
+ * (Phys. Rev. D 69, 082005; "BC04" below), which the paper cites for the
+ * orbital equations, the harmonic amplitudes and the LISA response without
+ * printing them (Sec. 2 "Waveform generation").
+ *
+ * Steps, in the paper's order (Sec. 3 "Overview"):
+ *   1. per-walker scalars: validity, z(d_L), Xi(z) [Eq. (6)], propagation
+ *      delay Delta T [Eqs. (4)-(5)], overall factor 1/(Xi d_L)
+ *   2. orbit: Eq. (1) with Y = {Phi, nu, gamma~, e, alpha}, classical RK4
+ *      with a fixed coarse step, stopped at the last stable orbit
+ *      (nu_LSO of Sec. 3 "Waveform computation")
+ *   3. time-domain waveform: Eq. (2), Peters-Mathews harmonics n=1..n_max,
+ *      projected on the two low-frequency LISA channels with Doppler phase
+ *      modulation; the orbit is read between coarse nodes by cubic Hermite
+ *      interpolation; Bessel functions evaluated per sample
+ *   4. FFT: h~(f_k) = dt * sum_j x_j exp(-2 pi i j k / N)  (Sec. 3)
+ *   5. likelihood, Eq. (8) read as -1/2 <d - m | d - m> with the noise
+ *      weighted inner product, m = (1/Xi d_L) exp(-2 pi i f Delta T) h~
+ *      (Eq. (4); the distance factor enters only here, Sec. 3 file list)
+ *
+ * Readings where the paper is silent or garbled are listed in the design
+ * notes of the repository; each is marked "reading" at the place it is used.
+ *
+ * Parity pins: see tests/test_oracle_*.py.  The 1PN and spin coefficients of
+ * the BC04 orbital equations and the absolute sign / orientation conventions
+ * of the response are parity unpinned (no printed values exist to check).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---- parameter row layout (17 doubles per walker) ---------------------- */
+enum {
+    I_M = 0,      /* central mass M [Msun]                                   */
+    I_MU = 1,     /* compact-object mass mu [Msun]                           */
+    I_A = 2,      /* spin S/M^2                                              */
+    I_E0 = 3,     /* eccentricity at t = 0                                   */
+    I_NU0 = 4,    /* orbital frequency nu at t = 0 [Hz]                      */
+    I_PHI0 = 5,   /* mean anomaly Phi at t = 0 [rad]                         */
+    I_GT0 = 6,    /* gamma~ at t = 0 [rad]                                   */
+    I_AL0 = 7,    /* alpha at t = 0 [rad]                                    */
+    I_CLAM = 8,   /* cos(lambda), L-S inclination                            */
+    I_THS = 9,    /* source polar angle theta_S (ecliptic) [rad]             */
+    I_PHS = 10,   /* source azimuth phi_S [rad]                              */
+    I_THK = 11,   /* spin polar angle theta_K [rad]                          */
+    I_PHK = 12,   /* spin azimuth phi_K [rad]                                */
+    I_DL = 13,    /* luminosity distance d_L [Gpc]                           */
+    I_XI0 = 14,   /* Xi_0 of Eq. (6)                                         */
+    I_NXI = 15,   /* n of Eq. (6)                                            */
+    I_AT = 16,    /* alpha_T of Eq. (3): c_T^2 = 1 + alpha_T, constant       */
+    NPAR = 17
+};
+
+/* ---- physical constants (SI-derived; masses and distances in seconds) -- */
+#define O_PI 3.14159265358979323846
+static const double O_TSUN = 4.925490947641267e-6;   /* G Msun / c^3 [s]   */
+static const double O_CLIGHT = 299792458.0;           /* [m/s]              */
+static const double O_PARSEC = 3.0856775814913673e16; /* [m]                */
+static const double O_AU = 1.495978707e11;            /* [m]                */
+static const double O_YEAR = 31557600.0;              /* Julian year [s]    */
+static const double O_H0 = 67.66;                     /* [km/s/Mpc]         */
+static const double O_OMEGA_M = 0.3111;               /* flat LCDM          */
+
+typedef struct {
+    double T_obs;        /* observation time [s]                            */
+    double dt;           /* sampling interval [s]                           */
+    int64_t N;           /* transform length, power of two >= N_valid        */
+    int32_t n_harm;      /* n_max of Eq. (2)                                 */
+    int32_t coarse_log2; /* coarse ODE step = dt * 2^coarse_log2            */
+    int32_t lo_only;     /* test hook: leading-order (Peters-Mathews) ODE    */
+    int32_t pad;
+} oracle_cfg;
+
+static int64_t n_valid_of(const oracle_cfg *c) { return (int64_t)llround(c->T_obs / c->dt); }
+static int64_t n_intervals_of(const oracle_cfg *c)
+{
+    int64_t m = (int64_t)1 << c->coarse_log2;
+    return (n_valid_of(c) + m - 1) / m;
+}
+
+/* ======================================================================== */
+/* Cosmology: d_L(z) for flat LCDM (reading; the paper does not give it).   */
+/* ======================================================================== */
+static double inv_E(double z)
+{
+    double a = 1.0 + z;
+    return 1.0 / sqrt(O_OMEGA_M * a * a * a + 1.0 - O_OMEGA_M);
+}
+
+/* integral_0^z dz'/E(z'): Romberg integration (trapezoid rule with
+ * Richardson extrapolation), run until two diagonal estimates agree to
+ * 1e-15 relative; the integrand is analytic on [0, z]. */
+static double comoving_integral(double z)
+{
+    if (z <= 0.0) return 0.0;
+    double R[2][24];
+    double *prev = R[0], *cur = R[1];
+    double h = z;
+    prev[0] = 0.5 * h * (inv_E(0.0) + inv_E(z));
+    for (int k = 1; k < 24; ++k) {
+        h *= 0.5;
+        double s = 0.0;
+        int64_t n = (int64_t)1 << (k - 1);
+        for (int64_t i = 0; i < n; ++i) s += inv_E((2 * i + 1) * h);
+        cur[0] = 0.5 * prev[0] + h * s;
+        double f = 1.0;
+        for (int j = 1; j <= k; ++j) {
+            f *= 4.0;
+            cur[j] = cur[j - 1] + (cur[j - 1] - prev[j - 1]) / (f - 1.0);
+        }
+        if (k >= 4 && fabs(cur[k] - prev[k - 1]) <= 1e-15 * fabs(cur[k])) return cur[k];
+        double *t = prev; prev = cur; cur = t;
+    }
+    return prev[23];
+}
+
+/* Hubble distance c/H0 in seconds of light travel */
+static double hubble_distance_s(void)
+{
+    return (O_CLIGHT / 1000.0 / O_H0) * 1e6 * O_PARSEC / O_CLIGHT;
+}
+
+/* d_L(z) in seconds */
+double oracle_dl_of_z(double z)
+{
+    return (1.0 + z) * hubble_distance_s() * comoving_integral(z);
+}
+
+/* invert d_L(z) = D (seconds) by Newton's method; d_L is convex increasing,
+ * so starting to the right of the root converges monotonically. */
+double oracle_z_of_dl(double D)
+{
+    double DH = hubble_distance_s();
+    if (!(D > 0.0)) return 0.0;
+    double z = D / DH; /* d_L(D/DH) >= D: right of the root */
+    for (int it = 0; it < 200; ++it) {
+        double I = comoving_integral(z);
+        double f = (1.0 + z) * DH * I - D;
+        double fp = DH * I + (1.0 + z) * DH * inv_E(z);
+        double dz = f / fp;
+        z -= dz;
+        if (fabs(dz) <= 1e-16 * (1.0 + z)) break;
+    }
+    return z;
+}
+
+/* ======================================================================== */
+/* Step 1: per-walker scalars.                                              */
+/* out[8] = {valid, z, Xi, chi [s], DeltaT [s], g = 1/(Xi D), D [s], 0}     */
+/* ======================================================================== */
+static double nu_lso(double M_s, double e)
+{
+    /* Sec. 3 "Waveform computation": nu_LSO = c^3/(2 pi G M) ((1-e^2)/(6+2e))^{3/2} */
+    return pow((1.0 - e * e) / (6.0 + 2.0 * e), 1.5) / (2.0 * O_PI * M_s);
+}
+
+static void walker_scalars(const double *p, double out[8])
+{
+    memset(out, 0, 8 * sizeof(double));
+    for (int i = 0; i < NPAR; ++i)
+        if (!isfinite(p[i])) return;
+    double M = p[I_M], mu = p[I_MU], a = p[I_A], e0 = p[I_E0], nu0 = p[I_NU0];
+    double dl = p[I_DL], at = p[I_AT], cl = p[I_CLAM];
+    int ok = (mu > 0.0) && (mu < M) && (a >= 0.0) && (a <= 1.0) && (e0 >= 0.0) &&
+             (e0 < 1.0) && (nu0 > 0.0) && (dl > 0.0) && (at > -1.0) && (cl >= -1.0) &&
+             (cl <= 1.0);
+    if (!ok) return;
+    double M_s = M * O_TSUN;
+    if (!(nu0 < nu_lso(M_s, e0))) return;
+    double D = dl * 1e9 * O_PARSEC / O_CLIGHT;
+    double z = oracle_z_of_dl(D);
+    /* Eq. (6) */
+    double Xi = p[I_XI0] + (1.0 - p[I_XI0]) / pow(1.0 + z, p[I_NXI]);
+    if (!(Xi > 0.0) || !isfinite(Xi)) return;
+    double chi = D / (1.0 + z);
+    /* reading of Eqs. (3)-(5) for constant alpha_T: the wave crosses the
+     * comoving distance chi at speed c_T = sqrt(1 + alpha_T), so it arrives
+     * later by (1/c_T - 1) chi/c.  1/c_T - 1 is written without cancellation
+     * as -alpha_T / (c_T (1 + c_T)). */
+    double ct = sqrt(1.0 + at);
+    double dT = -at / (ct * (1.0 + ct)) * chi;
+    out[0] = 1.0;
+    out[1] = z;
+    out[2] = Xi;
+    out[3] = chi;
+    out[4] = dT;
+    out[5] = 1.0 / (Xi * D);
+    out[6] = D;
+}
+
+int oracle_scalars(const double *params, int64_t B, double *out)
+{
+    for (int64_t w = 0; w < B; ++w) walker_scalars(params + w * NPAR, out + w * 8);
+    return 0;
+}
+
+/* ======================================================================== */
+/* Step 2: orbital ODE, Eq. (1), right-hand side of BC04 (reading R1).      */
+/* y = {Phi, nu, gamma~, e, alpha}                                          */
+/* ======================================================================== */
+static void ak_rhs(const double y[5], double M_s, double mu_s, double a, double cl,
+                   int lo_only, double dy[5])
+{
+    double nu = y[1], e = y[3];
+    double x = 2.0 * O_PI * M_s * nu;          /* PN parameter, Sec. 2 */
+    double e2 = e * e, e4 = e2 * e2, e6 = e4 * e2;
+    double eps = 1.0 - e2;
+    double x23 = pow(x, 2.0 / 3.0);
+
+    dy[0] = 2.0 * O_PI * nu;
+
+    /* d nu / dt */
+    double brace = (1.0 + 73.0 / 24.0 * e2 + 37.0 / 96.0 * e4) * eps;
+    if (!lo_only) {
+        brace += x23 * (1273.0 / 336.0 - 2561.0 / 224.0 * e2 - 3885.0 / 128.0 * e4 -
+                        13147.0 / 5376.0 * e6);
+        brace -= x * a * cl * pow(eps, -0.5) *
+                 (73.0 / 12.0 + 1211.0 / 24.0 * e2 + 3143.0 / 96.0 * e4 + 65.0 / 64.0 * e6);
+    }
+    dy[1] = 96.0 / (10.0 * O_PI) * (mu_s / (M_s * M_s * M_s)) * pow(x, 11.0 / 3.0) *
+            pow(eps, -4.5) * brace;
+
+    /* d gamma~ / dt */
+    dy[2] = 6.0 * O_PI * nu * x23 / eps * (1.0 + 0.25 * x23 / eps * (26.0 - 15.0 * e2)) -
+            12.0 * O_PI * nu * a * cl * x * pow(eps, -1.5);
+
+    /* d e / dt */
+    double inner = (304.0 + 121.0 * e2) * eps;
+    if (!lo_only) {
+        inner = (304.0 + 121.0 * e2) * eps * (1.0 + 12.0 * x23) -
+                x23 / 56.0 * (8.0 * 16705.0 + 12.0 * 9082.0 * e2 - 25211.0 * e4);
+    }
+    double de = -(e / 15.0) * (mu_s / (M_s * M_s)) * pow(eps, -3.5) * pow(x, 8.0 / 3.0) * inner;
+    if (!lo_only) {
+        de += e * (mu_s / (M_s * M_s)) * a * cl * pow(x, 11.0 / 3.0) * pow(eps, -4.0) *
+              (1364.0 / 5.0 + 5032.0 / 15.0 * e2 + 263.0 / 10.0 * e4);
+    }
+    dy[3] = de;
+
+    /* d alpha / dt */
+    dy[4] = 4.0 * O_PI * nu * a * x * pow(eps, -1.5);
+}
+
+/* exported for tests: right-hand side at a state, for one parameter row */
+int oracle_rhs(const double *y5, const double *prow, int lo_only, double *dy5)
+{
+    ak_rhs(y5, prow[I_M] * O_TSUN, prow[I_MU] * O_TSUN, prow[I_A], prow[I_CLAM], lo_only, dy5);
+    return 0;
+}
+
+/* node k is before the last stable orbit: nu < nu_LSO(e), i.e.
+ * x^{2/3} (6 + 2e) < 1 - e^2 (Sec. 3), with a finite state and 0 <= e < 1 */
+static int node_ok(const double y[5], double M_s)
+{
+    double nu = y[1], e = y[3];
+    if (!isfinite(y[0]) || !isfinite(nu) || !isfinite(y[2]) || !isfinite(e) || !isfinite(y[4]))
+        return 0;
+    if (!(e >= 0.0 && e < 1.0 && nu > 0.0)) return 0;
+    double x = 2.0 * O_PI * M_s * nu;
+    return pow(x, 2.0 / 3.0) * (6.0 + 2.0 * e) < 1.0 - e * e;
+}
+
+/* Classical RK4 on t_k = k h, h = dt 2^coarse_log2 (reading R3).
+ * orb[(K+1)][10]: Y_k then f(Y_k).  Returns K_w, the index of the last node
+ * before the LSO (reading R5); nodes after it are zero. */
+static int64_t walker_orbit(const double *p, const oracle_cfg *c, double *orb)
+{
+    int64_t K = n_intervals_of(c);
+    double h = c->dt * (double)((int64_t)1 << c->coarse_log2);
+    double M_s = p[I_M] * O_TSUN, mu_s = p[I_MU] * O_TSUN, a = p[I_A], cl = p[I_CLAM];
+    memset(orb, 0, (size_t)(K + 1) * 10 * sizeof(double));
+    double y[5] = {p[I_PHI0], p[I_NU0], p[I_GT0], p[I_E0], p[I_AL0]};
+    double k1[5], k2[5], k3[5], k4[5], yt[5];
+    ak_rhs(y, M_s, mu_s, a, cl, c->lo_only, k1);
+    for (int i = 0; i < 5; ++i) { orb[i] = y[i]; orb[5 + i] = k1[i]; }
+    int64_t Kw = K;
+    for (int64_t k = 0; k < K; ++k) {
+        for (int i = 0; i < 5; ++i) yt[i] = y[i] + 0.5 * h * k1[i];
+        ak_rhs(yt, M_s, mu_s, a, cl, c->lo_only, k2);
+        for (int i = 0; i < 5; ++i) yt[i] = y[i] + 0.5 * h * k2[i];
+        ak_rhs(yt, M_s, mu_s, a, cl, c->lo_only, k3);
+        for (int i = 0; i < 5; ++i) yt[i] = y[i] + h * k3[i];
+        ak_rhs(yt, M_s, mu_s, a, cl, c->lo_only, k4);
+        for (int i = 0; i < 5; ++i) y[i] = y[i] + h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+        if (!node_ok(y, M_s)) { Kw = k; break; }   /* node k+1 is past the LSO */
+        ak_rhs(y, M_s, mu_s, a, cl, c->lo_only, k1);
+        double *o = orb + (k + 1) * 10;
+        for (int i = 0; i < 5; ++i) { o[i] = y[i]; o[5 + i] = k1[i]; }
+    }
+    return Kw;
+}
+
+int oracle_orbit(const double *params, int64_t B, const oracle_cfg *c, double *orb, int32_t *Kw)
+{
+    int64_t K = n_intervals_of(c);
+    for (int64_t w = 0; w < B; ++w) {
+        double s[8];
+        walker_scalars(params + w * NPAR, s);
+        double *o = orb + w * (K + 1) * 10;
+        if (s[0] == 0.0) {
+            memset(o, 0, (size_t)(K + 1) * 10 * sizeof(double));
+            Kw[w] = -1;
+            continue;
+        }
+        Kw[w] = (int32_t)walker_orbit(params + w * NPAR, c, o);
+    }
+    return 0;
+}
+
+/* cubic Hermite on [t_k, t_k + h] from values and derivatives, u in [0,1] */
+static double hermite(double y0, double d0, double y1, double d1, double h, double u)
+{
+    double u2 = u * u, u3 = u2 * u;
+    return (2.0 * u3 - 3.0 * u2 + 1.0) * y0 + (u3 - 2.0 * u2 + u) * h * d0 +
+           (-2.0 * u3 + 3.0 * u2) * y1 + (u3 - u2) * h * d1;
+}
+
+double oracle_hermite(double y0, double d0, double y1, double d1, double h, double u)
+{
+    return hermite(y0, d0, y1, d1, h, u);
+}
+
+/* ======================================================================== */
+/* Bessel functions J_k(x), k = 0..kmax, by Miller's backward recurrence    */
+/* J_{k-1} = (2k/x) J_k - J_{k+1}, normalised with J_0 + 2 sum J_{2k} = 1   */
+/* (Abramowitz & Stegun 9.1.27 and 9.1.46).                                  */
+/* ======================================================================== */
+static void bessel_j_upto(double x, int kmax, double *J /* [kmax+1] */)
+{
+    for (int k = 0; k <= kmax; ++k) J[k] = 0.0;
+    if (x == 0.0) { J[0] = 1.0; return; }
+    double ax = fabs(x);
+    int top = (kmax > (int)ax ? kmax : (int)ax);
+    int start = top + 24 + (int)sqrt(160.0 * (top + 1));
+    if (start & 1) start += 1;
+    double jp1 = 0.0, jk = 1e-300, norm = 0.0;
+    for (int k = start; k >= 1; --k) {
+        double jm1 = (2.0 * k / ax) * jk - jp1;   /* J_{k-1} */
+        jp1 = jk;
+        jk = jm1;
+        if ((k - 1) <= kmax) J[k - 1] = jk;
+        if (((k - 1) & 1) == 0 && (k - 1) > 0) norm += 2.0 * jk;
+        if (fabs(jk) > 1e250) {                   /* rescale everything kept */
+            jk *= 1e-250; jp1 *= 1e-250; norm *= 1e-250;
+            for (int i = 0; i <= kmax; ++i) J[i] *= 1e-250;
+        }
+    }
+    norm += jk; /* + J_0 */
+    for (int k = 0; k <= kmax; ++k) J[k] /= norm;
+    if (x < 0.0)
+        for (int k = 1; k <= kmax; k += 2) J[k] = -J[k];
+}
+
+/* J_n(x) for any integer n (J_{-n} = (-1)^n J_n) */
+double oracle_besselj(int n, double x)
+{
+    int an = n < 0 ? -n : n;
+    double *J = (double *)malloc((size_t)(an + 1) * sizeof(double));
+    bessel_j_upto(x, an, J);
+    double v = J[an];
+    free(J);
+    if (n < 0 && (an & 1)) v = -v;
+    return v;
+}
+
+static double jn_signed(const double *J, int k)
+{
+    if (k >= 0) return J[k];
+    return (k & 1) ? -J[-k] : J[-k];
+}
+
+/* Peters-Mathews harmonic coefficients as used by BC04 (Eq. (2) of the
+ * paper with amplitudes of Peters & Mathews): for X = n e,
+ *   P_n = J_{n-2} - 2e J_{n-1} + (2/n) J_n + 2e J_{n+1} - J_{n+2}
+ *   Q_n = sqrt(1-e^2) (J_{n-2} - 2 J_n + J_{n+2})
+ *   R_n = J_n
+ * J holds J_0..J_{n+2}(X). */
+static void pm_coeffs_from(int n, double e, const double *J, double *P, double *Q, double *R)
+{
+    double jm2 = jn_signed(J, n - 2), jm1 = jn_signed(J, n - 1), j0 = J[n], jp1 = J[n + 1],
+           jp2 = J[n + 2];
+    *P = jm2 - 2.0 * e * jm1 + (2.0 / n) * j0 + 2.0 * e * jp1 - jp2;
+    *Q = sqrt(1.0 - e * e) * (jm2 - 2.0 * j0 + jp2);
+    *R = j0;
+}
+
+int oracle_pm_coeffs(int n, double e, double *out3)
+{
+    double J[128];
+    if (n < 1 || n + 2 >= 128) return -1;
+    bessel_j_upto(n * e, n + 2, J);
+    pm_coeffs_from(n, e, J, &out3[0], &out3[1], &out3[2]);
+    return 0;
+}
+
+/* LISA low-frequency antenna patterns (BC04, after Cutler 1998) */
+static void antenna(double cth, double phi, double psi, double *Fp, double *Fx)
+{
+    double a = 0.5 * (1.0 + cth * cth);
+    *Fp = a * cos(2.0 * phi) * cos(2.0 * psi) - cth * sin(2.0 * phi) * sin(2.0 * psi);
+    *Fx = a * cos(2.0 * phi) * sin(2.0 * psi) + cth * sin(2.0 * phi) * cos(2.0 * psi);
+}
+
+int oracle_antenna(double cth, double phi, double psi, double *out2)
+{
+    antenna(cth, phi, psi, &out2[0], &out2[1]);
+    return 0;
+}
+
+/* ======================================================================== */
+/* Step 3: time-domain waveform of one walker at unit distance, GR.         */
+/* Writes channels I and II, x[2][N]; optional diagnostics per sample       */
+/* diag[N][8] = {h+, hx, A, c_iota, Phi', gamma, cos theta_d, 0}.           */
+/* ======================================================================== */
+static void walker_waveform(const double *p, const oracle_cfg *c, const double *orb, int64_t Kw,
+                            double *x /* [2][N] */, double *diag /* [N][8] or NULL */)
+{
+    int64_t N = c->N, Nv = n_valid_of(c);
+    int64_t m = (int64_t)1 << c->coarse_log2;
+    double h = c->dt * (double)m;
+    int nh = c->n_harm;
+    memset(x, 0, (size_t)(2 * N) * sizeof(double));
+    if (diag) memset(diag, 0, (size_t)(8 * N) * sizeof(double));
+    if (Kw <= 0) return;
+
+    double M_s = p[I_M] * O_TSUN, mu_s = p[I_MU] * O_TSUN;
+    double cl = p[I_CLAM], sl = sqrt(1.0 - cl * cl);
+    double thS = p[I_THS], phS = p[I_PHS], thK = p[I_THK], phK = p[I_PHK];
+    /* source direction N, spin direction S and the basis e1, e2 orthogonal to S */
+    double Nv3[3] = {sin(thS) * cos(phS), sin(thS) * sin(phS), cos(thS)};
+    double Sv[3] = {sin(thK) * cos(phK), sin(thK) * sin(phK), cos(thK)};
+    double e1[3] = {-cos(thK) * cos(phK), -cos(thK) * sin(phK), sin(thK)};
+    double e2[3] = {sin(phK), -cos(phK), 0.0};
+    double NS = Nv3[0] * Sv[0] + Nv3[1] * Sv[1] + Nv3[2] * Sv[2];
+    double R = O_AU / O_CLIGHT; /* 1 AU in light seconds */
+    double s3 = sqrt(3.0);
+
+    double *J = (double *)malloc((size_t)(nh + 3) * sizeof(double));
+    int64_t jend = Kw * m;
+    if (jend > Nv) jend = Nv;
+    for (int64_t j = 0; j < jend; ++j) {
+        int64_t k = j / m;
+        double u = (double)(j - k * m) / (double)m;
+        const double *o0 = orb + k * 10, *o1 = orb + (k + 1) * 10;
+        double Y[5];
+        for (int i = 0; i < 5; ++i) Y[i] = hermite(o0[i], o0[5 + i], o1[i], o1[5 + i], h, u);
+        double Phi = Y[0], nu = Y[1], gt = Y[2], e = Y[3], al = Y[4];
+        double t = (double)j * c->dt;
+
+        /* orbital angular momentum direction, precessing about S */
+        double L[3];
+        for (int i = 0; i < 3; ++i) L[i] = cl * Sv[i] + sl * (cos(al) * e1[i] + sin(al) * e2[i]);
+        double ci = L[0] * Nv3[0] + L[1] * Nv3[1] + L[2] * Nv3[2];
+        /* beta: angle from L x N to L x S in the orbital plane */
+        double SxL[3] = {Sv[1] * L[2] - Sv[2] * L[1], Sv[2] * L[0] - Sv[0] * L[2],
+                         Sv[0] * L[1] - Sv[1] * L[0]};
+        double sb = Nv3[0] * SxL[0] + Nv3[1] * SxL[1] + Nv3[2] * SxL[2];
+        double cb = NS - ci * cl;
+        double beta = atan2(sb, cb);
+        double gam = gt + beta;
+
+        /* detector position and Doppler phase (BC04) */
+        double phib = 2.0 * O_PI * t / O_YEAR;
+        double Phid = Phi + 2.0 * O_PI * nu * R * sin(thS) * cos(phib - phS);
+        /* detector-plane normal, tilted by 60 degrees */
+        double zd[3] = {-0.5 * s3 * cos(phib), -0.5 * s3 * sin(phib), 0.5};
+        double cthd = Nv3[0] * zd[0] + Nv3[1] * zd[1] + Nv3[2] * zd[2];
+        double phid = phib + atan2(s3 * cos(thS) + sin(thS) * cos(phib - phS),
+                                   2.0 * sin(thS) * sin(phib - phS));
+        double Lz = L[0] * zd[0] + L[1] * zd[1] + L[2] * zd[2];
+        double Lxz[3] = {L[1] * zd[2] - L[2] * zd[1], L[2] * zd[0] - L[0] * zd[2],
+                         L[0] * zd[1] - L[1] * zd[0]};
+        double NLz = Nv3[0] * Lxz[0] + Nv3[1] * Lxz[1] + Nv3[2] * Lxz[2];
+        double psi = atan2(Lz - ci * cthd, NLz);
+        double FpI, FxI, FpII, FxII;
+        antenna(cthd, phid, psi, &FpI, &FxI);
+        antenna(cthd, phid - 0.25 * O_PI, psi, &FpII, &FxII);
+
+        /* harmonic sum (Peters-Mathews; unit distance, no 1/d_L) */
+        double A = pow(2.0 * O_PI * M_s * nu, 2.0 / 3.0) * mu_s;
+        double c2g = cos(2.0 * gam), s2g = sin(2.0 * gam);
+        double hp = 0.0, hx = 0.0;
+        for (int n = 1; n <= nh; ++n) {
+            double P, Q, Rn;
+            bessel_j_upto(n * e, n + 2, J);
+            pm_coeffs_from(n, e, J, &P, &Q, &Rn);
+            double an = -n * A * P * cos(n * Phid);
+            double bn = -n * A * Q * sin(n * Phid);
+            double cn = 2.0 * A * Rn * cos(n * Phid);
+            hp += -(1.0 + ci * ci) * (an * c2g - bn * s2g) + (1.0 - ci * ci) * cn;
+            hx += 2.0 * ci * (bn * c2g + an * s2g);
+        }
+        x[j] = 0.5 * s3 * (FpI * hp + FxI * hx);
+        x[N + j] = 0.5 * s3 * (FpII * hp + FxII * hx);
+        if (diag) {
+            double *d = diag + 8 * j;
+            d[0] = hp; d[1] = hx; d[2] = A; d[3] = ci; d[4] = Phid; d[5] = gam; d[6] = cthd;
+        }
+    }
+    free(J);
+}
+
+static int cfg_ok(const oracle_cfg *c)
+{
+    if (!(c->dt > 0.0) || !(c->T_obs > 0.0) || c->N < 2 || (c->N & (c->N - 1))) return 0;
+    if (n_valid_of(c) > c->N || n_valid_of(c) < 1) return 0;
+    if (c->n_harm < 1 || c->n_harm > 100 || c->coarse_log2 < 0 || c->coarse_log2 > 30) return 0;
+    return 1;
+}
+
+int oracle_waveform(const double *params, int64_t B, const oracle_cfg *c, double *x /* [B][2][N] */)
+{
+    if (!cfg_ok(c)) return -1;
+    int64_t K = n_intervals_of(c);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t w = 0; w < B; ++w) {
+        double s[8];
+        const double *p = params + w * NPAR;
+        walker_scalars(p, s);
+        double *xw = x + w * 2 * c->N;
+        if (s[0] == 0.0) { memset(xw, 0, (size_t)(2 * c->N) * sizeof(double)); continue; }
+        double *orb = (double *)malloc((size_t)(K + 1) * 10 * sizeof(double));
+        int64_t Kw = walker_orbit(p, c, orb);
+        walker_waveform(p, c, orb, Kw, xw, NULL);
+        free(orb);
+    }
+    return 0;
+}
+
+/* single walker waveform with per-sample diagnostics, for pin tests */
+int oracle_waveform_diag(const double *p, const oracle_cfg *c, double *x, double *diag)
+{
+    if (!cfg_ok(c)) return -1;
+    double s[8];
+    walker_scalars(p, s);
+    if (s[0] == 0.0) return -2;
+    int64_t K = n_intervals_of(c);
+    double *orb = (double *)malloc((size_t)(K + 1) * 10 * sizeof(double));
+    int64_t Kw = walker_orbit(p, c, orb);
+    walker_waveform(p, c, orb, Kw, x, diag);
+    free(orb);
+    return 0;
+}
+
+/* ======================================================================== */
+/* Step 4: discrete Fourier transform, iterative radix-2 Cooley-Tukey.       */
+/* ======================================================================== */
+static void fft_inplace(double *re, double *im, int64_t n)
+{
+    /* bit reversal */
+    for (int64_t i = 1, j = 0; i < n; ++i) {
+        int64_t bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) {
+            double t = re[i]; re[i] = re[j]; re[j] = t;
+            t = im[i]; im[i] = im[j]; im[j] = t;
+        }
+    }
+    /* twiddles exp(-2 pi i k / n), k < n/2, from the library cos / sin */
+    double *wr = (double *)malloc((size_t)(n / 2 + 1) * sizeof(double));
+    double *wi = (double *)malloc((size_t)(n / 2 + 1) * sizeof(double));
+    for (int64_t k = 0; k < n / 2; ++k) {
+        double ang = 2.0 * O_PI * (double)k / (double)n;
+        wr[k] = cos(ang);
+        wi[k] = -sin(ang);
+    }
+    for (int64_t len = 2; len <= n; len <<= 1) {
+        int64_t half = len >> 1, step = n / len;
+        for (int64_t s = 0; s < n; s += len) {
+            for (int64_t q = 0; q < half; ++q) {
+                double c = wr[q * step], d = wi[q * step];
+                int64_t a = s + q, b = s + q + half;
+                double tr = re[b] * c - im[b] * d;
+                double ti = re[b] * d + im[b] * c;
+                re[b] = re[a] - tr; im[b] = im[a] - ti;
+                re[a] += tr; im[a] += ti;
+            }
+        }
+    }
+    free(wr);
+    free(wi);
+}
+
+/* X[m][N/2+1][2] = dt * DFT of each real row x[m][N], bins 0..N/2 */
+int oracle_rfft(const double *x, int64_t M, int64_t N, double dt, double *X)
+{
+    if (N < 2 || (N & (N - 1))) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < M; ++r) {
+        double *re = (double *)malloc((size_t)N * sizeof(double));
+        double *im = (double *)calloc((size_t)N, sizeof(double));
+        memcpy(re, x + r * N, (size_t)N * sizeof(double));
+        fft_inplace(re, im, N);
+        double *o = X + r * (N / 2 + 1) * 2;
+        for (int64_t k = 0; k <= N / 2; ++k) { o[2 * k] = dt * re[k]; o[2 * k + 1] = dt * im[k]; }
+        free(re);
+        free(im);
+    }
+    return 0;
+}
+
+/* ======================================================================== */
+/* Step 5: likelihood.                                                      */
+/* ======================================================================== */
+
+/* exp(-2 pi i k phi) with phi = Delta T / (N dt); k*phi is reduced mod 1
+ * exactly (the product's rounding error is recovered with an FMA). */
+static void delay_phase(int64_t k, double phi_frac, double *cr, double *ci)
+{
+    double kk = (double)k;
+    double p = kk * phi_frac;
+    double err = fma(kk, phi_frac, -p);
+    double f = (p - floor(p)) + err;
+    f -= floor(f);
+    *cr = cos(2.0 * O_PI * f);
+    *ci = -sin(2.0 * O_PI * f);
+}
+
+typedef struct { double s, c; } neumaier;
+static void nsum_add(neumaier *a, double v)
+{
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v)) a->c += (a->s - t) + v;
+    else a->c += (v - t) + a->s;
+    a->s = t;
+}
+
+/* lnL = -1/2 sum_{channels} sum_{k=1}^{N/2-1} (4 df / S_k) |d_k - m_k|^2 (reading R8) */
+static double walker_loglike(const double *p, const double *data, const double *psd,
+                             const oracle_cfg *c, double *scratch_x, double *scratch_X)
+{
+    double s[8];
+    walker_scalars(p, s);
+    if (s[0] == 0.0) return -INFINITY;
+    int64_t N = c->N, K = n_intervals_of(c), H = N / 2 + 1;
+    double *orb = (double *)malloc((size_t)(K + 1) * 10 * sizeof(double));
+    int64_t Kw = walker_orbit(p, c, orb);
+    walker_waveform(p, c, orb, Kw, scratch_x, NULL);
+    free(orb);
+    /* FFT both channels */
+    for (int ch = 0; ch < 2; ++ch) {
+        double *re = scratch_X, *im = scratch_X + N;
+        memcpy(re, scratch_x + ch * N, (size_t)N * sizeof(double));
+        memset(im, 0, (size_t)N * sizeof(double));
+        fft_inplace(re, im, N);
+        /* keep bins 0..N/2, scaled by dt, interleaved re/im */
+        double *spec = scratch_X + 2 * N + ch * 2 * H;
+        for (int64_t k = 0; k < H; ++k) { spec[2 * k] = c->dt * re[k]; spec[2 * k + 1] = c->dt * im[k]; }
+    }
+    double g = s[5], dT = s[4];
+    double df = 1.0 / ((double)N * c->dt);
+    double phi = dT / ((double)N * c->dt);
+    phi -= floor(phi);
+    neumaier acc = {0.0, 0.0};
+    for (int ch = 0; ch < 2; ++ch) {
+        const double *spec = scratch_X + 2 * N + ch * 2 * H;
+        const double *d = data + ch * 2 * H;
+        for (int64_t k = 1; k < N / 2; ++k) {
+            double cr, ci;
+            delay_phase(k, phi, &cr, &ci);
+            double hr = spec[2 * k], hi = spec[2 * k + 1];
+            double mr = g * (cr * hr - ci * hi);
+            double mi = g * (cr * hi + ci * hr);
+            double rr = d[2 * k] - mr, ri = d[2 * k + 1] - mi;
+            nsum_add(&acc, (4.0 * df / psd[k]) * (rr * rr + ri * ri));
+        }
+    }
+    return -0.5 * (acc.s + acc.c);
+}
+
+int oracle_loglike(const double *params, int64_t B, const double *data /* [2][N/2+1][2] */,
+                   const double *psd /* [N/2+1] */, const oracle_cfg *c, double *lnL)
+{
+    if (!cfg_ok(c)) return -1;
+    int64_t N = c->N, H = N / 2 + 1;
+#pragma omp parallel
+    {
+        double *sx = (double *)malloc((size_t)(2 * N) * sizeof(double));
+        double *sX = (double *)malloc((size_t)(2 * N + 4 * H) * sizeof(double));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t w = 0; w < B; ++w)
+            lnL[w] = walker_loglike(params + w * NPAR, data, psd, c, sx, sX);
+        free(sx);
+        free(sX);
+    }
+    return 0;
+}
+
+/* ======================================================================== */
+/* Data set helpers (inputs of the likelihood).                             */
+/* ======================================================================== */
+
+/* LISA instrumental noise of BC04 (the paper's example noise model, Sec. 3),
+ * one-sided, in Hz^-1; confusion noise omitted (reading R12). */
+int oracle_psd_bc04(const double *f, int64_t n, double *S)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double v = f[i];
+        S[i] = (v > 0.0) ? 9.18e-52 / (v * v * v * v) + 1.59e-41 + 9.18e-38 * v * v : INFINITY;
+    }
+    return 0;
+}
+
+/* data = m[theta_inj] + n, with n_k = sqrt(S_k N dt / 4) (x_k + i y_k) for the
+ * standard normal draws gauss[2][N/2+1][2] (NULL: noise-less data); bins 0
+ * and N/2 carry no noise.  hinj is the unit-distance GR spectrum. */
+int oracle_make_data(const double *hinj, const double *pinj, const double *psd,
+                     const double *gauss, int64_t N, double dt, double *data)
+{
+    double s[8];
+    walker_scalars(pinj, s);
+    if (s[0] == 0.0) return -2;
+    int64_t H = N / 2 + 1;
+    double g = s[5];
+    double phi = s[4] / ((double)N * dt);
+    phi -= floor(phi);
+    for (int ch = 0; ch < 2; ++ch) {
+        for (int64_t k = 0; k < H; ++k) {
+            double cr, ci;
+            delay_phase(k, phi, &cr, &ci);
+            const double *hk = hinj + (ch * H + k) * 2;
+            double mr = g * (cr * hk[0] - ci * hk[1]);
+            double mi = g * (cr * hk[1] + ci * hk[0]);
+            double nr = 0.0, ni = 0.0;
+            if (gauss && k > 0 && k < N / 2) {
+                double sig = sqrt(psd[k] * (double)N * dt / 4.0);
+                nr = sig * gauss[(ch * H + k) * 2];
+                ni = sig * gauss[(ch * H + k) * 2 + 1];
+            }
+            data[(ch * H + k) * 2] = mr + nr;
+            data[(ch * H + k) * 2 + 1] = mi + ni;
+        }
+    }
+    return 0;
+}
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

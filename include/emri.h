@@ -1,0 +1,154 @@
+/*
+ * emri.h -- C ABI of the MI355X batched EMRI log-likelihood library (libemri).
+ *
+ * The library evaluates, for a batch of MCMC walkers, the log-likelihood of
+ * Saltas & Oliveri, "emri_mc" (arXiv:2311.17174): each walker's Analytic
+ * Kludge waveform is generated from the orbital ODE system (Eq. (1)) and the
+ * harmonic sum (Eq. (2)), projected on the two low-frequency LISA channels,
+ * Fourier transformed (Sec. 3, "Waveform computation"), damped by 1/Xi and
+ * delayed by the GW-speed term (Eqs. (4)-(6)), and weighted by the noise
+ * curve against the data (Eq. (8)).
+ *
+ * Conventions for every entry point:
+ *  - Array pointers are DEVICE pointers owned by the caller, unless stated.
+ *    The library never allocates or frees device memory.  Scratch memory is
+ *    the caller's workspace `ws` of `ws_bytes` bytes (size it with
+ *    emri_workspace_bytes); its contents are undefined after a call.
+ *  - Every call is asynchronous on `stream` (0 = the null stream).  Inputs
+ *    must stay valid, and outputs must not be read, until the stream has
+ *    reached the call's end.  Calls that share a workspace must be ordered.
+ *  - Call-level errors (null pointer, bad configuration, workspace too
+ *    small, launch failure) return a negative status and launch nothing new;
+ *    emri_last_error() then describes the error (per host thread).
+ *  - Per-walker errors are not call errors: a walker outside the physical
+ *    domain gets lnL = -infinity (the log-prior convention of the paper's
+ *    sampler, Sec. 3 file list) and the call returns EMRI_OK.
+ *  - No NaN and no exception crosses the ABI.
+ *  - A parameter row is 17 doubles (EMRI_NPAR), row-major [B][17]:
+ *      0 M [Msun]   1 mu [Msun]   2 a = S/M^2 in [0,1]   3 e0 in [0,1)
+ *      4 nu0 [Hz], 0 < nu0 < nu_LSO(e0)   5 Phi0   6 gamma~0   7 alpha0
+ *      8 cos(lambda)   9 theta_S   10 phi_S   11 theta_K   12 phi_K [rad]
+ *      13 d_L [Gpc] > 0   14 Xi0   15 n (Eq. (6))
+ *      16 alpha_T > -1: constant GW-speed parameter, c_T^2 = 1 + alpha_T
+ *         (Eq. (3)); 0 is General Relativity.
+ *    The first three entries are the masses and spin, as in the paper's
+ *    parameter-vector convention (Sec. 3).  The state Y = (Phi, nu, gamma~,
+ *    e, alpha) of Eq. (1) starts at t = 0 from entries 3..7.
+ */
+#ifndef EMRI_H
+#define EMRI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EMRI_NPAR 17
+#define EMRI_ABI_VERSION 1
+
+typedef enum {
+    EMRI_OK = 0,
+    EMRI_EINVAL = -1,        /* bad argument or configuration              */
+    EMRI_EWORKSPACE = -2,    /* workspace or dataset buffer too small      */
+    EMRI_EDEVICE = -3,       /* HIP launch or device error                 */
+    EMRI_EUNSUPPORTED = -4   /* valid request outside the supported range  */
+} emri_status;
+
+typedef enum {
+    EMRI_FP64 = 0,  /* every stage in FP64                                   */
+    EMRI_MIXED = 1  /* FP64 orbit, phases and final reduction; FP32 harmonic
+                       sum, response, FFT and products with compensated sums */
+} emri_precision;
+
+/* Problem configuration (host struct, passed by pointer).
+ *  T_obs        observation time [s] > 0; N_valid = round(T_obs/dt) samples
+ *  dt           sampling interval [s] > 0 (the paper uses 0.1 Hz, Sec. 3)
+ *  N            transform length, a power of two, 2^12 <= N <= 2^24,
+ *               N >= N_valid; samples N_valid..N-1 are zero padding
+ *  n_harm       number of harmonics n_max of Eq. (2), 1..64
+ *  precision    emri_precision
+ *  coarse_log2  the orbit is integrated with step h = dt * 2^coarse_log2
+ *               (8..12) and read between nodes by cubic Hermite interpolation
+ *  reserved     must be 0 */
+typedef struct {
+    double T_obs;
+    double dt;
+    int64_t N;
+    int32_t n_harm;
+    int32_t precision;
+    int32_t coarse_log2;
+    int32_t reserved;
+} emri_cfg;
+
+/* Library ABI version (EMRI_ABI_VERSION). */
+int emri_abi_version(void);
+
+/* Message for the last non-OK status returned on this host thread. */
+const char* emri_last_error(void);
+
+/* Workspace bytes for B walkers processed at once (0 if cfg is invalid).
+ * The waveform, FFT and likelihood entry points all accept this size. */
+size_t emri_workspace_bytes(const emri_cfg* cfg, int64_t B);
+
+/* Time-domain waveforms (Eqs. (1)-(2) with the LISA response and Doppler
+ * phase), at unit distance and without propagation effects -- the paper's
+ * waveform() excludes the distance factor (Sec. 3 file list).
+ *  params  [B][17] fp64
+ *  ht      [B][N][2] real, channel-interleaved (I, II) per sample; fp64 for
+ *          EMRI_FP64, fp32 for EMRI_MIXED; zero after N_valid and after the
+ *          plunge (the last orbital node before nu reaches nu_LSO(e));
+ *          an invalid walker's rows are all zero
+ *  ws      workspace of at least emri_workspace_bytes(cfg, B) bytes */
+emri_status emri_waveform_batch(const double* params, int64_t B, const emri_cfg* cfg, void* ht,
+                                void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Fourier transform of time-domain waveforms (Sec. 3, "appropriate
+ * normalisation" read as h~(f_k) = dt sum_j h_j exp(-2 pi i j k / N)).
+ *  ht   [B][N][2] real, as written by emri_waveform_batch (fp64 or fp32)
+ *  hf   [B][2][N/2+1] complex (re, im interleaved), bins f_k = k/(N dt),
+ *       channel I then II; fp64 or fp32 following cfg->precision
+ *  ht and hf must not overlap the workspace. */
+emri_status emri_fft_batch(const void* ht, int64_t B, const emri_cfg* cfg, void* hf, void* ws,
+                           size_t ws_bytes, hipStream_t stream);
+
+/* Log-likelihood per walker (Eq. (8), read as -1/2 <d - m | d - m>):
+ *   lnL_w = -1/2 sum_{I,II} sum_{k=1}^{N/2-1} (4 df / S_k) |d_k - m_k|^2,
+ *   m_k = exp(-2 pi i f_k DeltaT) h~_k / (Xi d_L)      (Eqs. (4)-(6))
+ * with df = 1/(N dt); DC and Nyquist bins are excluded.
+ *  data  [2][N/2+1] complex fp64 (re, im interleaved), channel I then II
+ *  psd   [N/2+1] fp64 one-sided noise PSD S_k [1/Hz]; psd[0] is ignored;
+ *        every other entry must be positive (checked on the device: a
+ *        non-positive entry gives that bin weight 0)
+ *  T_obs, dt  must equal cfg->T_obs and cfg->dt
+ *  lnL   [B] fp64 output
+ *  ws    at least emri_dataset_bytes(cfg) + emri_workspace_bytes(cfg, 1)
+ *        bytes; walkers are processed in as many chunks as the workspace
+ *        requires (all at once with dataset + workspace_bytes(cfg, B)) */
+emri_status emri_loglike_batch(const double* params, int64_t B, const double* data,
+                               const double* psd, double T_obs, double dt, const emri_cfg* cfg,
+                               double* lnL, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Resident data sets for repeated likelihood calls (the serving loop).
+ * emri_dataset_init writes, into the caller's buffer `ds`, the data and
+ * noise weights in the order the likelihood kernels read them (and, for
+ * EMRI_MIXED, whitened FP32 copies and the FP64 data norm).  The buffer is
+ * valid for the cfg it was made with (same N, dt, precision). */
+size_t emri_dataset_bytes(const emri_cfg* cfg);
+emri_status emri_dataset_init(const double* data, const double* psd, const emri_cfg* cfg,
+                              void* ds, size_t ds_bytes, hipStream_t stream);
+
+/* As emri_loglike_batch, on a resident data set made by emri_dataset_init.
+ *  ws  at least emri_workspace_bytes(cfg, 1) bytes; chunked as needed. */
+emri_status emri_loglike_dataset(const double* params, int64_t B, const void* ds,
+                                 const emri_cfg* cfg, double* lnL, void* ws, size_t ws_bytes,
+                                 hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EMRI_H */

@@ -471,7 +471,9 @@ static void walker_waveform(const double *p, const oracle_cfg *c, const double *
                          Sv[0] * L[1] - Sv[1] * L[0]};
         double sb = Nv3[0] * SxL[0] + Nv3[1] * SxL[1] + Nv3[2] * SxL[2];
         double cb = NS - ci * cl;
-        double beta = atan2(sb, cb);
+        /* beta is undefined when L is parallel to S or to N (sb = cb = 0 up
+         * to rounding); it is taken as 0 there (reading R4) */
+        double beta = (sb * sb + cb * cb < 1e-24) ? 0.0 : atan2(sb, cb);
         double gam = gt + beta;
 
         /* detector position and Doppler phase (BC04) */

@@ -1,0 +1,262 @@
+// api.hip -- the C ABI of libemri (declared in include/emri.h): argument
+// checks, workspace planning, chunking and the launch sequence of the hot
+// path.  Every arithmetic step runs in the kernels of walker.hip, synth.hip,
+// fft.hip and like.hip.
+#include "internal.hpp"
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+namespace emri {
+
+static thread_local std::string g_err;
+
+static emri_status fail(emri_status st, const char* msg)
+{
+    g_err = msg ? msg : "";
+    return st;
+}
+
+static emri_status fail_hip(hipError_t e, const char* where)
+{
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: %s", where, hipGetErrorString(e));
+    g_err = buf;
+    return EMRI_EDEVICE;
+}
+
+emri_status make_plan(const emri_cfg* cfg, int64_t B, Plan* p, const char** err)
+{
+    *err = nullptr;
+    if (!cfg) { *err = "cfg is NULL"; return EMRI_EINVAL; }
+    if (!(cfg->T_obs > 0.0) || !isfinite(cfg->T_obs)) { *err = "T_obs must be positive"; return EMRI_EINVAL; }
+    if (!(cfg->dt > 0.0) || !isfinite(cfg->dt)) { *err = "dt must be positive"; return EMRI_EINVAL; }
+    if (cfg->N <= 0 || (cfg->N & (cfg->N - 1))) { *err = "N must be a power of two"; return EMRI_EINVAL; }
+    if (cfg->N < ((int64_t)1 << 12) || cfg->N > ((int64_t)1 << 24)) {
+        *err = "N must be in [2^12, 2^24]";
+        return EMRI_EUNSUPPORTED;
+    }
+    const double nvd = cfg->T_obs / cfg->dt;
+    if (!(nvd < 9.0e18)) { *err = "T_obs/dt too large"; return EMRI_EINVAL; }
+    const int64_t Nv = (int64_t)llround(nvd);
+    if (Nv < 1 || Nv > cfg->N) { *err = "need 1 <= round(T_obs/dt) <= N"; return EMRI_EINVAL; }
+    if (cfg->n_harm < 1 || cfg->n_harm > 64) { *err = "n_harm must be in [1, 64]"; return EMRI_EINVAL; }
+    if (cfg->precision != EMRI_FP64 && cfg->precision != EMRI_MIXED) {
+        *err = "unknown precision";
+        return EMRI_EINVAL;
+    }
+    if (cfg->coarse_log2 < 8 || cfg->coarse_log2 > 12) {
+        *err = "coarse_log2 must be in [8, 12]";
+        return EMRI_EUNSUPPORTED;
+    }
+    if (cfg->reserved != 0) { *err = "reserved must be 0"; return EMRI_EINVAL; }
+    if (B < 0) { *err = "B must be >= 0"; return EMRI_EINVAL; }
+
+    Plan& q = *p;
+    memset(&q, 0, sizeof q);
+    q.T_obs = cfg->T_obs;
+    q.dt = cfg->dt;
+    q.N = cfg->N;
+    q.Nv = Nv;
+    int m = 0;
+    while (((int64_t)1 << m) < q.N) ++m;
+    q.m = m;
+    q.nh = cfg->n_harm;
+    q.prec = cfg->precision;
+    q.cl = cfg->coarse_log2;
+    q.L = (int64_t)1 << q.cl;
+    q.K = (Nv + q.L - 1) / q.L;
+    // FFT split: rows (pass B, contiguous) up to 2^13, columns the rest
+    q.m1 = (m + 1) / 2 + 1;
+    if (q.m1 > 13) q.m1 = 13;
+    q.m2 = m - q.m1;
+    q.R1 = (int64_t)1 << q.m1;
+    q.R2 = (int64_t)1 << q.m2;
+    q.esz = (q.prec == EMRI_FP64) ? 16 : 8;
+    q.hsz = (q.prec == EMRI_FP64) ? 8 : 4;
+    int ta = (int)(64 / q.esz);
+    while (ta > 1 && ta * q.R2 / 8 > 1024) ta /= 2;
+    while (ta > 1 && (size_t)ta * (q.R2 + 1) * q.esz > 160 * 1024) ta /= 2;
+    q.TA = ta;
+    q.s_lo = (m + 1) / 2;
+
+    q.B = B;
+    size_t o = 0;
+    const TwLayout tl = tw_layout(q);
+    q.off_tw = o; o += align256(tl.bytes);
+    q.off_wc = o; o += align256((size_t)B * WC * 8);
+    q.off_orb = o; o += align256((size_t)B * (q.K + 1) * 10 * 8);
+    q.off_co = o; o += align256((size_t)B * q.K * 16 * 8);
+    q.off_ch = o; o += align256((size_t)B * q.K * q.nh * 12 * q.hsz);
+    q.off_z = o; o += align256((size_t)B * q.N * q.esz);
+    q.off_part = o; o += align256((size_t)B * q.R2 * 8);
+    q.total = o;
+
+    size_t d = 0;
+    const int64_t half = q.N / 2;
+    q.ds_off_d = d; d += align256((size_t)2 * half * q.esz);
+    q.ds_off_w = d; d += align256((size_t)half * (q.prec == EMRI_FP64 ? 8 : 4));
+    q.ds_off_norm = d; d += 256;
+    q.ds_total = d;
+    return EMRI_OK;
+}
+
+static emri_status check_launch(hipError_t e, const char* where)
+{
+    if (e != hipSuccess) return fail_hip(e, where);
+    return EMRI_OK;
+}
+
+// walkers [0, B) of params, workspace planned for at least B walkers
+static emri_status run_waveforms(const Plan& p, const double* params, int64_t B, void* ws,
+                                 void* out, hipStream_t s)
+{
+    emri_status st;
+    if ((st = check_launch(launch_walker_setup(p, params, B, ws, s), "walker setup"))) return st;
+    if ((st = check_launch(launch_tables(p, B, ws, s), "amplitude tables"))) return st;
+    if ((st = check_launch(launch_synth(p, B, ws, out, s), "synthesis"))) return st;
+    return EMRI_OK;
+}
+
+// largest chunk <= B whose plan fits in `bytes`
+static int64_t fit_chunk(const emri_cfg* cfg, int64_t B, size_t bytes)
+{
+    Plan p;
+    const char* err;
+    int64_t lo = 0, hi = B;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        make_plan(cfg, mid, &p, &err);
+        if (p.total <= bytes) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+}  // namespace emri
+
+using namespace emri;
+
+extern "C" {
+
+int emri_abi_version(void) { return EMRI_ABI_VERSION; }
+
+const char* emri_last_error(void) { return g_err.c_str(); }
+
+size_t emri_workspace_bytes(const emri_cfg* cfg, int64_t B)
+{
+    Plan p;
+    const char* err;
+    if (make_plan(cfg, B < 1 ? 1 : B, &p, &err) != EMRI_OK) return 0;
+    return p.total;
+}
+
+size_t emri_dataset_bytes(const emri_cfg* cfg)
+{
+    Plan p;
+    const char* err;
+    if (make_plan(cfg, 1, &p, &err) != EMRI_OK) return 0;
+    return p.ds_total;
+}
+
+emri_status emri_waveform_batch(const double* params, int64_t B, const emri_cfg* cfg, void* ht,
+                                void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    Plan p;
+    const char* err;
+    emri_status st = make_plan(cfg, B, &p, &err);
+    if (st != EMRI_OK) return fail(st, err);
+    if (B == 0) return EMRI_OK;
+    if (!params || !ht || !ws) return fail(EMRI_EINVAL, "null pointer argument");
+    if (ws_bytes < p.total) return fail(EMRI_EWORKSPACE, "workspace smaller than emri_workspace_bytes(cfg, B)");
+    return run_waveforms(p, params, B, ws, ht, stream);
+}
+
+emri_status emri_fft_batch(const void* ht, int64_t B, const emri_cfg* cfg, void* hf, void* ws,
+                           size_t ws_bytes, hipStream_t stream)
+{
+    Plan p;
+    const char* err;
+    emri_status st = make_plan(cfg, B, &p, &err);
+    if (st != EMRI_OK) return fail(st, err);
+    if (B == 0) return EMRI_OK;
+    if (!ht || !hf || !ws) return fail(EMRI_EINVAL, "null pointer argument");
+    if (ws_bytes < p.total) return fail(EMRI_EWORKSPACE, "workspace smaller than emri_workspace_bytes(cfg, B)");
+    if ((st = check_launch(launch_twiddles(p, ws, stream), "twiddles"))) return st;
+    if ((st = check_launch(launch_fft_from(p, B, ht, ws, stream), "fft"))) return st;
+    return check_launch(launch_unpack(p, B, ws, hf, stream), "unpack");
+}
+
+static emri_status loglike_chunks(const emri_cfg* cfg, const double* params, int64_t B,
+                                  const void* ds, double* lnL, void* ws, size_t ws_bytes,
+                                  hipStream_t stream)
+{
+    Plan p1;
+    const char* err;
+    emri_status st = make_plan(cfg, 1, &p1, &err);
+    if (st != EMRI_OK) return fail(st, err);
+    if (ws_bytes < p1.total) return fail(EMRI_EWORKSPACE, "workspace smaller than emri_workspace_bytes(cfg, 1)");
+    const int64_t chunk = fit_chunk(cfg, B, ws_bytes);
+    Plan p;
+    make_plan(cfg, chunk, &p, &err);
+    if ((st = check_launch(launch_twiddles(p, ws, stream), "twiddles"))) return st;
+    for (int64_t w0 = 0; w0 < B; w0 += chunk) {
+        const int64_t nb = (B - w0 < chunk) ? (B - w0) : chunk;
+        if ((st = run_waveforms(p, params + w0 * EMRI_NPAR, nb, ws,
+                                (char*)ws + p.off_z, stream)))
+            return st;
+        if ((st = check_launch(launch_fft(p, nb, ws, stream), "fft"))) return st;
+        if ((st = check_launch(launch_likelihood(p, nb, ds, ws, lnL + w0, stream), "likelihood")))
+            return st;
+    }
+    return EMRI_OK;
+}
+
+emri_status emri_loglike_batch(const double* params, int64_t B, const double* data,
+                               const double* psd, double T_obs, double dt, const emri_cfg* cfg,
+                               double* lnL, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    Plan p;
+    const char* err;
+    emri_status st = make_plan(cfg, 1, &p, &err);
+    if (st != EMRI_OK) return fail(st, err);
+    if (T_obs != cfg->T_obs || dt != cfg->dt) return fail(EMRI_EINVAL, "T_obs and dt must equal cfg->T_obs and cfg->dt");
+    if (B < 0) return fail(EMRI_EINVAL, "B must be >= 0");
+    if (B == 0) return EMRI_OK;
+    if (!params || !data || !psd || !lnL || !ws) return fail(EMRI_EINVAL, "null pointer argument");
+    const size_t dsb = align256(p.ds_total);
+    if (ws_bytes < dsb + p.total) return fail(EMRI_EWORKSPACE, "workspace smaller than emri_dataset_bytes(cfg) + emri_workspace_bytes(cfg, 1)");
+    if ((st = check_launch(launch_dataset(p, data, psd, ws, stream), "dataset"))) return st;
+    return loglike_chunks(cfg, params, B, ws, lnL, (char*)ws + dsb, ws_bytes - dsb, stream);
+}
+
+emri_status emri_dataset_init(const double* data, const double* psd, const emri_cfg* cfg,
+                              void* ds, size_t ds_bytes, hipStream_t stream)
+{
+    Plan p;
+    const char* err;
+    emri_status st = make_plan(cfg, 1, &p, &err);
+    if (st != EMRI_OK) return fail(st, err);
+    if (!data || !psd || !ds) return fail(EMRI_EINVAL, "null pointer argument");
+    if (ds_bytes < p.ds_total) return fail(EMRI_EWORKSPACE, "dataset buffer smaller than emri_dataset_bytes(cfg)");
+    return check_launch(launch_dataset(p, data, psd, ds, stream), "dataset");
+}
+
+emri_status emri_loglike_dataset(const double* params, int64_t B, const void* ds,
+                                 const emri_cfg* cfg, double* lnL, void* ws, size_t ws_bytes,
+                                 hipStream_t stream)
+{
+    Plan p;
+    const char* err;
+    emri_status st = make_plan(cfg, 1, &p, &err);
+    if (st != EMRI_OK) return fail(st, err);
+    if (B < 0) return fail(EMRI_EINVAL, "B must be >= 0");
+    if (B == 0) return EMRI_OK;
+    if (!params || !ds || !lnL || !ws) return fail(EMRI_EINVAL, "null pointer argument");
+    return loglike_chunks(cfg, params, B, ds, lnL, ws, ws_bytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,353 @@
+// fft.hip -- stage (c): batched FFT of the two-channel waveform.
+//
+// The two real channels are packed as one complex signal z_j = h_I(t_j) +
+// i h_II(t_j); a single N-point complex transform gives both spectra
+// (X_I,k = (Z_k + conj Z_{N-k})/2, X_II,k = (Z_k - conj Z_{N-k})/(2i)).
+//
+// Four-step decomposition N = R1 * R2, j = j1 + R1 j2, k = k2 + R2 k1:
+//   pass A  for each column j1: R2-point FFT over j2 (stride R1), times the
+//           twiddle W_N^{j1 k2}, stored back in place at k2 R1 + j1; a
+//           workgroup owns TA adjacent columns (coalesced runs of TA
+//           elements) and holds them in LDS
+//   pass B  for each row k2: R1-point FFT over j1 (contiguous), in place
+// The spectrum is left in "transposed" order: z[k2 R1 + k1] = Z[k2 + R2 k1].
+// The likelihood reads it in that order (its data and weights are stored in
+// the same order), so no reordering pass is needed on the hot path.
+//
+// In-LDS transforms are Stockham autosort with radix 8 stages (one radix-4 or
+// radix-2 stage for the remainder), L/8 lanes per transform, twiddles from a
+// table W_L^e.  All twiddle tables are computed on the device in FP64 with
+// sincospi and rounded to FP32 for the mixed path.
+#include "internal.hpp"
+
+namespace emri {
+
+template <typename R> struct C2;
+template <> struct C2<double> { using T = double2; };
+template <> struct C2<float> { using T = float2; };
+
+TwLayout tw_layout(const Plan& p)
+{
+    TwLayout t;
+    t.nA = p.R2;
+    t.nB = p.R1;
+    t.nlo = (int64_t)1 << p.s_lo;
+    t.nhi = p.N >> p.s_lo;
+    size_t o = 0;
+    t.oA = o; o += align256(t.nA * 16);
+    t.oB = o; o += align256(t.nB * 16);
+    t.olo = o; o += align256(t.nlo * 16);
+    t.ohi = o; o += align256(t.nhi * 16);
+    t.fA = o; o += align256(t.nA * 8);
+    t.fB = o; o += align256(t.nB * 8);
+    t.flo = o; o += align256(t.nlo * 8);
+    t.fhi = o; o += align256(t.nhi * 8);
+    t.bytes = o;
+    return t;
+}
+
+// table entry i of one of four tables: W_den^{i * mul} = exp(-2 pi i i mul / den)
+__global__ void k_twiddles(int64_t nA, int64_t nB, int64_t nlo, int64_t nhi, int64_t N,
+                           int s_lo, double2* tA, double2* tB, double2* tlo, double2* thi,
+                           float2* fA, float2* fB, float2* flo, float2* fhi)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double2* d;
+    float2* f;
+    double num, den;
+    if (i < nA) { d = tA; f = fA; num = (double)i; den = (double)nA; }
+    else if ((i -= nA) < nB) { d = tB; f = fB; num = (double)i; den = (double)nB; }
+    else if ((i -= nB) < nlo) { d = tlo; f = flo; num = (double)i; den = (double)N; }
+    else if ((i -= nlo) < nhi) {
+        d = thi; f = fhi;
+        // exponent i 2^s_lo of W_N, reduced: (i 2^s_lo) / N = i / (N >> s_lo)
+        num = (double)i; den = (double)(N >> s_lo);
+    } else return;
+    double s, c;
+    sincospi(-2.0 * num / den, &s, &c);
+    d[i] = double2{c, s};
+    f[i] = float2{(float)c, (float)s};
+}
+
+hipError_t launch_twiddles(const Plan& p, void* ws, hipStream_t s)
+{
+    const TwLayout t = tw_layout(p);
+    char* b = (char*)ws + p.off_tw;
+    const int64_t n = t.nA + t.nB + t.nlo + t.nhi;
+    hipLaunchKernelGGL(k_twiddles, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, t.nA,
+                       t.nB, t.nlo, t.nhi, p.N, p.s_lo, (double2*)(b + t.oA),
+                       (double2*)(b + t.oB), (double2*)(b + t.olo), (double2*)(b + t.ohi),
+                       (float2*)(b + t.fA), (float2*)(b + t.fB), (float2*)(b + t.flo),
+                       (float2*)(b + t.fhi));
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// small DFTs in registers, natural order out: b_q = sum_t a_t W_R^{t q}
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ inline void dft2(R& ar, R& ai, R& br, R& bi)
+{
+    const R tr = ar - br, ti = ai - bi;
+    ar += br; ai += bi;
+    br = tr; bi = ti;
+}
+
+template <typename R>
+__device__ inline void dft4(R* xr, R* xi)  // 4 values, in place
+{
+    const R t0r = xr[0] + xr[2], t0i = xi[0] + xi[2];
+    const R t1r = xr[0] - xr[2], t1i = xi[0] - xi[2];
+    const R t2r = xr[1] + xr[3], t2i = xi[1] + xi[3];
+    const R t3r = xi[1] - xi[3], t3i = xr[3] - xr[1];   // (a1 - a3) * (-i)
+    xr[0] = t0r + t2r; xi[0] = t0i + t2i;
+    xr[2] = t0r - t2r; xi[2] = t0i - t2i;
+    xr[1] = t1r + t3r; xi[1] = t1i + t3i;
+    xr[3] = t1r - t3r; xi[3] = t1i - t3i;
+}
+
+template <typename R>
+__device__ inline void dft8(R* xr, R* xi)
+{
+    R er[4] = {xr[0], xr[2], xr[4], xr[6]}, ei[4] = {xi[0], xi[2], xi[4], xi[6]};
+    R orr[4] = {xr[1], xr[3], xr[5], xr[7]}, oi[4] = {xi[1], xi[3], xi[5], xi[7]};
+    dft4(er, ei);
+    dft4(orr, oi);
+    const R h = (R)0.70710678118654752440084436210484903928;
+    // W_8^1 = (1 - i)/sqrt2, W_8^2 = -i, W_8^3 = -(1 + i)/sqrt2
+    R w1r = h * (orr[1] + oi[1]), w1i = h * (oi[1] - orr[1]);
+    R w2r = oi[2], w2i = -orr[2];
+    R w3r = h * (oi[3] - orr[3]), w3i = -h * (orr[3] + oi[3]);
+    xr[0] = er[0] + orr[0]; xi[0] = ei[0] + oi[0];
+    xr[4] = er[0] - orr[0]; xi[4] = ei[0] - oi[0];
+    xr[1] = er[1] + w1r; xi[1] = ei[1] + w1i;
+    xr[5] = er[1] - w1r; xi[5] = ei[1] - w1i;
+    xr[2] = er[2] + w2r; xi[2] = ei[2] + w2i;
+    xr[6] = er[2] - w2r; xi[6] = ei[2] - w2i;
+    xr[3] = er[3] + w3r; xi[3] = ei[3] + w3i;
+    xr[7] = er[3] - w3r; xi[7] = ei[3] - w3i;
+}
+
+template <typename R>
+__device__ inline void cmul(R& xr, R& xi, R wr, R wi)
+{
+    const R t = xr * wr - xi * wi;
+    xi = xr * wi + xi * wr;
+    xr = t;
+}
+
+// One Stockham stage of radix RR over an L-point column in LDS: lane t
+// handles 8/RR butterflies j = t + b L/8; Ns is the product of the radices
+// of the previous stages.
+template <typename R, int RR>
+__device__ inline void lds_stage(R* re, R* im, int L, int Ns, int t,
+                                 const typename C2<R>::T* __restrict__ tw)
+{
+    constexpr int NB = 8 / RR;
+    const int stride = L / RR;
+    const int tws = L / (Ns * RR);          // W_{Ns RR}^{r k} = W_L^{r k tws}
+    R vr[8], vi[8];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = t + b * (L / 8);
+        const int k = j & (Ns - 1);
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+            R xr = re[j + r * stride], xi = im[j + r * stride];
+            if (r > 0 && k > 0) {
+                const typename C2<R>::T wv = tw[r * k * tws];
+                cmul(xr, xi, wv.x, wv.y);
+            }
+            vr[b * RR + r] = xr;
+            vi[b * RR + r] = xi;
+        }
+    }
+    __syncthreads();
+    if constexpr (RR == 8) {
+        dft8(vr, vi);
+    } else if constexpr (RR == 4) {
+        dft4(vr, vi);
+        dft4(vr + 4, vi + 4);
+    } else {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) dft2(vr[2 * b], vi[2 * b], vr[2 * b + 1], vi[2 * b + 1]);
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = t + b * (L / 8);
+        const int k = j & (Ns - 1);
+        const int base = (j - k) * RR + k;
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+            re[base + r * Ns] = vr[b * RR + r];
+            im[base + r * Ns] = vi[b * RR + r];
+        }
+    }
+    __syncthreads();
+}
+
+// L-point FFT (L = 2^lgL >= 8) of one column held in LDS (re/im arrays), by
+// lane t of L/8.  Every lane of the workgroup must call it (barriers).
+template <typename R>
+__device__ void lds_fft(R* re, R* im, int L, int lgL, int t,
+                        const typename C2<R>::T* __restrict__ tw)
+{
+    const int n8 = lgL / 3, rem = lgL - 3 * n8;
+    int Ns = 1;
+    for (int st = 0; st < n8; ++st) {
+        lds_stage<R, 8>(re, im, L, Ns, t, tw);
+        Ns *= 8;
+    }
+    if (rem == 2) lds_stage<R, 4>(re, im, L, Ns, t, tw);
+    else if (rem == 1) lds_stage<R, 2>(re, im, L, Ns, t, tw);
+}
+
+// pass A: TA columns of length L (= R2) per workgroup, TA * L / 8 lanes.
+// in and out may alias (the tile's read and write sets coincide).
+template <typename R>
+__global__ void __launch_bounds__(1024) k_fft_cols(const typename C2<R>::T* in,
+                                                   typename C2<R>::T* out, int64_t N, int64_t R1,
+                                                   int L, int lgL, int TA, int s_lo,
+                                                   const typename C2<R>::T* __restrict__ twL,
+                                                   const typename C2<R>::T* __restrict__ tlo,
+                                                   const typename C2<R>::T* __restrict__ thi)
+{
+    using T2 = typename C2<R>::T;
+    extern __shared__ unsigned char smem_raw[];
+    R* sre = (R*)smem_raw;
+    const int LP = L + 1;                   // padded column stride
+    R* sim = sre + TA * LP;
+    const int64_t w = blockIdx.y;
+    const int64_t c0 = (int64_t)blockIdx.x * TA;
+    const T2* src = in + w * N;
+    T2* dst = out + w * N;
+    const int nt = blockDim.x;
+    const int tmask = TA - 1;
+    int tsh = 0;
+    while ((1 << tsh) < TA) ++tsh;
+    for (int q = threadIdx.x; q < TA * L; q += nt) {
+        const int cc = q & tmask, r = q >> tsh;
+        const T2 v = src[c0 + cc + R1 * (int64_t)r];
+        sre[cc * LP + r] = v.x;
+        sim[cc * LP + r] = v.y;
+    }
+    __syncthreads();
+    const int lanes = L / 8;
+    const int col = threadIdx.x / lanes, t = threadIdx.x - col * lanes;
+    lds_fft<R>(sre + col * LP, sim + col * LP, L, lgL, t, twL);
+    const int64_t lomask = ((int64_t)1 << s_lo) - 1;
+    for (int q = threadIdx.x; q < TA * L; q += nt) {
+        const int cc = q & tmask, k2 = q >> tsh;
+        R xr = sre[cc * LP + k2], xi = sim[cc * LP + k2];
+        const int64_t e = (c0 + cc) * (int64_t)k2;      // < N
+        const T2 a = thi[e >> s_lo], b = tlo[e & lomask];
+        const R wr = a.x * b.x - a.y * b.y, wi = a.x * b.y + a.y * b.x;
+        cmul(xr, xi, wr, wi);
+        dst[c0 + cc + R1 * (int64_t)k2] = T2{xr, xi};
+    }
+}
+
+// pass B: one row of length L (= R1) per workgroup, L / 8 lanes, in place
+template <typename R>
+__global__ void __launch_bounds__(1024) k_fft_rows(typename C2<R>::T* z, int64_t N, int L,
+                                                   int lgL,
+                                                   const typename C2<R>::T* __restrict__ twL)
+{
+    using T2 = typename C2<R>::T;
+    extern __shared__ unsigned char smem_raw[];
+    R* sre = (R*)smem_raw;
+    R* sim = sre + L;
+    const int64_t w = blockIdx.y;
+    T2* row = z + w * N + (int64_t)blockIdx.x * L;
+    for (int q = threadIdx.x; q < L; q += blockDim.x) {
+        const T2 v = row[q];
+        sre[q] = v.x;
+        sim[q] = v.y;
+    }
+    __syncthreads();
+    lds_fft<R>(sre, sim, L, lgL, threadIdx.x, twL);
+    for (int q = threadIdx.x; q < L; q += blockDim.x) row[q] = T2{sre[q], sim[q]};
+}
+
+template <typename R>
+static hipError_t fft_typed(const Plan& p, int64_t B, const void* in, void* ws, hipStream_t s)
+{
+    using T2 = typename C2<R>::T;
+    char* base = (char*)ws;
+    const TwLayout t = tw_layout(p);
+    const char* twb = base + p.off_tw;
+    const bool f64 = sizeof(R) == 8;
+    const T2* tA = (const T2*)(twb + (f64 ? t.oA : t.fA));
+    const T2* tB = (const T2*)(twb + (f64 ? t.oB : t.fB));
+    const T2* tlo = (const T2*)(twb + (f64 ? t.olo : t.flo));
+    const T2* thi = (const T2*)(twb + (f64 ? t.ohi : t.fhi));
+    T2* z = (T2*)(base + p.off_z);
+    const int LA = (int)p.R2, LB = (int)p.R1;
+    const size_t ldsA = (size_t)p.TA * (LA + 1) * 2 * sizeof(R);
+    const size_t ldsB = (size_t)LB * 2 * sizeof(R);
+    static bool attr_done = false;
+    if (!attr_done) {
+        (void)hipFuncSetAttribute((const void*)k_fft_cols<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+        (void)hipFuncSetAttribute((const void*)k_fft_rows<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+        attr_done = true;
+    }
+    hipLaunchKernelGGL(k_fft_cols<R>, dim3((unsigned)(p.R1 / p.TA), (unsigned)B),
+                       dim3((unsigned)(p.TA * LA / 8)), ldsA, s, (const T2*)(in ? in : z), z, p.N,
+                       p.R1, LA, p.m2, p.TA, p.s_lo, tA, tlo, thi);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fft_rows<R>, dim3((unsigned)p.R2, (unsigned)B), dim3((unsigned)(LB / 8)),
+                       ldsB, s, z, p.N, LB, p.m1, tB);
+    return hipGetLastError();
+}
+
+// FFT of the packed signal: input `in` (NULL: the workspace signal itself),
+// result in the workspace signal buffer, transposed order.
+hipError_t launch_fft_from(const Plan& p, int64_t B, const void* in, void* ws, hipStream_t s)
+{
+    if (p.prec == EMRI_FP64) return fft_typed<double>(p, B, in, ws, s);
+    return fft_typed<float>(p, B, in, ws, s);
+}
+
+hipError_t launch_fft(const Plan& p, int64_t B, void* ws, hipStream_t s)
+{
+    return launch_fft_from(p, B, nullptr, ws, s);
+}
+
+// unpack: transposed packed spectrum -> hf[B][2][N/2+1], scaled by dt
+template <typename R>
+__global__ void k_unpack(const typename C2<R>::T* __restrict__ z, typename C2<R>::T* __restrict__ hf,
+                         int64_t N, int64_t R1, int64_t R2, double dt)
+{
+    using T2 = typename C2<R>::T;
+    const int64_t H = N / 2 + 1;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t w = blockIdx.y;
+    if (k >= H) return;
+    const T2* zw = z + w * N;
+    const int64_t km = (N - k) & (N - 1);
+    const T2 a = zw[(k % R2) * R1 + k / R2];
+    const T2 b = zw[(km % R2) * R1 + km / R2];
+    const R h = (R)(0.5 * dt);
+    // X_I = (a + conj b)/2, X_II = (a - conj b)/(2i)
+    hf[(w * 2 + 0) * H + k] = T2{h * (a.x + b.x), h * (a.y - b.y)};
+    hf[(w * 2 + 1) * H + k] = T2{h * (a.y + b.y), -h * (a.x - b.x)};
+}
+
+hipError_t launch_unpack(const Plan& p, int64_t B, const void* ws, void* hf, hipStream_t s)
+{
+    const char* base = (const char*)ws;
+    const int64_t H = p.N / 2 + 1;
+    dim3 grid((unsigned)((H + 255) / 256), (unsigned)B);
+    if (p.prec == EMRI_FP64)
+        hipLaunchKernelGGL(k_unpack<double>, grid, dim3(256), 0, s,
+                           (const double2*)(base + p.off_z), (double2*)hf, p.N, p.R1, p.R2, p.dt);
+    else
+        hipLaunchKernelGGL(k_unpack<float>, grid, dim3(256), 0, s,
+                           (const float2*)(base + p.off_z), (float2*)hf, p.N, p.R1, p.R2, p.dt);
+    return hipGetLastError();
+}
+
+}  // namespace emri

@@ -1,0 +1,115 @@
+// internal.hpp -- shared declarations of the HIP implementation of libemri.
+//
+// Layout of the per-call workspace (all arrays [B][...] for the walkers of one
+// chunk, 256-byte aligned):
+//   tw      FFT twiddle tables (see fft.hip)
+//   wc      [B][WC] fp64 walker constants (scalars + geometry), see WC_*
+//   orb     [B][K+1][10] fp64 orbit nodes: Y_k = (Phi, nu, gamma~, e, alpha)
+//           then dY/dt at t_k = k h
+//   co      [B][K][16] fp64 power-basis Hermite coefficients of Phi, nu,
+//           gamma~, alpha on each coarse interval (u = (t - t_k)/h in [0,1])
+//   ch      [B][K][n_harm][12] harmonic coefficients (fp64, or fp32 for the
+//           mixed path): for each n the cubic in u of A n P_n, A n Q_n and
+//           2 A J_n(ne) (4 coefficients each)
+//   z       [B][N] complex: packed signal h_I + i h_II; the FFT runs in
+//           place and leaves the spectrum in transposed order
+//   part    [B][R2] fp64 per-row partial sums of the likelihood
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/emri.h"
+
+namespace emri {
+
+// ---- walker-constant slots (fp64) ---------------------------------------
+enum {
+    WC_VALID = 0,   // 1: physical walker, 0: lnL = -inf
+    WC_MS = 1,      // M in seconds
+    WC_MUS = 2,     // mu in seconds
+    WC_A = 3,       // spin a = S/M^2
+    WC_CL = 4,      // cos(lambda)
+    WC_SL = 5,      // sin(lambda)
+    WC_G = 6,       // 1/(Xi d_L) with d_L in seconds
+    WC_PHI = 7,     // Delta T / (N dt) reduced to [0, 1)
+    WC_NX = 8, WC_NY = 9, WC_NZ = 10,          // source direction N
+    WC_SX = 11, WC_SY = 12, WC_SZ = 13,        // spin direction S
+    WC_E1X = 14, WC_E1Y = 15, WC_E1Z = 16,     // e1 = (z - S cos th_K)/sin th_K
+    WC_E2X = 17, WC_E2Y = 18,                  // e2 = S x z / sin th_K (z comp 0)
+    WC_NS = 19,     // N . S
+    WC_CTS = 20, WC_STS = 21, WC_CPS = 22, WC_SPS = 23,  // cos/sin theta_S, phi_S
+    WC_DOP = 24,    // 2 pi R sin(theta_S), R = 1 AU / c
+    WC_KW = 25,     // index of the last orbit node before the LSO
+    WC_Z = 26, WC_XI = 27, WC_DT = 28, WC_D = 29,
+    WC_HASDT = 30,  // 1 if Delta T != 0
+    WC = 32
+};
+
+// ---- physical constants (this library's own copy) -----------------------
+constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr double kSunSeconds = 4.925490947641267e-6;      // G Msun / c^3
+constexpr double kLightSpeed = 299792458.0;                // m/s
+constexpr double kParsecM = 3.0856775814913673e16;         // m
+constexpr double kAuSeconds = 1.495978707e11 / 299792458.0;
+constexpr double kYearSeconds = 365.25 * 86400.0;          // Julian year
+constexpr double kHubble = 67.66;                           // km/s/Mpc
+constexpr double kOmegaM = 0.3111;
+
+// ---- plan: sizes and workspace offsets ----------------------------------
+struct Plan {
+    // problem
+    double T_obs, dt;
+    int64_t N, Nv;         // transform length, valid samples
+    int m;                 // log2 N
+    int nh;                // harmonics
+    int prec;              // emri_precision
+    int cl;                // coarse_log2
+    int64_t L;             // samples per coarse interval, 2^cl
+    int64_t K;             // coarse intervals covering N_valid
+    // FFT: N = R1 * R2; pass A: R2-point column FFTs (stride R1), T per WG;
+    // pass B: R1-point row FFTs
+    int m1, m2;
+    int64_t R1, R2;
+    int TA;                // columns per pass-A workgroup
+    int s_lo;              // split of the four-step twiddle exponent
+    size_t esz;            // bytes per complex element (16 or 8)
+    size_t hsz;            // bytes per harmonic coefficient (8 or 4)
+    // workspace (bytes, for B walkers)
+    int64_t B;
+    size_t off_tw, off_wc, off_orb, off_co, off_ch, off_z, off_part, total;
+    // dataset buffer
+    size_t ds_off_d, ds_off_w, ds_off_norm, ds_total;
+};
+
+// fills p; returns EMRI_OK or an error (message in err)
+emri_status make_plan(const emri_cfg* cfg, int64_t B, Plan* p, const char** err);
+
+// twiddle table layout inside the tw region (complex fp64 then fp32 copies)
+struct TwLayout {
+    int64_t nA, nB, nlo, nhi;     // entries of each table
+    size_t oA, oB, olo, ohi;      // fp64 tables (double2)
+    size_t fA, fB, flo, fhi;      // fp32 tables (float2)
+    size_t bytes;
+};
+TwLayout tw_layout(const Plan& p);
+
+// ---- launchers (return hipSuccess or the launch error) -------------------
+hipError_t launch_walker_setup(const Plan& p, const double* params, int64_t B, void* ws,
+                               hipStream_t s);
+hipError_t launch_tables(const Plan& p, int64_t B, void* ws, hipStream_t s);
+hipError_t launch_synth(const Plan& p, int64_t B, void* ws, void* out, hipStream_t s);
+hipError_t launch_twiddles(const Plan& p, void* ws, hipStream_t s);
+hipError_t launch_fft(const Plan& p, int64_t B, void* ws, hipStream_t s);  // z -> z (transposed)
+// FFT reading `in` ([B][N] complex, NULL: the workspace signal), result in z
+hipError_t launch_fft_from(const Plan& p, int64_t B, const void* in, void* ws, hipStream_t s);
+hipError_t launch_unpack(const Plan& p, int64_t B, const void* ws, void* hf, hipStream_t s);
+hipError_t launch_dataset(const Plan& p, const double* data, const double* psd, void* ds,
+                          hipStream_t s);
+hipError_t launch_likelihood(const Plan& p, int64_t B, const void* ds, void* ws, double* lnL,
+                             hipStream_t s);
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace emri

@@ -1,0 +1,238 @@
+// synth.hip -- stage (b): time-domain AK waveform on the fine sampling grid.
+//
+// One workgroup of 256 lanes per (coarse interval k, walker w); each lane
+// produces SPT = 2^coarse_log2 / 256 samples j = k 2^cl + lane + 256 s, so a
+// wave's stores are 64 consecutive samples (coalesced).  Everything a wave
+// needs from the orbit and the amplitude tables is uniform over the interval
+// and is read with scalar loads.
+//
+// Per sample (Eq. (2) with the BC04 response; the oracle spells out the same
+// quantities with angles and atan2, here double angles come from the
+// tangent-pair identities cos 2x = (c^2 - s^2)/(c^2 + s^2) and
+// sin 2x = 2 s c / (c^2 + s^2), so no inverse trigonometry is evaluated):
+//   Phi, nu, gamma~, alpha      cubic Hermite in u (FP64)
+//   Phi' = Phi + 2 pi nu R sin(theta_S) cos(phibar - phi_S)  Doppler phase
+//   L = cos(lambda) S + sin(lambda) (cos(alpha) e1 + sin(alpha) e2)
+//   S_a = sum_n A n P_n cos(n Phi'), S_b = sum_n A n Q_n sin(n Phi'),
+//   S_c = sum_n 2 A J_n cos(n Phi')   (harmonics by complex rotation)
+//   h+ = (1 + c^2)(S_a cos 2g - S_b sin 2g) + (1 - c^2) S_c
+//   hx = -2 c (S_b cos 2g + S_a sin 2g),  c = L.N, g = gamma~ + beta
+//   h_I/II = sqrt(3)/2 (F+ h+ + Fx hx), channel II at phi_d - pi/4
+#include "internal.hpp"
+
+namespace emri {
+
+template <typename R> struct V2;
+template <> struct V2<double> { using T = double2; };
+template <> struct V2<float> { using T = float2; };
+
+// sin/cos of a small angle d (|d| < 1e-2) by Taylor series to d^9
+template <typename R>
+__device__ inline void small_sincos(R d, R* s, R* c)
+{
+    const R d2 = d * d;
+    *s = d * (R(1) - d2 * (R(1) / R(6) - d2 * (R(1) / R(120) - d2 * (R(1) / R(5040) - d2 * (R(1) / R(362880))))));
+    *c = R(1) - d2 * (R(0.5) - d2 * (R(1) / R(24) - d2 * (R(1) / R(720) - d2 * (R(1) / R(40320)))));
+}
+
+// cos 2x, sin 2x for x = atan2(y, x0); (1, 0) when undefined, that is when
+// x0^2 + y^2 < 1e-24 (only reached by degenerate geometry, where rounding
+// residues would otherwise pick an arbitrary angle)
+template <typename R>
+__device__ inline void double_angle(R x0, R y, R* c2, R* s2)
+{
+    const R d = x0 * x0 + y * y;
+    if (d >= R(1e-24)) {
+        const R id = R(1) / d;
+        *c2 = (x0 * x0 - y * y) * id;
+        *s2 = R(2) * x0 * y * id;
+    } else {
+        *c2 = R(1);
+        *s2 = R(0);
+    }
+}
+
+// sin/cos of an FP64 angle in precision R: FP64 uses the library sincos;
+// FP32 reduces the angle modulo 2 pi in FP64 first.
+__device__ inline void angle_sincos(double a, double* s, double* c) { sincos(a, s, c); }
+__device__ inline void angle_sincos(double a, float* s, float* c)
+{
+    double r = a * (0.5 / kPi);
+    r -= rint(r);                      // r in [-1/2, 1/2]
+    sincospif((float)(2.0 * r), s, c);
+}
+
+template <typename R, typename HT, int SPT>
+__global__ void __launch_bounds__(256) k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
+                                               double dt, const double* __restrict__ wc,
+                                               const double* __restrict__ co,
+                                               const HT* __restrict__ ch,
+                                               typename V2<R>::T* __restrict__ out)
+{
+    using R2 = typename V2<R>::T;
+    constexpr int L = 256 * SPT;
+    const int64_t k = blockIdx.x;
+    const int64_t w = blockIdx.y;
+    const int lane = threadIdx.x;
+    R2* zw = out + w * N;
+    const int64_t j0 = k * L;
+    const double* c = wc + w * WC;
+    const int64_t Kw = (int64_t)c[WC_KW];
+    if (c[WC_VALID] == 0.0 || k >= Kw || j0 >= Nv) {
+#pragma unroll
+        for (int s = 0; s < SPT; ++s) zw[j0 + lane + 256 * s] = R2{R(0), R(0)};
+        return;
+    }
+
+    // ---- uniform per interval --------------------------------------------
+    const double* q = co + (w * K + k) * 16;
+    const double dop = c[WC_DOP];
+    const double cps = c[WC_CPS], sps = c[WC_SPS];
+    // detector azimuth at the start of the interval
+    double sb0, cb0;
+    sincospi(2.0 * (double)j0 * dt / kYearSeconds, &sb0, &cb0);
+    const double dphi = 2.0 * kPi * dt / kYearSeconds;   // per sample
+    const double invL = 1.0 / (double)L;
+
+    // ---- per sample: phases ------------------------------------------------
+    R u[SPT], cpb[SPT], spb[SPT];          // u, cos/sin of phibar
+    R c1[SPT], s1[SPT];                     // e^{i Phi'}
+#pragma unroll
+    for (int s = 0; s < SPT; ++s) {
+        const int off = lane + 256 * s;
+        const double ud = (double)off * invL;
+        u[s] = (R)ud;
+        const double Phi = ((q[3] * ud + q[2]) * ud + q[1]) * ud + q[0];
+        const double nu = ((q[7] * ud + q[6]) * ud + q[5]) * ud + q[4];
+        R sd, cd;
+        small_sincos<R>((R)(dphi * (double)off), &sd, &cd);
+        const R cb = (R)cb0 * cd - (R)sb0 * sd;
+        const R sb = (R)sb0 * cd + (R)cb0 * sd;
+        cpb[s] = cb;
+        spb[s] = sb;
+        const double cdel = (double)cb * cps + (double)sb * sps;   // cos(phibar - phi_S)
+        const double Phid = Phi + dop * nu * cdel;
+        angle_sincos(Phid, &s1[s], &c1[s]);
+    }
+
+    // ---- harmonic sum ------------------------------------------------------
+    R Sa[SPT], Sb[SPT], Sc[SPT], cn[SPT], sn[SPT];
+#pragma unroll
+    for (int s = 0; s < SPT; ++s) {
+        Sa[s] = Sb[s] = Sc[s] = R(0);
+        cn[s] = c1[s];
+        sn[s] = s1[s];
+    }
+    const HT* hq = ch + (w * K + k) * (int64_t)nh * 12;
+    for (int n = 0; n < nh; ++n) {
+        const HT* t = hq + 12 * n;
+        const R a0 = (R)t[0], a1 = (R)t[1], a2 = (R)t[2], a3 = (R)t[3];
+        const R b0 = (R)t[4], b1 = (R)t[5], b2 = (R)t[6], b3 = (R)t[7];
+        const R e0 = (R)t[8], e1 = (R)t[9], e2 = (R)t[10], e3 = (R)t[11];
+#pragma unroll
+        for (int s = 0; s < SPT; ++s) {
+            const R x = u[s];
+            const R ua = ((a3 * x + a2) * x + a1) * x + a0;
+            const R ub = ((b3 * x + b2) * x + b1) * x + b0;
+            const R uc = ((e3 * x + e2) * x + e1) * x + e0;
+            Sa[s] += ua * cn[s];
+            Sb[s] += ub * sn[s];
+            Sc[s] += uc * cn[s];
+            const R cc = cn[s] * c1[s] - sn[s] * s1[s];
+            sn[s] = sn[s] * c1[s] + cn[s] * s1[s];
+            cn[s] = cc;
+        }
+    }
+
+    // ---- geometry, response, store -----------------------------------------
+    const R Nx = (R)c[WC_NX], Ny = (R)c[WC_NY], Nz = (R)c[WC_NZ];
+    const R Sx = (R)c[WC_SX], Sy = (R)c[WC_SY], Sz = (R)c[WC_SZ];
+    const R E1x = (R)c[WC_E1X], E1y = (R)c[WC_E1Y], E1z = (R)c[WC_E1Z];
+    const R E2x = (R)c[WC_E2X], E2y = (R)c[WC_E2Y];
+    const R cl = (R)c[WC_CL], sl = (R)c[WC_SL], NS = (R)c[WC_NS];
+    const R cts = (R)c[WC_CTS], sts = (R)c[WC_STS];
+    const R Rcps = (R)cps, Rsps = (R)sps;
+    // N x S, for sin(beta) = L . (N x S)
+    const R NSx = Ny * Sz - Nz * Sy, NSy = Nz * Sx - Nx * Sz, NSz = Nx * Sy - Ny * Sx;
+    const R h3 = (R)0.8660254037844386467637231707529362;  // sqrt(3)/2
+#pragma unroll
+    for (int s = 0; s < SPT; ++s) {
+        const int64_t j = j0 + lane + 256 * s;
+        if (j >= Nv) {
+            zw[j] = R2{R(0), R(0)};
+            continue;
+        }
+        const double ud = (double)u[s];
+        const double gt = ((q[11] * ud + q[10]) * ud + q[9]) * ud + q[8];
+        const double al = ((q[15] * ud + q[14]) * ud + q[13]) * ud + q[12];
+        R sa, ca, s2g, c2g;
+        angle_sincos(al, &sa, &ca);
+        angle_sincos(2.0 * gt, &s2g, &c2g);
+        const R Lx = cl * Sx + sl * (ca * E1x + sa * E2x);
+        const R Ly = cl * Sy + sl * (ca * E1y + sa * E2y);
+        const R Lz = cl * Sz + sl * (ca * E1z);
+        const R ci = Lx * Nx + Ly * Ny + Lz * Nz;
+        // beta: cos ~ N.S - c cos(lambda), sin ~ L.(N x S)
+        // (undefined, taken as 0, when L is parallel to S: sin(lambda) = 0)
+        R c2b = R(1), s2b = R(0);
+        if (sl != R(0)) double_angle<R>(NS - ci * cl, Lx * NSx + Ly * NSy + Lz * NSz, &c2b, &s2b);
+        const R c2 = c2g * c2b - s2g * s2b;     // cos 2 gamma
+        const R s2 = s2g * c2b + c2g * s2b;     // sin 2 gamma
+        const R ci2 = ci * ci;
+        const R hp = (R(1) + ci2) * (Sa[s] * c2 - Sb[s] * s2) + (R(1) - ci2) * Sc[s];
+        const R hx = R(-2) * ci * (Sb[s] * c2 + Sa[s] * s2);
+
+        // detector frame
+        const R cb = cpb[s], sb = spb[s];
+        const R cdel = cb * Rcps + sb * Rsps;         // cos(phibar - phi_S)
+        const R sdel = sb * Rcps - cb * Rsps;         // sin(phibar - phi_S)
+        const R cthd = R(0.5) * cts - h3 * sts * cdel;
+        R c2d, s2d;
+        double_angle<R>(R(2) * sts * sdel, R(2) * h3 * cts + sts * cdel, &c2d, &s2d);
+        const R c2pb = cb * cb - sb * sb, s2pb = R(2) * sb * cb;
+        const R c2p = c2pb * c2d - s2pb * s2d;        // cos 2 phi_d
+        const R s2p = s2pb * c2d + c2pb * s2d;        // sin 2 phi_d
+        // polarisation angle psi: tan psi = (L.zd - c cos th_d) / (zd . (N x L))
+        const R zx = -h3 * cb, zy = -h3 * sb, zz = R(0.5);
+        const R Lzd = Lx * zx + Ly * zy + Lz * zz;
+        const R NLx = Ny * Lz - Nz * Ly, NLy = Nz * Lx - Nx * Lz, NLz = Nx * Ly - Ny * Lx;
+        R c2s, s2s;
+        double_angle<R>(zx * NLx + zy * NLy + zz * NLz, Lzd - ci * cthd, &c2s, &s2s);
+        const R aa = R(0.5) * (R(1) + cthd * cthd);
+        const R FpI = aa * c2p * c2s - cthd * s2p * s2s;
+        const R FxI = aa * c2p * s2s + cthd * s2p * c2s;
+        const R FpII = aa * s2p * c2s + cthd * c2p * s2s;
+        const R FxII = aa * s2p * s2s - cthd * c2p * c2s;
+        zw[j] = R2{h3 * (FpI * hp + FxI * hx), h3 * (FpII * hp + FxII * hx)};
+    }
+}
+
+template <typename R, typename HT>
+static hipError_t synth_dispatch(const Plan& p, int64_t B, const char* base, void* out,
+                                 hipStream_t s)
+{
+    dim3 grid((unsigned)(p.N / p.L), (unsigned)B);
+    using R2 = typename V2<R>::T;
+    const double* wc = (const double*)(base + p.off_wc);
+    const double* co = (const double*)(base + p.off_co);
+    const HT* ch = (const HT*)(base + p.off_ch);
+    R2* o = (R2*)out;
+    switch (p.cl) {
+    case 8:  hipLaunchKernelGGL((k_synth<R, HT, 1>), grid, dim3(256), 0, s, p.K, p.Nv, p.N, p.nh, p.dt, wc, co, ch, o); break;
+    case 9:  hipLaunchKernelGGL((k_synth<R, HT, 2>), grid, dim3(256), 0, s, p.K, p.Nv, p.N, p.nh, p.dt, wc, co, ch, o); break;
+    case 10: hipLaunchKernelGGL((k_synth<R, HT, 4>), grid, dim3(256), 0, s, p.K, p.Nv, p.N, p.nh, p.dt, wc, co, ch, o); break;
+    case 11: hipLaunchKernelGGL((k_synth<R, HT, 8>), grid, dim3(256), 0, s, p.K, p.Nv, p.N, p.nh, p.dt, wc, co, ch, o); break;
+    case 12: hipLaunchKernelGGL((k_synth<R, HT, 16>), grid, dim3(256), 0, s, p.K, p.Nv, p.N, p.nh, p.dt, wc, co, ch, o); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_synth(const Plan& p, int64_t B, void* ws, void* out, hipStream_t s)
+{
+    const char* base = (const char*)ws;
+    if (p.prec == EMRI_FP64) return synth_dispatch<double, double>(p, B, base, out, s);
+    return synth_dispatch<float, float>(p, B, base, out, s);
+}
+
+}  // namespace emri

@@ -1,0 +1,382 @@
+// walker.hip -- per-walker stages of the likelihood: scalars, orbit, tables.
+//
+//  k_walker_setup   one lane per walker (FP64): validity, z(d_L), Xi(z),
+//                   propagation delay, geometry constants, then the orbital
+//                   ODE of Eq. (1) by classical RK4 on the coarse grid, stopped
+//                   at the last node before the LSO (Sec. 3).
+//  k_tables         one lane per (walker, coarse interval, harmonic): Bessel
+//                   functions of the Peters-Mathews amplitudes at both ends of
+//                   the interval and their time derivatives, folded into cubic
+//                   Hermite polynomials in the interval coordinate u.
+#include "internal.hpp"
+
+#include <math.h>
+
+namespace emri {
+
+struct GL8 {            // 8-point Gauss-Legendre rule on [-1, 1], both halves
+    double x[4], w[4];  // positive nodes and weights
+};
+
+// ---------------------------------------------------------------------------
+// cosmology (flat LCDM, Planck 2018 H0 and Omega_m): d_L = (1+z) D_H I(z),
+// I(z) = int_0^z dz'/E(z'), E = sqrt(Om (1+z)^3 + 1 - Om).
+// I(z) by composite 8-point Gauss-Legendre on 16 panels.
+// ---------------------------------------------------------------------------
+__device__ inline double inv_hubble_rate(double z)
+{
+    double a = 1.0 + z;
+    return rsqrt(kOmegaM * a * a * a + (1.0 - kOmegaM));
+}
+
+__device__ double comoving_integral(double z, const GL8& g)
+{
+    const int panels = 16;
+    double h = z / panels, acc = 0.0;
+    for (int p = 0; p < panels; ++p) {
+        double c = (p + 0.5) * h, r = 0.5 * h, s = 0.0;
+        for (int i = 0; i < 4; ++i)
+            s += g.w[i] * (inv_hubble_rate(c - r * g.x[i]) + inv_hubble_rate(c + r * g.x[i]));
+        acc += r * s;
+    }
+    return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Eq. (1): right-hand side of the AK orbital system (Barack & Cutler 2004),
+// written with x = 2 pi M nu, eps = 1 - e^2.  Depends only on (nu, e).
+// ---------------------------------------------------------------------------
+struct Rhs { double dPhi, dnu, dgt, de, dal; };
+
+__device__ inline Rhs ak_rhs(double nu, double e, double Ms, double mus, double a, double cl)
+{
+    const double x = 2.0 * kPi * Ms * nu;
+    const double x13 = cbrt(x);
+    const double x23 = x13 * x13;
+    const double e2 = e * e, e4 = e2 * e2, e6 = e4 * e2;
+    const double eps = 1.0 - e2;
+    const double ie = 1.0 / eps;
+    const double rse = rsqrt(eps);          // eps^{-1/2}
+    const double ie2 = ie * ie, ie4 = ie2 * ie2;
+    const double acl = a * cl;
+    const double M2 = Ms * Ms;
+    Rhs r;
+    r.dPhi = 2.0 * kPi * nu;
+    double b = (1.0 + (73.0 / 24.0) * e2 + (37.0 / 96.0) * e4) * eps +
+               x23 * (1273.0 / 336.0 - (2561.0 / 224.0) * e2 - (3885.0 / 128.0) * e4 -
+                      (13147.0 / 5376.0) * e6) -
+               x * acl * rse *
+                   (73.0 / 12.0 + (1211.0 / 24.0) * e2 + (3143.0 / 96.0) * e4 +
+                    (65.0 / 64.0) * e6);
+    const double x113 = x * x * x * x23;    // x^{11/3}
+    r.dnu = (96.0 / (10.0 * kPi)) * (mus / (M2 * Ms)) * x113 * ie4 * rse * b;
+    r.dgt = 6.0 * kPi * nu * x23 * ie * (1.0 + 0.25 * x23 * ie * (26.0 - 15.0 * e2)) -
+            12.0 * kPi * nu * acl * x * ie * rse;
+    const double x83 = x * x * x23;         // x^{8/3}
+    double br = (304.0 + 121.0 * e2) * eps * (1.0 + 12.0 * x23) -
+                (x23 / 56.0) * (133640.0 + 108984.0 * e2 - 25211.0 * e4);
+    r.de = -(e / 15.0) * (mus / M2) * ie2 * ie * rse * x83 * br +
+           e * (mus / M2) * acl * x113 * ie4 *
+               (1364.0 / 5.0 + (5032.0 / 15.0) * e2 + (263.0 / 10.0) * e4);
+    r.dal = 4.0 * kPi * nu * a * x * ie * rse;
+    return r;
+}
+
+// before the last stable orbit: nu < nu_LSO(e) of Sec. 3, on a sane state
+__device__ inline bool before_lso(double Phi, double nu, double gt, double e, double al, double Ms)
+{
+    if (!(isfinite(Phi) && isfinite(nu) && isfinite(gt) && isfinite(e) && isfinite(al)))
+        return false;
+    if (!(nu > 0.0 && e >= 0.0 && e < 1.0)) return false;
+    const double x13 = cbrt(2.0 * kPi * Ms * nu);
+    return x13 * x13 * (6.0 + 2.0 * e) < (1.0 - e) * (1.0 + e);
+}
+
+// ---------------------------------------------------------------------------
+// k_walker_setup: one lane per walker
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_walker_setup(const double* __restrict__ params, int64_t B,
+                                                     int64_t K, double h, double Ndt, GL8 gl,
+                                                     double* __restrict__ wc,
+                                                     double* __restrict__ orb)
+{
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= B) return;
+    const double* p = params + w * EMRI_NPAR;
+    double* c = wc + w * WC;
+    for (int i = 0; i < WC; ++i) c[i] = 0.0;
+    c[WC_KW] = -1.0;
+
+    bool ok = true;
+    for (int i = 0; i < EMRI_NPAR; ++i) ok = ok && isfinite(p[i]);
+    const double M = p[0], mu = p[1], a = p[2], e0 = p[3], nu0 = p[4];
+    const double cl = p[8], dl = p[13], xi0 = p[14], nxi = p[15], at = p[16];
+    ok = ok && mu > 0.0 && mu < M && a >= 0.0 && a <= 1.0 && e0 >= 0.0 && e0 < 1.0 &&
+         nu0 > 0.0 && dl > 0.0 && at > -1.0 && cl >= -1.0 && cl <= 1.0;
+    const double Ms = M * kSunSeconds, mus = mu * kSunSeconds;
+    ok = ok && before_lso(p[5], nu0, p[6], e0, p[7], Ms);
+    if (!ok) return;
+
+    // distance, redshift, Eq. (6), delay, overall factor
+    const double D = dl * 1e9 * kParsecM / kLightSpeed;
+    const double DH = (kLightSpeed / 1000.0 / kHubble) * 1e6 * kParsecM / kLightSpeed;
+    double z = D / DH;
+    for (int it = 0; it < 40; ++it) {
+        const double I = comoving_integral(z, gl);
+        const double f = (1.0 + z) * DH * I - D;
+        const double fp = DH * I + (1.0 + z) * DH * inv_hubble_rate(z);
+        const double dz = f / fp;
+        z -= dz;
+        if (fabs(dz) <= 4e-16 * (1.0 + z)) break;
+    }
+    const double Xi = xi0 + (1.0 - xi0) * exp(-nxi * log1p(z));
+    if (!(Xi > 0.0) || !isfinite(Xi)) return;
+    const double chi = D / (1.0 + z);
+    const double cT = sqrt(1.0 + at);
+    const double dT = -at / (cT * (1.0 + cT)) * chi;
+    double ph = dT / Ndt;
+    ph -= floor(ph);
+
+    const double thS = p[9], phS = p[10], thK = p[11], phK = p[12];
+    double sts, cts, sps, cps, stk, ctk, spk, cpk;
+    sincos(thS, &sts, &cts);
+    sincos(phS, &sps, &cps);
+    sincos(thK, &stk, &ctk);
+    sincos(phK, &spk, &cpk);
+
+    c[WC_MS] = Ms;
+    c[WC_MUS] = mus;
+    c[WC_A] = a;
+    c[WC_CL] = cl;
+    c[WC_SL] = sqrt(fmax(0.0, (1.0 - cl) * (1.0 + cl)));
+    c[WC_G] = 1.0 / (Xi * D);
+    c[WC_PHI] = ph;
+    c[WC_NX] = sts * cps; c[WC_NY] = sts * sps; c[WC_NZ] = cts;
+    c[WC_SX] = stk * cpk; c[WC_SY] = stk * spk; c[WC_SZ] = ctk;
+    c[WC_E1X] = -ctk * cpk; c[WC_E1Y] = -ctk * spk; c[WC_E1Z] = stk;
+    c[WC_E2X] = spk; c[WC_E2Y] = -cpk;
+    c[WC_NS] = sts * stk * (cps * cpk + sps * spk) + cts * ctk;
+    c[WC_CTS] = cts; c[WC_STS] = sts; c[WC_CPS] = cps; c[WC_SPS] = sps;
+    c[WC_DOP] = 2.0 * kPi * kAuSeconds * sts;
+    c[WC_Z] = z; c[WC_XI] = Xi; c[WC_DT] = dT; c[WC_D] = D;
+    c[WC_HASDT] = (dT != 0.0) ? 1.0 : 0.0;
+
+    // orbit: classical RK4, nodes t_k = k h
+    double Y0 = p[5], Y1 = nu0, Y2 = p[6], Y3 = e0, Y4 = p[7];
+    double* o = orb + w * (K + 1) * 10;
+    Rhs f = ak_rhs(Y1, Y3, Ms, mus, a, cl);
+    o[0] = Y0; o[1] = Y1; o[2] = Y2; o[3] = Y3; o[4] = Y4;
+    o[5] = f.dPhi; o[6] = f.dnu; o[7] = f.dgt; o[8] = f.de; o[9] = f.dal;
+    int64_t Kw = K;
+    const double hh = 0.5 * h, h6 = h / 6.0;
+    for (int64_t k = 0; k < K; ++k) {
+        const Rhs k2 = ak_rhs(Y1 + hh * f.dnu, Y3 + hh * f.de, Ms, mus, a, cl);
+        const Rhs k3 = ak_rhs(Y1 + hh * k2.dnu, Y3 + hh * k2.de, Ms, mus, a, cl);
+        const Rhs k4 = ak_rhs(Y1 + h * k3.dnu, Y3 + h * k3.de, Ms, mus, a, cl);
+        Y0 += h6 * (f.dPhi + 2.0 * k2.dPhi + 2.0 * k3.dPhi + k4.dPhi);
+        Y1 += h6 * (f.dnu + 2.0 * k2.dnu + 2.0 * k3.dnu + k4.dnu);
+        Y2 += h6 * (f.dgt + 2.0 * k2.dgt + 2.0 * k3.dgt + k4.dgt);
+        Y3 += h6 * (f.de + 2.0 * k2.de + 2.0 * k3.de + k4.de);
+        Y4 += h6 * (f.dal + 2.0 * k2.dal + 2.0 * k3.dal + k4.dal);
+        if (!before_lso(Y0, Y1, Y2, Y3, Y4, Ms)) { Kw = k; break; }
+        f = ak_rhs(Y1, Y3, Ms, mus, a, cl);
+        double* q = o + (k + 1) * 10;
+        q[0] = Y0; q[1] = Y1; q[2] = Y2; q[3] = Y3; q[4] = Y4;
+        q[5] = f.dPhi; q[6] = f.dnu; q[7] = f.dgt; q[8] = f.de; q[9] = f.dal;
+    }
+    c[WC_KW] = (double)Kw;
+    c[WC_VALID] = 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// Bessel functions J_{n-3..n+3}(X), X >= 0, by downward recurrence
+// J_{q-1} = (2q/X) J_q - J_{q+1} from a high even order, normalised with
+// J_0 + 2 (J_2 + J_4 + ...) = 1.  A sliding window of seven orders is kept.
+// ---------------------------------------------------------------------------
+__device__ void bessel7(int n, double X, double J[7])
+{
+    if (X == 0.0) {
+        for (int i = 0; i < 7; ++i) J[i] = (n - 3 + i == 0) ? 1.0 : 0.0;
+        return;
+    }
+    const int lo = n - 3 > 0 ? n - 3 : 0;
+    const int top = max(n + 3, (int)ceil(X));
+    int S = top + 16 + (int)sqrt(200.0 * top);
+    S += S & 1;
+    // window w[i] = J_{q+i} once order q has been produced
+    double w0 = 1e-280, w1 = 0.0, w2 = 0.0, w3 = 0.0, w4 = 0.0, w5 = 0.0, w6 = 0.0;
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0, s6 = 0;
+    double norm = (S & 1) ? 0.0 : 2.0 * w0;  // S even: J_S enters the sum
+    const double iX2 = 2.0 / X;
+    for (int q = S; q >= 1; --q) {
+        const double next = (q * iX2) * w0 - w1;  // J_{q-1}
+        w6 = w5; w5 = w4; w4 = w3; w3 = w2; w2 = w1; w1 = w0; w0 = next;
+        const int o = q - 1;
+        if (o > 0 && !(o & 1)) norm += 2.0 * w0;
+        if (fabs(w0) > 1e200) {  // keep the saved window on the running scale
+            const double r = 1e-200;
+            w0 *= r; w1 *= r; w2 *= r; w3 *= r; w4 *= r; w5 *= r; w6 *= r; norm *= r;
+            if (o < lo) { s0 *= r; s1 *= r; s2 *= r; s3 *= r; s4 *= r; s5 *= r; s6 *= r; }
+        }
+        if (o == lo) { s0 = w0; s1 = w1; s2 = w2; s3 = w3; s4 = w4; s5 = w5; s6 = w6; }
+    }
+    norm += w0;  // J_0
+    const double in = 1.0 / norm;
+    if (n >= 3) {
+        J[0] = s0 * in; J[1] = s1 * in; J[2] = s2 * in; J[3] = s3 * in;
+        J[4] = s4 * in; J[5] = s5 * in; J[6] = s6 * in;
+    } else if (n == 2) {  // orders -1..5 from J_0..J_6
+        J[0] = -s1 * in; J[1] = s0 * in; J[2] = s1 * in; J[3] = s2 * in;
+        J[4] = s3 * in; J[5] = s4 * in; J[6] = s5 * in;
+    } else {              // n == 1: orders -2..4
+        J[0] = s2 * in; J[1] = -s1 * in; J[2] = s0 * in; J[3] = s1 * in;
+        J[4] = s2 * in; J[5] = s3 * in; J[6] = s4 * in;
+    }
+}
+
+// values and e-derivatives of n P_n, n Q_n, 2 J_n at (n, e); A factor applied
+// by the caller.  J holds J_{n-3..n+3}(n e).
+struct PM { double a, b, c, da, db, dc; };
+
+__device__ inline PM pm_amplitudes(int n, double e, const double J[7])
+{
+    // J[3] = J_n; derivative dJ_k/dX = (J_{k-1} - J_{k+1})/2, X = n e
+    const double jm2 = J[1], jm1 = J[2], j0 = J[3], jp1 = J[4], jp2 = J[5];
+    const double dm2 = 0.5 * (J[0] - J[2]), dm1 = 0.5 * (J[1] - J[3]), d0 = 0.5 * (J[2] - J[4]),
+                 dp1 = 0.5 * (J[3] - J[5]), dp2 = 0.5 * (J[4] - J[6]);
+    const double dn = (double)n;
+    const double P = jm2 - 2.0 * e * jm1 + (2.0 / dn) * j0 + 2.0 * e * jp1 - jp2;
+    const double dP = dn * (dm2 - 2.0 * e * dm1 + (2.0 / dn) * d0 + 2.0 * e * dp1 - dp2) -
+                      2.0 * jm1 + 2.0 * jp1;
+    const double s = sqrt((1.0 - e) * (1.0 + e));
+    const double qb = jm2 - 2.0 * j0 + jp2;
+    const double Q = s * qb;
+    const double dQ = (s > 0.0 ? -e / s : 0.0) * qb + s * dn * (dm2 - 2.0 * d0 + dp2);
+    PM r;
+    r.a = dn * P;  r.da = dn * dP;
+    r.b = dn * Q;  r.db = dn * dQ;
+    r.c = 2.0 * j0; r.dc = 2.0 * dn * d0;
+    return r;
+}
+
+// cubic Hermite in u from values/derivatives (derivatives per unit time)
+__device__ inline void hermite_coeffs(double y0, double d0, double y1, double d1, double h,
+                                      double c[4])
+{
+    c[0] = y0;
+    c[1] = h * d0;
+    c[2] = 3.0 * (y1 - y0) - h * (2.0 * d0 + d1);
+    c[3] = 2.0 * (y0 - y1) + h * (d0 + d1);
+}
+
+template <typename HT>
+__global__ void __launch_bounds__(256) k_tables(int64_t K, int nh, double h,
+                                                const double* __restrict__ wc,
+                                                const double* __restrict__ orb,
+                                                double* __restrict__ co, HT* __restrict__ ch)
+{
+    const int64_t w = blockIdx.y;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= K * nh) return;
+    const double* c = wc + w * WC;
+    if (c[WC_VALID] == 0.0) return;
+    const int64_t k = t / nh;
+    const int n = (int)(t - k * nh) + 1;
+    const int64_t Kw = (int64_t)c[WC_KW];
+    if (k >= Kw) return;
+    const double* o0 = orb + (w * (K + 1) + k) * 10;
+    const double* o1 = o0 + 10;
+    const double Ms = c[WC_MS], mus = c[WC_MUS];
+
+    if (n == 1) {  // orbital interpolants: Phi, nu, gamma~, alpha
+        double* q = co + (w * K + k) * 16;
+        const int comp[4] = {0, 1, 2, 4};
+        for (int i = 0; i < 4; ++i) {
+            double cc[4];
+            hermite_coeffs(o0[comp[i]], o0[5 + comp[i]], o1[comp[i]], o1[5 + comp[i]], h, cc);
+            q[4 * i + 0] = cc[0]; q[4 * i + 1] = cc[1]; q[4 * i + 2] = cc[2]; q[4 * i + 3] = cc[3];
+        }
+    }
+
+    // A = (2 pi M nu)^{2/3} mu and the amplitudes at both nodes
+    double v[2][3], d[2][3];
+    for (int s = 0; s < 2; ++s) {
+        const double* o = s ? o1 : o0;
+        const double nu = o[1], e = o[3], dnu = o[6], de = o[8];
+        const double x13 = cbrt(2.0 * kPi * Ms * nu);
+        const double A = x13 * x13 * mus;
+        const double dA = (2.0 / 3.0) * A * dnu / nu;
+        double J[7];
+        bessel7(n, n * e, J);
+        const PM pm = pm_amplitudes(n, e, J);
+        v[s][0] = A * pm.a; d[s][0] = dA * pm.a + A * pm.da * de;
+        v[s][1] = A * pm.b; d[s][1] = dA * pm.b + A * pm.db * de;
+        v[s][2] = A * pm.c; d[s][2] = dA * pm.c + A * pm.dc * de;
+    }
+    HT* q = ch + ((w * K + k) * nh + (n - 1)) * 12;
+    for (int i = 0; i < 3; ++i) {
+        double cc[4];
+        hermite_coeffs(v[0][i], d[0][i], v[1][i], d[1][i], h, cc);
+        for (int j = 0; j < 4; ++j) q[4 * i + j] = (HT)cc[j];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+static GL8 make_gl8()
+{
+    // roots of the Legendre polynomial P_8 by Newton's method in long double
+    GL8 g;
+    const int n = 8;
+    for (int i = 0; i < 4; ++i) {
+        long double x = cosl(3.14159265358979323846264338327950288L * (i + 0.75L) / (n + 0.5L));
+        long double dp = 0;
+        for (int it = 0; it < 100; ++it) {
+            long double p0 = 1, p1 = x;
+            for (int k = 2; k <= n; ++k) {
+                long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+                p0 = p1; p1 = p2;
+            }
+            dp = n * (x * p1 - p0) / (x * x - 1);
+            long double dx = p1 / dp;
+            x -= dx;
+            if (fabsl(dx) < 1e-19L) break;
+        }
+        g.x[i] = (double)x;
+        g.w[i] = (double)(2.0L / ((1 - x * x) * dp * dp));
+    }
+    return g;
+}
+
+hipError_t launch_walker_setup(const Plan& p, const double* params, int64_t B, void* ws,
+                               hipStream_t s)
+{
+    static const GL8 gl = make_gl8();
+    char* base = (char*)ws;
+    const double h = p.dt * (double)p.L;
+    dim3 grid((unsigned)((B + 63) / 64));
+    hipLaunchKernelGGL(k_walker_setup, grid, dim3(64), 0, s, params, B, p.K, h,
+                       (double)p.N * p.dt, gl, (double*)(base + p.off_wc),
+                       (double*)(base + p.off_orb));
+    return hipGetLastError();
+}
+
+hipError_t launch_tables(const Plan& p, int64_t B, void* ws, hipStream_t s)
+{
+    char* base = (char*)ws;
+    const double h = p.dt * (double)p.L;
+    const int64_t n = p.K * p.nh;
+    dim3 grid((unsigned)((n + 255) / 256), (unsigned)B);
+    if (p.prec == EMRI_FP64)
+        hipLaunchKernelGGL(k_tables<double>, grid, dim3(256), 0, s, p.K, p.nh, h,
+                           (const double*)(base + p.off_wc), (const double*)(base + p.off_orb),
+                           (double*)(base + p.off_co), (double*)(base + p.off_ch));
+    else
+        hipLaunchKernelGGL(k_tables<float>, grid, dim3(256), 0, s, p.K, p.nh, h,
+                           (const double*)(base + p.off_wc), (const double*)(base + p.off_orb),
+                           (double*)(base + p.off_co), (float*)(base + p.off_ch));
+    return hipGetLastError();
+}
+
+}  // namespace emri

@@ -1,0 +1,217 @@
+"""Thin Python binding of libemri (include/emri.h): argument marshalling only.
+
+Every step of the likelihood runs in the HIP kernels of ``libemri.so``; this
+module passes torch device pointers and the current stream through ctypes.
+Importing it loads the library and fails loudly if it has not been built
+(``python -m paper_2311_17174_amd.build``).  There is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch  # must be imported before the library so one HIP runtime is used
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libemri.so")
+
+NPAR = 17
+FP64 = 0
+MIXED = 1
+PRECISIONS = {"fp64": FP64, "mixed": MIXED}
+
+EXPORTED = ("emri_abi_version", "emri_last_error", "emri_workspace_bytes",
+            "emri_waveform_batch", "emri_fft_batch", "emri_loglike_batch",
+            "emri_dataset_bytes", "emri_dataset_init", "emri_loglike_dataset")
+
+
+class EmriError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where} failed with status {status}: {msg}")
+        self.status = status
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [("T_obs", ctypes.c_double), ("dt", ctypes.c_double), ("N", ctypes.c_int64),
+                ("n_harm", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("coarse_log2", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+@dataclass(frozen=True)
+class Config:
+    T_obs: float
+    dt: float
+    N: int
+    n_harm: int
+    precision: int = FP64
+    coarse_log2: int = 10
+
+    @staticmethod
+    def from_workload(w) -> "Config":
+        return Config(w.T_obs, w.dt, w.N, w.n_harm, PRECISIONS[w.precision], w.coarse_log2)
+
+    def c(self) -> _Cfg:
+        return _Cfg(float(self.T_obs), float(self.dt), int(self.N), int(self.n_harm),
+                    int(self.precision), int(self.coarse_log2), 0)
+
+    @property
+    def real_dtype(self) -> torch.dtype:
+        return torch.float64 if self.precision == FP64 else torch.float32
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2311_17174_amd.build` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, i64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64
+    cp = ctypes.POINTER(_Cfg)
+    d = ctypes.c_double
+    sig = {
+        "emri_abi_version": ([], ctypes.c_int),
+        "emri_last_error": ([], ctypes.c_char_p),
+        "emri_workspace_bytes": ([cp, i64], sz),
+        "emri_dataset_bytes": ([cp], sz),
+        "emri_waveform_batch": ([vp, i64, cp, vp, vp, sz, vp], ctypes.c_int),
+        "emri_fft_batch": ([vp, i64, cp, vp, vp, sz, vp], ctypes.c_int),
+        "emri_loglike_batch": ([vp, i64, vp, vp, d, d, cp, vp, vp, sz, vp], ctypes.c_int),
+        "emri_dataset_init": ([vp, vp, cp, vp, sz, vp], ctypes.c_int),
+        "emri_loglike_dataset": ([vp, i64, vp, cp, vp, vp, sz, vp], ctypes.c_int),
+    }
+    for name, (a, r) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = a
+        f.restype = r
+    return L
+
+
+lib = _load()
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise EmriError(rc, where, lib.emri_last_error().decode())
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _dev(t: torch.Tensor, dtype: torch.dtype, shape, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t.data_ptr()
+
+
+def workspace_bytes(cfg: Config, B: int) -> int:
+    c = cfg.c()
+    n = lib.emri_workspace_bytes(ctypes.byref(c), int(B))
+    if n == 0:
+        raise EmriError(-1, "emri_workspace_bytes", "invalid configuration")
+    return n
+
+
+def dataset_bytes(cfg: Config) -> int:
+    c = cfg.c()
+    n = lib.emri_dataset_bytes(ctypes.byref(c))
+    if n == 0:
+        raise EmriError(-1, "emri_dataset_bytes", "invalid configuration")
+    return n
+
+
+def alloc_workspace(cfg: Config, B: int, device="cuda", with_dataset: bool = False):
+    n = workspace_bytes(cfg, B) + (dataset_bytes(cfg) + 256 if with_dataset else 0)
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def waveform_batch(params: torch.Tensor, cfg: Config, out: torch.Tensor | None = None,
+                   ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """[B][N][2] channel-interleaved time-domain waveforms (unit distance)."""
+    B = params.shape[0]
+    pp = _dev(params, torch.float64, (B, NPAR), "params")
+    if out is None:
+        out = torch.empty((B, cfg.N, 2), dtype=cfg.real_dtype, device=params.device)
+    op = _dev(out, cfg.real_dtype, (B, cfg.N, 2), "out")
+    if ws is None:
+        ws = alloc_workspace(cfg, B, params.device)
+    c = cfg.c()
+    _check(lib.emri_waveform_batch(pp, B, ctypes.byref(c), op, ws.data_ptr(), ws.numel(),
+                                   _stream(stream)), "emri_waveform_batch")
+    return out
+
+
+def fft_batch(ht: torch.Tensor, cfg: Config, out: torch.Tensor | None = None,
+              ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """[B][2][N/2+1] complex spectra (dt-normalised) of [B][N][2] waveforms."""
+    B = ht.shape[0]
+    hp = _dev(ht, cfg.real_dtype, (B, cfg.N, 2), "ht")
+    H = cfg.N // 2 + 1
+    if out is None:
+        out = torch.empty((B, 2, H, 2), dtype=cfg.real_dtype, device=ht.device)
+    op = _dev(out, cfg.real_dtype, (B, 2, H, 2), "out")
+    if ws is None:
+        ws = alloc_workspace(cfg, B, ht.device)
+    c = cfg.c()
+    _check(lib.emri_fft_batch(hp, B, ctypes.byref(c), op, ws.data_ptr(), ws.numel(),
+                              _stream(stream)), "emri_fft_batch")
+    return torch.view_as_complex(out)
+
+
+def loglike_batch(params: torch.Tensor, data: torch.Tensor, psd: torch.Tensor, cfg: Config,
+                  out: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+                  stream=None) -> torch.Tensor:
+    """lnL[B] (fp64).  data: [2][N/2+1][2] fp64 (re, im), psd: [N/2+1] fp64."""
+    B = params.shape[0]
+    H = cfg.N // 2 + 1
+    pp = _dev(params, torch.float64, (B, NPAR), "params")
+    dp = _dev(data, torch.float64, (2, H, 2), "data")
+    sp = _dev(psd, torch.float64, (H,), "psd")
+    if out is None:
+        out = torch.empty(B, dtype=torch.float64, device=params.device)
+    op = _dev(out, torch.float64, (B,), "out")
+    if ws is None:
+        ws = alloc_workspace(cfg, B, params.device, with_dataset=True)
+    c = cfg.c()
+    _check(lib.emri_loglike_batch(pp, B, dp, sp, float(cfg.T_obs), float(cfg.dt),
+                                  ctypes.byref(c), op, ws.data_ptr(), ws.numel(),
+                                  _stream(stream)), "emri_loglike_batch")
+    return out
+
+
+def dataset_init(data: torch.Tensor, psd: torch.Tensor, cfg: Config,
+                 out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    H = cfg.N // 2 + 1
+    dp = _dev(data, torch.float64, (2, H, 2), "data")
+    sp = _dev(psd, torch.float64, (H,), "psd")
+    n = dataset_bytes(cfg)
+    if out is None:
+        out = torch.empty(n, dtype=torch.uint8, device=data.device)
+    c = cfg.c()
+    _check(lib.emri_dataset_init(dp, sp, ctypes.byref(c), out.data_ptr(), out.numel(),
+                                 _stream(stream)), "emri_dataset_init")
+    return out
+
+
+def loglike_dataset(params: torch.Tensor, ds: torch.Tensor, cfg: Config,
+                    out: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+                    stream=None) -> torch.Tensor:
+    B = params.shape[0]
+    pp = _dev(params, torch.float64, (B, NPAR), "params")
+    if out is None:
+        out = torch.empty(B, dtype=torch.float64, device=params.device)
+    op = _dev(out, torch.float64, (B,), "out")
+    if ws is None:
+        ws = alloc_workspace(cfg, B, params.device)
+    c = cfg.c()
+    _check(lib.emri_loglike_dataset(pp, B, ds.data_ptr(), ctypes.byref(c), op, ws.data_ptr(),
+                                    ws.numel(), _stream(stream)), "emri_loglike_dataset")
+    return out

@@ -1,0 +1,99 @@
+"""Host-side checks of the C ABI (no GPU compute): the library loads, exports
+every entry point include/emri.h declares, and its planning functions
+validate configurations and size workspaces consistently."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2311_17174_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "emri.h")
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_2311_17174_amd import emri
+    return emri
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(emri_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_api():
+    names = declared_functions()
+    for n in ("emri_waveform_batch", "emri_fft_batch", "emri_loglike_batch",
+              "emri_workspace_bytes", "emri_dataset_init", "emri_loglike_dataset"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(E):
+    out = subprocess.check_output(["nm", "-D", "--defined-only", E.LIB_PATH]).decode()
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    assert set(E.EXPORTED) == set(declared_functions())
+    assert E.lib.emri_abi_version() == 1
+
+
+def test_struct_layout_matches_header(E):
+    # int64 N at offset 16, then four int32: 40 bytes in total
+    assert ctypes.sizeof(E._Cfg) == 40
+    assert E._Cfg.N.offset == 16 and E._Cfg.n_harm.offset == 24
+
+
+@pytest.mark.parametrize("bad", [
+    dict(N=3 << 12), dict(N=1 << 11), dict(N=1 << 25), dict(dt=0.0), dict(T_obs=-1.0),
+    dict(n_harm=0), dict(n_harm=65), dict(precision=2), dict(coarse_log2=7),
+    dict(coarse_log2=13), dict(T_obs=1e7),
+])
+def test_invalid_configurations_are_rejected(E, bad):
+    base = dict(T_obs=2.5 * 86400, dt=10.0, N=1 << 15, n_harm=8, precision=0, coarse_log2=10)
+    base.update(bad)
+    c = E.Config(**base)
+    assert E.lib.emri_workspace_bytes(ctypes.byref(c.c()), 4) == 0
+    assert E.lib.emri_dataset_bytes(ctypes.byref(c.c())) == 0
+
+
+def test_workspace_grows_with_batch_and_precision(E):
+    for w in (W.config1(), W.config2(), W.small()):
+        c = E.Config.from_workload(w)
+        sizes = [E.workspace_bytes(c, b) for b in (1, 2, 8, 64)]
+        assert sizes == sorted(sizes) and sizes[0] < sizes[-1]
+        per = (sizes[3] - sizes[2]) / 56
+        # the packed signal dominates: N complex elements per walker
+        assert per >= w.N * 16
+        cm = E.Config.from_workload(w.with_(precision="mixed"))
+        assert E.workspace_bytes(cm, 64) < sizes[3]
+        assert E.dataset_bytes(cm) < E.dataset_bytes(c)
+
+
+def test_config2_fits_one_mi355x(E):
+    c = E.Config.from_workload(W.config2())
+    total = E.workspace_bytes(c, 256) + E.dataset_bytes(c)
+    assert total < 32 * 2 ** 30     # well inside 288 GB of HBM
+
+
+def test_call_errors_without_launch(E):
+    """A null workspace or a mismatched T_obs is a call error that is caught on
+    the host before anything touches a device."""
+    c = E.Config.from_workload(W.small())
+    cc = c.c()
+    rc = E.lib.emri_loglike_batch(None, 4, None, None, c.T_obs, c.dt, ctypes.byref(cc), None,
+                                  None, 0, None)
+    assert rc == -1
+    assert b"null" in E.lib.emri_last_error()
+    rc = E.lib.emri_loglike_batch(None, 4, None, None, c.T_obs + 1, c.dt, ctypes.byref(cc),
+                                  None, None, 0, None)
+    assert rc == -1
+    rc = E.lib.emri_loglike_batch(None, 0, None, None, c.T_obs, c.dt, ctypes.byref(cc), None,
+                                  None, 0, None)
+    assert rc == 0
+    rc = E.lib.emri_waveform_batch(ctypes.c_void_p(8), 4, ctypes.byref(cc), ctypes.c_void_p(8),
+                                   ctypes.c_void_p(8), 16, None)
+    assert rc == -2

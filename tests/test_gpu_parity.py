@@ -1,0 +1,214 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Tolerances (derived in the design notes):
+  FP64 waveform  |dh| <= 64 n_max Phi_max eps64 max|h|: the only non-rounding
+                 differences are the phase roundings (Phi ~ 1e3..1e6 rad,
+                 multiplied by n up to n_max) and the coarse-table
+                 interpolation of the Bessel amplitudes (~1e-14)
+  FP64 spectrum  |dX| <= 1e-12 max|X|
+  FP64 lnL       relative 1e-10 (the stated FP64 target)
+  mixed lnL      relative 1e-4 (the stated mixed target)
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2311_17174_amd import workloads as W
+from tests.gpu_common import EPS64, max_phase, ocfg, oracle_dataset, say, to_device_data
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_2311_17174_amd import emri
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return emri
+
+
+def gpu_params(P):
+    return torch.from_numpy(np.ascontiguousarray(P)).cuda()
+
+
+def edge_walkers(w):
+    """walkers around the injection plus modified gravity, a GW-speed delay,
+    degenerate geometry and invalid rows"""
+    P = list(W.walkers(w, B=6))
+    p = w.inj.copy(); p[14], p[15] = 0.9, 2.0; P.append(p)                  # Xi(z)
+    p = w.inj.copy(); p[16] = -2.4e-13; P.append(p)                         # delay ~1e4 s
+    p = w.inj.copy(); p[3] = 0.0; P.append(p)                               # circular
+    p = w.inj.copy(); p[8] = 1.0; P.append(p)                               # L || S
+    p = w.inj.copy(); p[2] = 0.0; P.append(p)                               # no spin
+    p = w.inj.copy(); p[1] = 2e6; P.append(p)                               # mu > M
+    p = w.inj.copy(); p[4] = 1.0; P.append(p)                               # past the LSO
+    p = w.inj.copy(); p[13] = np.nan; P.append(p)                           # NaN
+    return np.array(P)
+
+
+# ------------------------------------------------------------------ waveform
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_waveform_parity_small(E, prec):
+    w = W.small(prec, n_harm=8)
+    P = edge_walkers(w)
+    say("waveform", w.name, P.shape)
+    cfg = E.Config.from_workload(w)
+    got = E.waveform_batch(gpu_params(P), cfg).cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    ref = O.waveform(P, ocfg(w))                    # [B][2][N]
+    got = got.transpose(0, 2, 1)
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(got - ref), axis=(1, 2)) / scale
+    say("max rel err per walker", err)
+    if prec == "fp64":
+        tol = 64 * w.n_harm * max_phase(w, P[:5]) * EPS64
+    else:
+        tol = 2e-5
+    assert np.all(err <= tol), (err, tol)
+    # invalid walkers: all zero; padding after N_valid: zero
+    assert np.all(got[-3:] == 0.0)
+    assert np.all(got[:, :, w.n_valid:] == 0.0)
+
+
+def test_waveform_plunge_inside_window(E):
+    """A walker that reaches the LSO mid-window: zeros after the last node."""
+    w = W.small("fp64", n_harm=6, days=20.0, N=1 << 18, M=1e5, e0=0.5, a=0.9, nu0=6.3e-3)
+    P = W.walkers(w, B=3)
+    orb, kw = O.orbit(P, ocfg(w))
+    say("plunge nodes", kw, "of", w.n_intervals)
+    assert np.all(kw < w.n_intervals - 2)
+    cfg = E.Config.from_workload(w)
+    got = E.waveform_batch(gpu_params(P), cfg).cpu().numpy().transpose(0, 2, 1)
+    ref = O.waveform(P, ocfg(w))
+    scale = np.max(np.abs(ref))
+    tol = 64 * w.n_harm * max_phase(w, P) * EPS64
+    assert np.max(np.abs(got - ref)) <= tol * scale
+    for b in range(3):
+        assert np.all(got[b, :, kw[b] << w.coarse_log2:] == 0.0)
+        assert np.any(got[b, :, (kw[b] << w.coarse_log2) - 1] != 0.0)
+
+
+# ----------------------------------------------------------------------- FFT
+@pytest.mark.parametrize("logN", [12, 13, 15, 18, 20])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fft_parity(E, logN, prec):
+    N = 1 << logN
+    dt = 10.0
+    w = W.Workload("fft", 3, (N - 5) * dt, dt, N, 1, 10, prec)
+    cfg = E.Config.from_workload(w)
+    x = np.random.Generator(np.random.PCG64(logN)).standard_normal((3, N, 2))
+    x[:, N - 5:] = 0.0
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    say("fft", logN, prec)
+    xt = torch.from_numpy(x).to(dtype).cuda().contiguous()
+    got = E.fft_batch(xt, cfg).cpu().numpy().astype(np.complex128)
+    ref = O.rfft(xt.cpu().double().numpy().transpose(0, 2, 1), dt)   # [3][2][N/2+1]
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    say("rel err", err)
+    assert err <= (1e-12 if prec == "fp64" else 2e-6)
+
+
+# ---------------------------------------------------------------- likelihood
+@pytest.mark.parametrize("noise", [True, False])
+def test_loglike_parity_fp64_small(E, noise):
+    w = W.small("fp64", n_harm=8)
+    P = edge_walkers(w)
+    d, S = oracle_dataset(w, noise)
+    ref = O.loglike(P, d, S, ocfg(w))
+    cfg = E.Config.from_workload(w)
+    dd, ss = to_device_data(d, S)
+    got = E.loglike_batch(gpu_params(P), dd, ss, cfg).cpu().numpy()
+    say("lnL ref", ref)
+    say("lnL got", got)
+    fin = np.isfinite(ref)
+    assert np.array_equal(fin, np.isfinite(got))
+    assert np.all(got[~fin] == -np.inf)
+    if noise:
+        np.testing.assert_allclose(got[fin], ref[fin], rtol=1e-10, atol=0)
+    else:
+        # noise-less data: lnL(injection) = 0; scale by the optimal SNR^2
+        zero = np.zeros_like(d)
+        hh = -2.0 * O.loglike(w.inj[None], zero, S, ocfg(w))[0]
+        assert np.max(np.abs(got[fin] - ref[fin])) <= 1e-10 * hh
+        assert abs(got[0]) <= 1e-10 * hh
+
+
+def test_loglike_parity_mixed_small(E):
+    w = W.small("mixed", n_harm=8)
+    P = edge_walkers(w)
+    d, S = oracle_dataset(w, True)
+    ref = O.loglike(P, d, S, ocfg(w))
+    cfg = E.Config.from_workload(w)
+    dd, ss = to_device_data(d, S)
+    got = E.loglike_batch(gpu_params(P), dd, ss, cfg).cpu().numpy()
+    fin = np.isfinite(ref)
+    assert np.array_equal(fin, np.isfinite(got))
+    rel = np.abs(got[fin] - ref[fin]) / np.abs(ref[fin])
+    say("mixed rel err", rel)
+    assert np.all(rel <= 1e-4)
+
+
+def test_batch_invariance_and_chunking(E):
+    """Per-walker results do not depend on the batch: permuted, split and
+    chunked evaluations are bitwise equal."""
+    w = W.small("fp64", n_harm=6)
+    P = W.walkers(w, B=12)
+    d, S = oracle_dataset(w, True)
+    cfg = E.Config.from_workload(w)
+    dd, ss = to_device_data(d, S)
+    full = E.loglike_batch(gpu_params(P), dd, ss, cfg).cpu().numpy()
+    perm = np.random.Generator(np.random.PCG64(9)).permutation(12)
+    permuted = E.loglike_batch(gpu_params(P[perm]), dd, ss, cfg).cpu().numpy()
+    assert np.array_equal(permuted, full[perm])
+    part = E.loglike_batch(gpu_params(P[3:5]), dd, ss, cfg).cpu().numpy()
+    assert np.array_equal(part, full[3:5])
+    # workspace for 5 walkers + the data set: 3 chunks
+    n = E.dataset_bytes(cfg) + 256 + E.workspace_bytes(cfg, 5)
+    ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+    chunked = E.loglike_batch(gpu_params(P), dd, ss, cfg, ws=ws).cpu().numpy()
+    assert np.array_equal(chunked, full)
+    # resident data set
+    ds = E.dataset_init(dd, ss, cfg)
+    res = E.loglike_dataset(gpu_params(P), ds, cfg).cpu().numpy()
+    assert np.array_equal(res, full)
+    # repeated calls are deterministic
+    again = E.loglike_batch(gpu_params(P), dd, ss, cfg).cpu().numpy()
+    assert np.array_equal(again, full)
+
+
+# ---------------------------------------------------------- full-size cases
+def test_config1_full_parity(E):
+    """Config 1 (FP64, B=32, 30 days, 2^18 samples, 16 harmonics): every walker."""
+    w = W.config1()
+    P = W.walkers(w)
+    say("config1 oracle data")
+    d, S = oracle_dataset(w, True)
+    cfg = E.Config.from_workload(w)
+    dd, ss = to_device_data(d, S)
+    got = E.loglike_batch(gpu_params(P), dd, ss, cfg).cpu().numpy()
+    say("config1 oracle lnL")
+    ref = O.loglike(P, d, S, ocfg(w))
+    rel = np.abs(got - ref) / np.abs(ref)
+    say("config1 max rel", rel.max())
+    assert np.all(rel <= 1e-10)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_config2_sampled_parity(E, prec):
+    """Config 2 / 3 (B=256, 1 yr, 2^22 samples, 30 harmonics) in the launch
+    configuration of the benchmark; the oracle checks sampled walkers."""
+    w = W.config2() if prec == "fp64" else W.config3()
+    P = W.walkers(w)
+    say("config2 oracle data", prec)
+    d, S = oracle_dataset(W.config2(), True)
+    cfg = E.Config.from_workload(w)
+    dd, ss = to_device_data(d, S)
+    got = E.loglike_batch(gpu_params(P), dd, ss, cfg).cpu().numpy()
+    assert np.all(np.isfinite(got))
+    idx = np.array([0, 1, 77, 255])
+    say("config2 oracle lnL for", idx)
+    ref = O.loglike(P[idx], d, S, ocfg(w))
+    rel = np.abs(got[idx] - ref) / np.abs(ref)
+    say(prec, "rel err", rel, "signal-part err", np.abs(got[idx] - ref))
+    assert np.all(rel <= (1e-10 if prec == "fp64" else 1e-4))

@@ -147,6 +147,34 @@ emri_status emri_loglike_dataset(const double* params, int64_t B, const void* ds
                                  const emri_cfg* cfg, double* lnL, void* ws, size_t ws_bytes,
                                  hipStream_t stream);
 
+/* Frequency-domain model of each walker, the quantity the likelihood
+ * compares with the data (Eqs. (4)-(6) applied to the transformed waveform):
+ *   m_k = exp(-2 pi i f_k DeltaT) h~_k / (Xi d_L),  k = 0..N/2
+ *  mf   [B][2][N/2+1] complex (re, im interleaved), fp64 or fp32 following
+ *       cfg->precision; an invalid walker's rows are zero
+ *  ws   at least emri_workspace_bytes(cfg, B) bytes
+ * With a noise draw added, the model at the injection is the mock data set
+ * (the paper's fiducial h[theta_0](f), Sec. 3 "Overview"). */
+emri_status emri_model_batch(const double* params, int64_t B, const emri_cfg* cfg, void* mf,
+                             void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* One-sided LISA noise PSD on the frequency grid f_k = k/(N dt), k = 0..N/2
+ * (the paper's get_noise(), Sec. 3).  model 0: instrumental noise of Barack
+ * & Cutler 2004, S(f) = 9.18e-52 f^-4 + 1.59e-41 + 9.18e-38 f^2 [1/Hz];
+ * psd[0] = +infinity.  Other models: EMRI_EUNSUPPORTED.
+ *  psd  [N/2+1] fp64 device output */
+emri_status emri_noise_psd(int model, int64_t N, double dt, double* psd, hipStream_t stream);
+
+/* Per-stage device timing (profiling).  While enabled, every kernel launch
+ * of the library is bracketed by HIP events on its stream.
+ * emri_trace_read synchronises the recorded events, writes for each stage i
+ * (0 <= i < n) the summed duration in ms and the number of launches since the
+ * previous read, and returns the number of stages.  Stage names come from
+ * emri_trace_stage_name.  Host-thread safe only if one thread traces. */
+emri_status emri_trace_enable(int on);
+int emri_trace_read(double* ms, int64_t* launches, int n);
+const char* emri_trace_stage_name(int i);
+
 #ifdef __cplusplus
 }
 #endif

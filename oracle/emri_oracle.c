@@ -488,7 +488,10 @@ static void walker_waveform(const double *p, const oracle_cfg *c, const double *
         double Lxz[3] = {L[1] * zd[2] - L[2] * zd[1], L[2] * zd[0] - L[0] * zd[2],
                          L[0] * zd[1] - L[1] * zd[0]};
         double NLz = Nv3[0] * Lxz[0] + Nv3[1] * Lxz[1] + Nv3[2] * Lxz[2];
-        double psi = atan2(Lz - ci * cthd, NLz);
+        /* psi is undefined for a face-on or face-off source (L parallel to
+         * N); it is taken as 0 there, like beta */
+        double yps = Lz - ci * cthd;
+        double psi = (yps * yps + NLz * NLz < 1e-24) ? 0.0 : atan2(yps, NLz);
         double FpI, FxI, FpII, FxII;
         antenna(cthd, phid, psi, &FpI, &FxI);
         antenna(cthd, phid - 0.25 * O_PI, psi, &FpII, &FxII);

@@ -8,11 +8,50 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
+#include <vector>
 
 namespace emri {
 
 static thread_local std::string g_err;
+
+// ---- event tracing ---------------------------------------------------------
+static const char* const kStageNames[ST_COUNT] = {
+    "walker_setup", "amplitude_tables", "synthesis", "twiddles", "fft_columns",
+    "fft_rows", "unpack", "dataset", "inner_product", "walker_sum", "noise_psd"};
+
+struct TraceRec { int stage; hipEvent_t a, b; };
+static std::mutex g_trace_mu;
+static bool g_trace_on = false;
+static std::vector<hipEvent_t> g_events;   // pool, reused after each read
+static size_t g_next_event = 0;
+static std::vector<TraceRec> g_recs;
+
+static hipEvent_t next_event()
+{
+    if (g_next_event == g_events.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        g_events.push_back(e);
+    }
+    return g_events[g_next_event++];
+}
+
+void trace_mark(int stage, hipStream_t s, bool begin)
+{
+    if (!g_trace_on) return;
+    std::lock_guard<std::mutex> lk(g_trace_mu);
+    hipEvent_t e = next_event();
+    if (!e) return;
+    if (hipEventRecord(e, s) != hipSuccess) return;
+    if (begin) {
+        g_recs.push_back(TraceRec{stage, e, nullptr});
+    } else {
+        for (size_t i = g_recs.size(); i-- > 0;)
+            if (g_recs[i].stage == stage && g_recs[i].b == nullptr) { g_recs[i].b = e; break; }
+    }
+}
 
 static emri_status fail(emri_status st, const char* msg)
 {
@@ -257,6 +296,65 @@ emri_status emri_loglike_dataset(const double* params, int64_t B, const void* ds
     if (B == 0) return EMRI_OK;
     if (!params || !ds || !lnL || !ws) return fail(EMRI_EINVAL, "null pointer argument");
     return loglike_chunks(cfg, params, B, ds, lnL, ws, ws_bytes, stream);
+}
+
+emri_status emri_model_batch(const double* params, int64_t B, const emri_cfg* cfg, void* mf,
+                             void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    Plan p;
+    const char* err;
+    emri_status st = make_plan(cfg, B, &p, &err);
+    if (st != EMRI_OK) return fail(st, err);
+    if (B == 0) return EMRI_OK;
+    if (!params || !mf || !ws) return fail(EMRI_EINVAL, "null pointer argument");
+    if (ws_bytes < p.total) return fail(EMRI_EWORKSPACE, "workspace smaller than emri_workspace_bytes(cfg, B)");
+    if ((st = run_waveforms(p, params, B, ws, (char*)ws + p.off_z, stream))) return st;
+    if ((st = check_launch(launch_twiddles(p, ws, stream), "twiddles"))) return st;
+    if ((st = check_launch(launch_fft(p, B, ws, stream), "fft"))) return st;
+    return check_launch(launch_model_unpack(p, B, ws, mf, stream), "unpack");
+}
+
+emri_status emri_noise_psd(int model, int64_t N, double dt, double* psd, hipStream_t stream)
+{
+    if (model != 0) return fail(EMRI_EUNSUPPORTED, "only noise model 0 (BC04 instrumental) exists");
+    if (N < 2 || (N & (N - 1)) || !(dt > 0.0) || !isfinite(dt))
+        return fail(EMRI_EINVAL, "N must be a power of two >= 2 and dt positive");
+    if (!psd) return fail(EMRI_EINVAL, "null pointer argument");
+    return check_launch(launch_noise_psd(N, dt, psd, stream), "noise psd");
+}
+
+emri_status emri_trace_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_trace_mu);
+    g_trace_on = on != 0;
+    return EMRI_OK;
+}
+
+int emri_trace_read(double* ms, int64_t* launches, int n)
+{
+    std::lock_guard<std::mutex> lk(g_trace_mu);
+    for (int i = 0; i < n && i < ST_COUNT; ++i) {
+        if (ms) ms[i] = 0.0;
+        if (launches) launches[i] = 0;
+    }
+    for (const TraceRec& r : g_recs) {
+        if (!r.b) continue;
+        if (hipEventSynchronize(r.b) != hipSuccess) continue;
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) continue;
+        if (r.stage < n) {
+            if (ms) ms[r.stage] += t;
+            if (launches) launches[r.stage] += 1;
+        }
+    }
+    g_recs.clear();
+    g_next_event = 0;
+    return ST_COUNT;
+}
+
+const char* emri_trace_stage_name(int i)
+{
+    return (i >= 0 && i < ST_COUNT) ? kStageNames[i] : "";
 }
 
 }  // extern "C"

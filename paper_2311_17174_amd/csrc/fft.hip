@@ -74,11 +74,13 @@ hipError_t launch_twiddles(const Plan& p, void* ws, hipStream_t s)
     const TwLayout t = tw_layout(p);
     char* b = (char*)ws + p.off_tw;
     const int64_t n = t.nA + t.nB + t.nlo + t.nhi;
+    trace_mark(ST_TWIDDLE, s, true);
     hipLaunchKernelGGL(k_twiddles, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, t.nA,
                        t.nB, t.nlo, t.nhi, p.N, p.s_lo, (double2*)(b + t.oA),
                        (double2*)(b + t.oB), (double2*)(b + t.olo), (double2*)(b + t.ohi),
                        (float2*)(b + t.fA), (float2*)(b + t.fB), (float2*)(b + t.flo),
                        (float2*)(b + t.fhi));
+    trace_mark(ST_TWIDDLE, s, false);
     return hipGetLastError();
 }
 
@@ -293,13 +295,17 @@ static hipError_t fft_typed(const Plan& p, int64_t B, const void* in, void* ws, 
                             160 * 1024);
         attr_done = true;
     }
+    trace_mark(ST_FFT_COLS, s, true);
     hipLaunchKernelGGL(k_fft_cols<R>, dim3((unsigned)(p.R1 / p.TA), (unsigned)B),
                        dim3((unsigned)(p.TA * LA / 8)), ldsA, s, (const T2*)(in ? in : z), z, p.N,
                        p.R1, LA, p.m2, p.TA, p.s_lo, tA, tlo, thi);
+    trace_mark(ST_FFT_COLS, s, false);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    trace_mark(ST_FFT_ROWS, s, true);
     hipLaunchKernelGGL(k_fft_rows<R>, dim3((unsigned)p.R2, (unsigned)B), dim3((unsigned)(LB / 8)),
                        ldsB, s, z, p.N, LB, p.m1, tB);
+    trace_mark(ST_FFT_ROWS, s, false);
     return hipGetLastError();
 }
 
@@ -316,10 +322,12 @@ hipError_t launch_fft(const Plan& p, int64_t B, void* ws, hipStream_t s)
     return launch_fft_from(p, B, nullptr, ws, s);
 }
 
-// unpack: transposed packed spectrum -> hf[B][2][N/2+1], scaled by dt
+// unpack: transposed packed spectrum -> hf[B][2][N/2+1], scaled by dt and,
+// when wc is given, by the propagation factor 1/(Xi d_L) exp(-2 pi i k phi)
 template <typename R>
 __global__ void k_unpack(const typename C2<R>::T* __restrict__ z, typename C2<R>::T* __restrict__ hf,
-                         int64_t N, int64_t R1, int64_t R2, double dt)
+                         int64_t N, int64_t R1, int64_t R2, double dt,
+                         const double* __restrict__ wc)
 {
     using T2 = typename C2<R>::T;
     const int64_t H = N / 2 + 1;
@@ -330,23 +338,80 @@ __global__ void k_unpack(const typename C2<R>::T* __restrict__ z, typename C2<R>
     const int64_t km = (N - k) & (N - 1);
     const T2 a = zw[(k % R2) * R1 + k / R2];
     const T2 b = zw[(km % R2) * R1 + km / R2];
-    const R h = (R)(0.5 * dt);
-    // X_I = (a + conj b)/2, X_II = (a - conj b)/(2i)
-    hf[(w * 2 + 0) * H + k] = T2{h * (a.x + b.x), h * (a.y - b.y)};
-    hf[(w * 2 + 1) * H + k] = T2{h * (a.y + b.y), -h * (a.x - b.x)};
+    double sr = 0.5 * dt, si = 0.0;
+    if (wc) {
+        const double* c = wc + w * WC;
+        if (c[WC_VALID] == 0.0) {
+            sr = 0.0;
+        } else {
+            sr *= c[WC_G];
+            if (c[WC_HASDT] != 0.0) {
+                // exp(-2 pi i frac(k phi)), product rounding kept by FMA
+                const double kk = (double)k, phi = c[WC_PHI];
+                const double pr = kk * phi;
+                double f = (pr - floor(pr)) + fma(kk, phi, -pr);
+                f -= floor(f);
+                double cs, sn;
+                sincospi(-2.0 * f, &sn, &cs);
+                si = sr * sn;
+                sr *= cs;
+            }
+        }
+    }
+    // X_I = (a + conj b)/2, X_II = (a - conj b)/(2i), times (sr + i si)
+    const double xr = (double)a.x + (double)b.x, xi = (double)a.y - (double)b.y;
+    const double yr = (double)a.y + (double)b.y, yi = -((double)a.x - (double)b.x);
+    hf[(w * 2 + 0) * H + k] = T2{(R)(sr * xr - si * xi), (R)(sr * xi + si * xr)};
+    hf[(w * 2 + 1) * H + k] = T2{(R)(sr * yr - si * yi), (R)(sr * yi + si * yr)};
+}
+
+static hipError_t unpack_any(const Plan& p, int64_t B, const void* ws, void* hf, bool model,
+                             hipStream_t s)
+{
+    const char* base = (const char*)ws;
+    const int64_t H = p.N / 2 + 1;
+    const double* wc = model ? (const double*)(base + p.off_wc) : nullptr;
+    dim3 grid((unsigned)((H + 255) / 256), (unsigned)B);
+    trace_mark(ST_UNPACK, s, true);
+    if (p.prec == EMRI_FP64)
+        hipLaunchKernelGGL(k_unpack<double>, grid, dim3(256), 0, s,
+                           (const double2*)(base + p.off_z), (double2*)hf, p.N, p.R1, p.R2, p.dt,
+                           wc);
+    else
+        hipLaunchKernelGGL(k_unpack<float>, grid, dim3(256), 0, s,
+                           (const float2*)(base + p.off_z), (float2*)hf, p.N, p.R1, p.R2, p.dt,
+                           wc);
+    trace_mark(ST_UNPACK, s, false);
+    return hipGetLastError();
 }
 
 hipError_t launch_unpack(const Plan& p, int64_t B, const void* ws, void* hf, hipStream_t s)
 {
-    const char* base = (const char*)ws;
-    const int64_t H = p.N / 2 + 1;
-    dim3 grid((unsigned)((H + 255) / 256), (unsigned)B);
-    if (p.prec == EMRI_FP64)
-        hipLaunchKernelGGL(k_unpack<double>, grid, dim3(256), 0, s,
-                           (const double2*)(base + p.off_z), (double2*)hf, p.N, p.R1, p.R2, p.dt);
-    else
-        hipLaunchKernelGGL(k_unpack<float>, grid, dim3(256), 0, s,
-                           (const float2*)(base + p.off_z), (float2*)hf, p.N, p.R1, p.R2, p.dt);
+    return unpack_any(p, B, ws, hf, false, s);
+}
+
+hipError_t launch_model_unpack(const Plan& p, int64_t B, const void* ws, void* mf, hipStream_t s)
+{
+    return unpack_any(p, B, ws, mf, true, s);
+}
+
+// one-sided LISA noise PSD (instrumental noise of Barack & Cutler 2004)
+__global__ void k_noise_psd(int64_t H, double df, double* __restrict__ psd)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= H) return;
+    const double f = (double)k * df;
+    const double f2 = f * f;
+    psd[k] = (k == 0) ? INFINITY : 9.18e-52 / (f2 * f2) + 1.59e-41 + 9.18e-38 * f2;
+}
+
+hipError_t launch_noise_psd(int64_t N, double dt, double* psd, hipStream_t s)
+{
+    const int64_t H = N / 2 + 1;
+    trace_mark(ST_PSD, s, true);
+    hipLaunchKernelGGL(k_noise_psd, dim3((unsigned)((H + 255) / 256)), dim3(256), 0, s, H,
+                       1.0 / ((double)N * dt), psd);
+    trace_mark(ST_PSD, s, false);
     return hipGetLastError();
 }
 

@@ -110,6 +110,17 @@ hipError_t launch_dataset(const Plan& p, const double* data, const double* psd, 
 hipError_t launch_likelihood(const Plan& p, int64_t B, const void* ds, void* ws, double* lnL,
                              hipStream_t s);
 
+hipError_t launch_model_unpack(const Plan& p, int64_t B, const void* ws, void* mf,
+                               hipStream_t s);  // unpack with 1/(Xi d_L) and delay
+hipError_t launch_noise_psd(int64_t N, double dt, double* psd, hipStream_t s);
+
+// ---- per-stage event tracing (see emri_trace_enable) ---------------------
+enum Stage {
+    ST_SETUP = 0, ST_TABLES, ST_SYNTH, ST_TWIDDLE, ST_FFT_COLS, ST_FFT_ROWS, ST_UNPACK,
+    ST_DATASET, ST_LIKE, ST_WALKER_SUM, ST_PSD, ST_COUNT
+};
+void trace_mark(int stage, hipStream_t s, bool begin);
+
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace emri

@@ -97,6 +97,7 @@ hipError_t launch_dataset(const Plan& p, const double* data, const double* psd, 
     const int64_t half = p.N / 2;
     const double df = 1.0 / ((double)p.N * p.dt);
     dim3 grid((unsigned)((half + 255) / 256));
+    trace_mark(ST_DATASET, s, true);
     if (p.prec == EMRI_FP64) {
         hipLaunchKernelGGL(k_dataset<false>, grid, dim3(256), 0, s, data, psd, p.N, p.R1, p.R2,
                            df, (void*)(b + p.ds_off_d), (void*)(b + p.ds_off_w));
@@ -108,6 +109,7 @@ hipError_t launch_dataset(const Plan& p, const double* data, const double* psd, 
         hipLaunchKernelGGL(k_data_norm, dim3(1), dim3(1024), 0, s, data, psd, p.N, df,
                            (double*)(b + p.ds_off_norm));
     }
+    trace_mark(ST_DATASET, s, false);
     return hipGetLastError();
 }
 
@@ -232,6 +234,7 @@ hipError_t launch_likelihood(const Plan& p, int64_t B, const void* ds, void* ws,
     const double* wc = (const double*)(base + p.off_wc);
     double* part = (double*)(base + p.off_part);
     dim3 grid((unsigned)p.R2, (unsigned)B);
+    trace_mark(ST_LIKE, s, true);
     if (p.prec == EMRI_FP64)
         hipLaunchKernelGGL(k_like<false>, grid, dim3(kLikeThreads), 0, s,
                            (const void*)(base + p.off_z), p.N, p.R1, p.R2, p.dt, wc,
@@ -240,11 +243,14 @@ hipError_t launch_likelihood(const Plan& p, int64_t B, const void* ds, void* ws,
         hipLaunchKernelGGL(k_like<true>, grid, dim3(kLikeThreads), 0, s,
                            (const void*)(base + p.off_z), p.N, p.R1, p.R2, p.dt, wc,
                            (const void*)(db + p.ds_off_d), (const void*)(db + p.ds_off_w), part);
+    trace_mark(ST_LIKE, s, false);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const double* norm = (p.prec == EMRI_FP64) ? nullptr : (const double*)(db + p.ds_off_norm);
+    trace_mark(ST_WALKER_SUM, s, true);
     hipLaunchKernelGGL(k_walker_sum, dim3((unsigned)B), dim3(256), 0, s, part, p.R2, wc, norm,
                        lnL);
+    trace_mark(ST_WALKER_SUM, s, false);
     return hipGetLastError();
 }
 

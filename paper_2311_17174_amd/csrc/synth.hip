@@ -36,13 +36,18 @@ __device__ inline void small_sincos(R d, R* s, R* c)
 }
 
 // cos 2x, sin 2x for x = atan2(y, x0); (1, 0) when undefined, that is when
-// x0^2 + y^2 < 1e-24 (only reached by degenerate geometry, where rounding
-// residues would otherwise pick an arbitrary angle)
+// x0^2 + y^2 is below a threshold (only reached by degenerate geometry, where
+// rounding residues would otherwise pick an arbitrary angle): 1e-24 in FP64,
+// 1e-10 in FP32, where the residues themselves reach ~1e-14
+template <typename R> struct Degenerate;
+template <> struct Degenerate<double> { static constexpr double v = 1e-24; };
+template <> struct Degenerate<float> { static constexpr float v = 1e-10f; };
+
 template <typename R>
 __device__ inline void double_angle(R x0, R y, R* c2, R* s2)
 {
     const R d = x0 * x0 + y * y;
-    if (d >= R(1e-24)) {
+    if (d >= Degenerate<R>::v) {
         const R id = R(1) / d;
         *c2 = (x0 * x0 - y * y) * id;
         *s2 = R(2) * x0 * y * id;
@@ -231,8 +236,11 @@ static hipError_t synth_dispatch(const Plan& p, int64_t B, const char* base, voi
 hipError_t launch_synth(const Plan& p, int64_t B, void* ws, void* out, hipStream_t s)
 {
     const char* base = (const char*)ws;
-    if (p.prec == EMRI_FP64) return synth_dispatch<double, double>(p, B, base, out, s);
-    return synth_dispatch<float, float>(p, B, base, out, s);
+    trace_mark(ST_SYNTH, s, true);
+    const hipError_t e = (p.prec == EMRI_FP64) ? synth_dispatch<double, double>(p, B, base, out, s)
+                                               : synth_dispatch<float, float>(p, B, base, out, s);
+    trace_mark(ST_SYNTH, s, false);
+    return e;
 }
 
 }  // namespace emri

@@ -356,9 +356,11 @@ hipError_t launch_walker_setup(const Plan& p, const double* params, int64_t B, v
     char* base = (char*)ws;
     const double h = p.dt * (double)p.L;
     dim3 grid((unsigned)((B + 63) / 64));
+    trace_mark(ST_SETUP, s, true);
     hipLaunchKernelGGL(k_walker_setup, grid, dim3(64), 0, s, params, B, p.K, h,
                        (double)p.N * p.dt, gl, (double*)(base + p.off_wc),
                        (double*)(base + p.off_orb));
+    trace_mark(ST_SETUP, s, false);
     return hipGetLastError();
 }
 
@@ -368,6 +370,7 @@ hipError_t launch_tables(const Plan& p, int64_t B, void* ws, hipStream_t s)
     const double h = p.dt * (double)p.L;
     const int64_t n = p.K * p.nh;
     dim3 grid((unsigned)((n + 255) / 256), (unsigned)B);
+    trace_mark(ST_TABLES, s, true);
     if (p.prec == EMRI_FP64)
         hipLaunchKernelGGL(k_tables<double>, grid, dim3(256), 0, s, p.K, p.nh, h,
                            (const double*)(base + p.off_wc), (const double*)(base + p.off_orb),
@@ -376,6 +379,7 @@ hipError_t launch_tables(const Plan& p, int64_t B, void* ws, hipStream_t s)
         hipLaunchKernelGGL(k_tables<float>, grid, dim3(256), 0, s, p.K, p.nh, h,
                            (const double*)(base + p.off_wc), (const double*)(base + p.off_orb),
                            (double*)(base + p.off_co), (float*)(base + p.off_ch));
+    trace_mark(ST_TABLES, s, false);
     return hipGetLastError();
 }
 

@@ -23,7 +23,9 @@ PRECISIONS = {"fp64": FP64, "mixed": MIXED}
 
 EXPORTED = ("emri_abi_version", "emri_last_error", "emri_workspace_bytes",
             "emri_waveform_batch", "emri_fft_batch", "emri_loglike_batch",
-            "emri_dataset_bytes", "emri_dataset_init", "emri_loglike_dataset")
+            "emri_dataset_bytes", "emri_dataset_init", "emri_loglike_dataset",
+            "emri_model_batch", "emri_noise_psd", "emri_trace_enable", "emri_trace_read",
+            "emri_trace_stage_name")
 
 
 class EmriError(RuntimeError):
@@ -78,6 +80,12 @@ def _load():
         "emri_loglike_batch": ([vp, i64, vp, vp, d, d, cp, vp, vp, sz, vp], ctypes.c_int),
         "emri_dataset_init": ([vp, vp, cp, vp, sz, vp], ctypes.c_int),
         "emri_loglike_dataset": ([vp, i64, vp, cp, vp, vp, sz, vp], ctypes.c_int),
+        "emri_model_batch": ([vp, i64, cp, vp, vp, sz, vp], ctypes.c_int),
+        "emri_noise_psd": ([ctypes.c_int, i64, d, vp, vp], ctypes.c_int),
+        "emri_trace_enable": ([ctypes.c_int], ctypes.c_int),
+        "emri_trace_read": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                             ctypes.c_int], ctypes.c_int),
+        "emri_trace_stage_name": ([ctypes.c_int], ctypes.c_char_p),
     }
     for name, (a, r) in sig.items():
         f = getattr(L, name)
@@ -215,3 +223,53 @@ def loglike_dataset(params: torch.Tensor, ds: torch.Tensor, cfg: Config,
     _check(lib.emri_loglike_dataset(pp, B, ds.data_ptr(), ctypes.byref(c), op, ws.data_ptr(),
                                     ws.numel(), _stream(stream)), "emri_loglike_dataset")
     return out
+
+
+def model_batch(params: torch.Tensor, cfg: Config, out: torch.Tensor | None = None,
+                ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """[B][2][N/2+1] complex propagated model exp(-2 pi i f DT) h~ / (Xi d_L)."""
+    B = params.shape[0]
+    pp = _dev(params, torch.float64, (B, NPAR), "params")
+    H = cfg.N // 2 + 1
+    if out is None:
+        out = torch.empty((B, 2, H, 2), dtype=cfg.real_dtype, device=params.device)
+    op = _dev(out, cfg.real_dtype, (B, 2, H, 2), "out")
+    if ws is None:
+        ws = alloc_workspace(cfg, B, params.device)
+    c = cfg.c()
+    _check(lib.emri_model_batch(pp, B, ctypes.byref(c), op, ws.data_ptr(), ws.numel(),
+                                _stream(stream)), "emri_model_batch")
+    return torch.view_as_complex(out)
+
+
+def noise_psd(N: int, dt: float, model: int = 0, device="cuda", stream=None) -> torch.Tensor:
+    out = torch.empty(N // 2 + 1, dtype=torch.float64, device=device)
+    _check(lib.emri_noise_psd(int(model), int(N), float(dt), out.data_ptr(), _stream(stream)),
+           "emri_noise_psd")
+    return out
+
+
+class Tracer:
+    """Per-stage HIP-event timing of the library's kernels (context manager)."""
+
+    def __init__(self):
+        n = 32
+        self._ms = (ctypes.c_double * n)()
+        self._cnt = (ctypes.c_int64 * n)()
+
+    def __enter__(self):
+        self.read()                      # drop anything recorded before
+        lib.emri_trace_enable(1)
+        return self
+
+    def __exit__(self, *exc):
+        lib.emri_trace_enable(0)
+
+    def read(self) -> dict:
+        """{stage: (total_ms, launches)} since the previous read (synchronises)."""
+        k = lib.emri_trace_read(self._ms, self._cnt, 32)
+        out = {}
+        for i in range(k):
+            if self._cnt[i]:
+                out[lib.emri_trace_stage_name(i).decode()] = (self._ms[i], int(self._cnt[i]))
+        return out

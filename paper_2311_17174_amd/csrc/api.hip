@@ -6,6 +6,7 @@
 
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <mutex>
@@ -108,17 +109,29 @@ emri_status make_plan(const emri_cfg* cfg, int64_t B, Plan* p, const char** err)
     q.cl = cfg->coarse_log2;
     q.L = (int64_t)1 << q.cl;
     q.K = (Nv + q.L - 1) / q.L;
-    // FFT split: rows (pass B, contiguous) up to 2^13, columns the rest
+    // FFT split: rows (pass B, contiguous, fused with the likelihood) up to
+    // 2^12 so a row transform has 512 lanes; columns the rest (up to 2^12)
     q.m1 = (m + 1) / 2 + 1;
-    if (q.m1 > 13) q.m1 = 13;
+    if (q.m1 > 12) q.m1 = 12;
     q.m2 = m - q.m1;
     q.R1 = (int64_t)1 << q.m1;
     q.R2 = (int64_t)1 << q.m2;
     q.esz = (q.prec == EMRI_FP64) ? 16 : 8;
     q.hsz = (q.prec == EMRI_FP64) ? 8 : 4;
-    int ta = (int)(64 / q.esz);
-    while (ta > 1 && ta * q.R2 / 8 > 1024) ta /= 2;
-    while (ta > 1 && (size_t)ta * (q.R2 + 1) * q.esz > 160 * 1024) ta /= 2;
+    // columns per pass-A workgroup: rows of ta * esz = 64 bytes by default
+    // (EMRI_FFT_TA_BYTES overrides, for tuning), within 1024 lanes and the
+    // 160 KiB of LDS a workgroup may hold
+    size_t run_bytes = 64;
+    if (const char* env = getenv("EMRI_FFT_TA_BYTES")) run_bytes = (size_t)atoi(env);
+    int ta = (int)(run_bytes / q.esz);
+    if (ta < 1) ta = 1;
+    while (ta > 16) ta /= 2;
+    auto lds_a = [&](int t) {   // ta padded columns (fft_lds.hpp), re and im
+        const int L = (int)q.R2;
+        const int pl = ((L + (L >> 4)) + 15) & ~15;
+        return (size_t)t * (pl + (t > 1 ? 16 / t : 0)) * q.esz;
+    };
+    while (ta > 1 && (ta * q.R2 / 8 > 1024 || lds_a(ta) > 160 * 1024)) ta /= 2;
     q.TA = ta;
     q.s_lo = (m + 1) / 2;
 
@@ -247,7 +260,7 @@ static emri_status loglike_chunks(const emri_cfg* cfg, const double* params, int
         if ((st = run_waveforms(p, params + w0 * EMRI_NPAR, nb, ws,
                                 (char*)ws + p.off_z, stream)))
             return st;
-        if ((st = check_launch(launch_fft(p, nb, ws, stream), "fft"))) return st;
+        if ((st = check_launch(launch_fft_cols(p, nb, ws, stream), "fft columns"))) return st;
         if ((st = check_launch(launch_likelihood(p, nb, ds, ws, lnL + w0, stream), "likelihood")))
             return st;
     }

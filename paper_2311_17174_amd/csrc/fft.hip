@@ -18,13 +18,9 @@
 // radix-2 stage for the remainder), L/8 lanes per transform, twiddles from a
 // table W_L^e.  All twiddle tables are computed on the device in FP64 with
 // sincospi and rounded to FP32 for the mixed path.
-#include "internal.hpp"
+#include "fft_lds.hpp"
 
 namespace emri {
-
-template <typename R> struct C2;
-template <> struct C2<double> { using T = double2; };
-template <> struct C2<float> { using T = float2; };
 
 TwLayout tw_layout(const Plan& p)
 {
@@ -84,130 +80,26 @@ hipError_t launch_twiddles(const Plan& p, void* ws, hipStream_t s)
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// small DFTs in registers, natural order out: b_q = sum_t a_t W_R^{t q}
-// ---------------------------------------------------------------------------
-template <typename R>
-__device__ inline void dft2(R& ar, R& ai, R& br, R& bi)
+// column stride (per re/im array) of a pass-A tile: a padded column, plus a
+// skew of 16/TA slots so the TA columns of one row fall in distinct banks
+__host__ __device__ inline int col_stride(int L, int TA)
 {
-    const R tr = ar - br, ti = ai - bi;
-    ar += br; ai += bi;
-    br = tr; bi = ti;
+    return padded_len(L) + (TA > 1 ? 16 / TA : 0);
 }
 
-template <typename R>
-__device__ inline void dft4(R* xr, R* xi)  // 4 values, in place
+// XCD-aware tile order: the hardware hands consecutive workgroups to the 8
+// XCDs in turn; remap so that each XCD receives a contiguous run of tiles
+// (adjacent column tiles share 128-byte lines and one XCD's L2).
+__device__ inline int64_t xcd_tile(int64_t bid, int64_t nb)
 {
-    const R t0r = xr[0] + xr[2], t0i = xi[0] + xi[2];
-    const R t1r = xr[0] - xr[2], t1i = xi[0] - xi[2];
-    const R t2r = xr[1] + xr[3], t2i = xi[1] + xi[3];
-    const R t3r = xi[1] - xi[3], t3i = xr[3] - xr[1];   // (a1 - a3) * (-i)
-    xr[0] = t0r + t2r; xi[0] = t0i + t2i;
-    xr[2] = t0r - t2r; xi[2] = t0i - t2i;
-    xr[1] = t1r + t3r; xi[1] = t1i + t3i;
-    xr[3] = t1r - t3r; xi[3] = t1i - t3i;
-}
-
-template <typename R>
-__device__ inline void dft8(R* xr, R* xi)
-{
-    R er[4] = {xr[0], xr[2], xr[4], xr[6]}, ei[4] = {xi[0], xi[2], xi[4], xi[6]};
-    R orr[4] = {xr[1], xr[3], xr[5], xr[7]}, oi[4] = {xi[1], xi[3], xi[5], xi[7]};
-    dft4(er, ei);
-    dft4(orr, oi);
-    const R h = (R)0.70710678118654752440084436210484903928;
-    // W_8^1 = (1 - i)/sqrt2, W_8^2 = -i, W_8^3 = -(1 + i)/sqrt2
-    R w1r = h * (orr[1] + oi[1]), w1i = h * (oi[1] - orr[1]);
-    R w2r = oi[2], w2i = -orr[2];
-    R w3r = h * (oi[3] - orr[3]), w3i = -h * (orr[3] + oi[3]);
-    xr[0] = er[0] + orr[0]; xi[0] = ei[0] + oi[0];
-    xr[4] = er[0] - orr[0]; xi[4] = ei[0] - oi[0];
-    xr[1] = er[1] + w1r; xi[1] = ei[1] + w1i;
-    xr[5] = er[1] - w1r; xi[5] = ei[1] - w1i;
-    xr[2] = er[2] + w2r; xi[2] = ei[2] + w2i;
-    xr[6] = er[2] - w2r; xi[6] = ei[2] - w2i;
-    xr[3] = er[3] + w3r; xi[3] = ei[3] + w3i;
-    xr[7] = er[3] - w3r; xi[7] = ei[3] - w3i;
-}
-
-template <typename R>
-__device__ inline void cmul(R& xr, R& xi, R wr, R wi)
-{
-    const R t = xr * wr - xi * wi;
-    xi = xr * wi + xi * wr;
-    xr = t;
-}
-
-// One Stockham stage of radix RR over an L-point column in LDS: lane t
-// handles 8/RR butterflies j = t + b L/8; Ns is the product of the radices
-// of the previous stages.
-template <typename R, int RR>
-__device__ inline void lds_stage(R* re, R* im, int L, int Ns, int t,
-                                 const typename C2<R>::T* __restrict__ tw)
-{
-    constexpr int NB = 8 / RR;
-    const int stride = L / RR;
-    const int tws = L / (Ns * RR);          // W_{Ns RR}^{r k} = W_L^{r k tws}
-    R vr[8], vi[8];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        const int j = t + b * (L / 8);
-        const int k = j & (Ns - 1);
-#pragma unroll
-        for (int r = 0; r < RR; ++r) {
-            R xr = re[j + r * stride], xi = im[j + r * stride];
-            if (r > 0 && k > 0) {
-                const typename C2<R>::T wv = tw[r * k * tws];
-                cmul(xr, xi, wv.x, wv.y);
-            }
-            vr[b * RR + r] = xr;
-            vi[b * RR + r] = xi;
-        }
-    }
-    __syncthreads();
-    if constexpr (RR == 8) {
-        dft8(vr, vi);
-    } else if constexpr (RR == 4) {
-        dft4(vr, vi);
-        dft4(vr + 4, vi + 4);
-    } else {
-#pragma unroll
-        for (int b = 0; b < 4; ++b) dft2(vr[2 * b], vi[2 * b], vr[2 * b + 1], vi[2 * b + 1]);
-    }
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        const int j = t + b * (L / 8);
-        const int k = j & (Ns - 1);
-        const int base = (j - k) * RR + k;
-#pragma unroll
-        for (int r = 0; r < RR; ++r) {
-            re[base + r * Ns] = vr[b * RR + r];
-            im[base + r * Ns] = vi[b * RR + r];
-        }
-    }
-    __syncthreads();
-}
-
-// L-point FFT (L = 2^lgL >= 8) of one column held in LDS (re/im arrays), by
-// lane t of L/8.  Every lane of the workgroup must call it (barriers).
-template <typename R>
-__device__ void lds_fft(R* re, R* im, int L, int lgL, int t,
-                        const typename C2<R>::T* __restrict__ tw)
-{
-    const int n8 = lgL / 3, rem = lgL - 3 * n8;
-    int Ns = 1;
-    for (int st = 0; st < n8; ++st) {
-        lds_stage<R, 8>(re, im, L, Ns, t, tw);
-        Ns *= 8;
-    }
-    if (rem == 2) lds_stage<R, 4>(re, im, L, Ns, t, tw);
-    else if (rem == 1) lds_stage<R, 2>(re, im, L, Ns, t, tw);
+    if (nb & 7) return bid;
+    return (bid & 7) * (nb >> 3) + (bid >> 3);
 }
 
 // pass A: TA columns of length L (= R2) per workgroup, TA * L / 8 lanes.
 // in and out may alias (the tile's read and write sets coincide).
-template <typename R>
-__global__ void __launch_bounds__(1024) k_fft_cols(const typename C2<R>::T* in,
+template <typename R, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_fft_cols(const typename C2<R>::T* in,
                                                    typename C2<R>::T* out, int64_t N, int64_t R1,
                                                    int L, int lgL, int TA, int s_lo,
                                                    const typename C2<R>::T* __restrict__ twL,
@@ -217,10 +109,10 @@ __global__ void __launch_bounds__(1024) k_fft_cols(const typename C2<R>::T* in,
     using T2 = typename C2<R>::T;
     extern __shared__ unsigned char smem_raw[];
     R* sre = (R*)smem_raw;
-    const int LP = L + 1;                   // padded column stride
+    const int LP = col_stride(L, TA);
     R* sim = sre + TA * LP;
     const int64_t w = blockIdx.y;
-    const int64_t c0 = (int64_t)blockIdx.x * TA;
+    const int64_t c0 = xcd_tile(blockIdx.x, gridDim.x) * TA;
     const T2* src = in + w * N;
     T2* dst = out + w * N;
     const int nt = blockDim.x;
@@ -230,8 +122,8 @@ __global__ void __launch_bounds__(1024) k_fft_cols(const typename C2<R>::T* in,
     for (int q = threadIdx.x; q < TA * L; q += nt) {
         const int cc = q & tmask, r = q >> tsh;
         const T2 v = src[c0 + cc + R1 * (int64_t)r];
-        sre[cc * LP + r] = v.x;
-        sim[cc * LP + r] = v.y;
+        sre[cc * LP + px(r)] = v.x;
+        sim[cc * LP + px(r)] = v.y;
     }
     __syncthreads();
     const int lanes = L / 8;
@@ -240,7 +132,7 @@ __global__ void __launch_bounds__(1024) k_fft_cols(const typename C2<R>::T* in,
     const int64_t lomask = ((int64_t)1 << s_lo) - 1;
     for (int q = threadIdx.x; q < TA * L; q += nt) {
         const int cc = q & tmask, k2 = q >> tsh;
-        R xr = sre[cc * LP + k2], xi = sim[cc * LP + k2];
+        R xr = sre[cc * LP + px(k2)], xi = sim[cc * LP + px(k2)];
         const int64_t e = (c0 + cc) * (int64_t)k2;      // < N
         const T2 a = thi[e >> s_lo], b = tlo[e & lomask];
         const R wr = a.x * b.x - a.y * b.y, wi = a.x * b.y + a.y * b.x;
@@ -250,29 +142,30 @@ __global__ void __launch_bounds__(1024) k_fft_cols(const typename C2<R>::T* in,
 }
 
 // pass B: one row of length L (= R1) per workgroup, L / 8 lanes, in place
-template <typename R>
-__global__ void __launch_bounds__(1024) k_fft_rows(typename C2<R>::T* z, int64_t N, int L,
+template <typename R, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_fft_rows(typename C2<R>::T* z, int64_t N, int L,
                                                    int lgL,
                                                    const typename C2<R>::T* __restrict__ twL)
 {
     using T2 = typename C2<R>::T;
     extern __shared__ unsigned char smem_raw[];
     R* sre = (R*)smem_raw;
-    R* sim = sre + L;
+    R* sim = sre + padded_len(L);
     const int64_t w = blockIdx.y;
     T2* row = z + w * N + (int64_t)blockIdx.x * L;
     for (int q = threadIdx.x; q < L; q += blockDim.x) {
         const T2 v = row[q];
-        sre[q] = v.x;
-        sim[q] = v.y;
+        sre[px(q)] = v.x;
+        sim[px(q)] = v.y;
     }
     __syncthreads();
     lds_fft<R>(sre, sim, L, lgL, threadIdx.x, twL);
-    for (int q = threadIdx.x; q < L; q += blockDim.x) row[q] = T2{sre[q], sim[q]};
+    for (int q = threadIdx.x; q < L; q += blockDim.x) row[q] = T2{sre[px(q)], sim[px(q)]};
 }
 
 template <typename R>
-static hipError_t fft_typed(const Plan& p, int64_t B, const void* in, void* ws, hipStream_t s)
+static hipError_t fft_typed(const Plan& p, int64_t B, const void* in, void* ws, bool rows,
+                           hipStream_t s)
 {
     using T2 = typename C2<R>::T;
     char* base = (char*)ws;
@@ -285,36 +178,44 @@ static hipError_t fft_typed(const Plan& p, int64_t B, const void* in, void* ws, 
     const T2* thi = (const T2*)(twb + (f64 ? t.ohi : t.fhi));
     T2* z = (T2*)(base + p.off_z);
     const int LA = (int)p.R2, LB = (int)p.R1;
-    const size_t ldsA = (size_t)p.TA * (LA + 1) * 2 * sizeof(R);
-    const size_t ldsB = (size_t)LB * 2 * sizeof(R);
-    static bool attr_done = false;
-    if (!attr_done) {
-        (void)hipFuncSetAttribute((const void*)k_fft_cols<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
-        (void)hipFuncSetAttribute((const void*)k_fft_rows<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
-        attr_done = true;
-    }
+    const size_t ldsA = (size_t)p.TA * col_stride(LA, p.TA) * 2 * sizeof(R);
+    const size_t ldsB = (size_t)padded_len(LB) * 2 * sizeof(R);
+    hipError_t ae = allow_lds((const void*)k_fft_cols<R, 512>, ldsA);
+    if (ae == hipSuccess) ae = allow_lds((const void*)k_fft_cols<R, 1024>, ldsA);
+    if (ae == hipSuccess && rows) ae = allow_lds((const void*)k_fft_rows<R, 512>, ldsB);
+    if (ae != hipSuccess) return ae;
+    const int ntA = p.TA * LA / 8, ntB = LB / 8;
+    if (ntA > 1024 || ntB > 512) return hipErrorInvalidValue;
+    const T2* src = (const T2*)(in ? in : z);
     trace_mark(ST_FFT_COLS, s, true);
-    hipLaunchKernelGGL(k_fft_cols<R>, dim3((unsigned)(p.R1 / p.TA), (unsigned)B),
-                       dim3((unsigned)(p.TA * LA / 8)), ldsA, s, (const T2*)(in ? in : z), z, p.N,
-                       p.R1, LA, p.m2, p.TA, p.s_lo, tA, tlo, thi);
+    if (ntA <= 512)
+        hipLaunchKernelGGL((k_fft_cols<R, 512>), dim3((unsigned)(p.R1 / p.TA), (unsigned)B),
+                           dim3((unsigned)ntA), ldsA, s, src, z, p.N, p.R1, LA, p.m2, p.TA,
+                           p.s_lo, tA, tlo, thi);
+    else
+        hipLaunchKernelGGL((k_fft_cols<R, 1024>), dim3((unsigned)(p.R1 / p.TA), (unsigned)B),
+                           dim3((unsigned)ntA), ldsA, s, src, z, p.N, p.R1, LA, p.m2, p.TA,
+                           p.s_lo, tA, tlo, thi);
     trace_mark(ST_FFT_COLS, s, false);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || !rows) return e;
     trace_mark(ST_FFT_ROWS, s, true);
-    hipLaunchKernelGGL(k_fft_rows<R>, dim3((unsigned)p.R2, (unsigned)B), dim3((unsigned)(LB / 8)),
+    hipLaunchKernelGGL((k_fft_rows<R, 512>), dim3((unsigned)p.R2, (unsigned)B), dim3((unsigned)ntB),
                        ldsB, s, z, p.N, LB, p.m1, tB);
     trace_mark(ST_FFT_ROWS, s, false);
     return hipGetLastError();
 }
 
-// FFT of the packed signal: input `in` (NULL: the workspace signal itself),
-// result in the workspace signal buffer, transposed order.
 hipError_t launch_fft_from(const Plan& p, int64_t B, const void* in, void* ws, hipStream_t s)
 {
-    if (p.prec == EMRI_FP64) return fft_typed<double>(p, B, in, ws, s);
-    return fft_typed<float>(p, B, in, ws, s);
+    if (p.prec == EMRI_FP64) return fft_typed<double>(p, B, in, ws, true, s);
+    return fft_typed<float>(p, B, in, ws, true, s);
+}
+
+hipError_t launch_fft_cols(const Plan& p, int64_t B, void* ws, hipStream_t s)
+{
+    if (p.prec == EMRI_FP64) return fft_typed<double>(p, B, nullptr, ws, false, s);
+    return fft_typed<float>(p, B, nullptr, ws, false, s);
 }
 
 hipError_t launch_fft(const Plan& p, int64_t B, void* ws, hipStream_t s)

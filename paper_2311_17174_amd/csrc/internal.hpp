@@ -13,7 +13,7 @@
 //           2 A J_n(ne) (4 coefficients each)
 //   z       [B][N] complex: packed signal h_I + i h_II; the FFT runs in
 //           place and leaves the spectrum in transposed order
-//   part    [B][R2] fp64 per-row partial sums of the likelihood
+//   part    [B][R2/2+1] fp64 per-row-pair partial sums of the likelihood
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -104,9 +104,12 @@ hipError_t launch_twiddles(const Plan& p, void* ws, hipStream_t s);
 hipError_t launch_fft(const Plan& p, int64_t B, void* ws, hipStream_t s);  // z -> z (transposed)
 // FFT reading `in` ([B][N] complex, NULL: the workspace signal), result in z
 hipError_t launch_fft_from(const Plan& p, int64_t B, const void* in, void* ws, hipStream_t s);
+// pass A only (column FFTs with the four-step twiddle), in place on z
+hipError_t launch_fft_cols(const Plan& p, int64_t B, void* ws, hipStream_t s);
 hipError_t launch_unpack(const Plan& p, int64_t B, const void* ws, void* hf, hipStream_t s);
 hipError_t launch_dataset(const Plan& p, const double* data, const double* psd, void* ds,
                           hipStream_t s);
+// fused pass B + inner product + per-walker sum; expects pass A done on z
 hipError_t launch_likelihood(const Plan& p, int64_t B, const void* ds, void* ws, double* lnL,
                              hipStream_t s);
 
@@ -122,5 +125,12 @@ enum Stage {
 void trace_mark(int stage, hipStream_t s, bool begin);
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// allow a kernel `bytes` of dynamic LDS (needed above 64 KiB)
+inline hipError_t allow_lds(const void* kernel, size_t bytes)
+{
+    if (bytes <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
 
 }  // namespace emri

@@ -16,14 +16,14 @@
 // compensation per lane, FP64 across lanes; lnL = -<d|d>/2 + <d|m> - <m|m>/2
 // with <d|d> formed once in FP64 from the FP64 data.
 //
-// One workgroup per (row k2, walker) writes one FP64 partial; a second
-// kernel sums each walker's partials in a fixed order (results do not depend
-// on how walkers are batched).
-#include "internal.hpp"
+// The row FFT of the second pass is fused here: one workgroup per (pair of
+// rows, tile of walkers) transforms both rows in LDS and consumes the bins
+// directly, so the spectrum is never written to HBM.  Each (pair, walker)
+// gives one FP64 partial; a second kernel sums each walker's partials in a
+// fixed order (results do not depend on how walkers are batched).
+#include "fft_lds.hpp"
 
 namespace emri {
-
-constexpr int kLikeThreads = 256;
 
 // ---------------------------------------------------------------------------
 // data set
@@ -127,85 +127,153 @@ __device__ inline void delay_rotation(int64_t k, double phi, double* c, double* 
     sincospi(-2.0 * f, s, c);
 }
 
-template <bool MIXED>
-__global__ void __launch_bounds__(kLikeThreads) k_like(const void* __restrict__ zv, int64_t N,
-                                                       int64_t R1, int64_t R2, double dt,
-                                                       const double* __restrict__ wc,
-                                                       const void* __restrict__ dsd,
-                                                       const void* __restrict__ dsw,
-                                                       double* __restrict__ part)
+// Fused pass B + inner product.  Workgroup (g, walker tile): rows g and
+// R2 - g of the column-transformed signal (rows 0 and R2/2 pair with
+// themselves), L = R1 points each, L/8 lanes.  For each walker of the tile:
+// row A is transformed in LDS and lane t keeps its 8 values (positions
+// p = t + i L/8) in registers; row B is transformed in the same LDS; then
+// lane t owns the bins (A, p) for p < L/2, paired with (B, L-1-p), and the
+// bins (B, L-1-p) for p >= L/2, paired with (A, p).  Data and weights of the
+// lane's bins are read once per walker (the tile's walkers hit the cache).
+// One FP64 partial per (g, walker).
+template <typename R, bool MIXED, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_rows_like(const typename C2<R>::T* __restrict__ z,
+                                                    int64_t N, int L, int lgL, int64_t R2,
+                                                    double dt, const double* __restrict__ wc,
+                                                    const void* __restrict__ dsd,
+                                                    const void* __restrict__ dsw,
+                                                    const typename C2<R>::T* __restrict__ twL,
+                                                    double* __restrict__ part, int64_t B, int WT)
 {
-    __shared__ double sh[kLikeThreads / 64];
-    const int64_t k2 = blockIdx.x, w = blockIdx.y;
-    const double* c = wc + w * WC;
-    if (c[WC_VALID] == 0.0) {
-        if (threadIdx.x == 0) part[w * R2 + k2] = 0.0;
-        return;
-    }
-    const double scale = c[WC_G] * dt;
-    const bool hasdt = c[WC_HASDT] != 0.0;
-    const double phi = c[WC_PHI];
-    const int64_t half = N / 2, hr = R1 / 2;
-    const int64_t prow = (k2 == 0) ? 0 : (R2 - k2);
-    double result;
-    if (!MIXED) {
-        const double2* z = (const double2*)zv + w * N;
-        const double2* D = (const double2*)dsd;
-        const double* W = (const double*)dsw;
-        double acc = 0.0;
-        for (int64_t k1 = threadIdx.x; k1 < hr; k1 += kLikeThreads) {
-            const int64_t b = k2 * hr + k1;
-            const double2 a = z[k2 * R1 + k1];
-            const int64_t pc = (k2 == 0) ? ((R1 - k1) & (R1 - 1)) : (R1 - 1 - k1);
-            const double2 bb = z[prow * R1 + pc];
-            double xr = 0.5 * (a.x + bb.x), xi = 0.5 * (a.y - bb.y);     // X_I
-            double yr = 0.5 * (a.y + bb.y), yi = -0.5 * (a.x - bb.x);    // X_II
-            if (hasdt) {
-                double cr, ci;
-                delay_rotation(k2 + R2 * k1, phi, &cr, &ci);
-                double t = xr * cr - xi * ci; xi = xr * ci + xi * cr; xr = t;
-                t = yr * cr - yi * ci; yi = yr * ci + yi * cr; yr = t;
-            }
-            const double2 d0 = D[b], d1 = D[half + b];
-            const double r0 = d0.x - scale * xr, i0 = d0.y - scale * xi;
-            const double r1 = d1.x - scale * yr, i1 = d1.y - scale * yi;
-            acc += W[b] * (r0 * r0 + i0 * i0 + r1 * r1 + i1 * i1);
+    using T2 = typename C2<R>::T;
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ double sh[16];
+    R* sre = (R*)smem_raw;
+    R* sim = sre + padded_len(L);
+    const int64_t g = blockIdx.x;
+    const int64_t nparts = R2 / 2 + 1;
+    const bool self = (g == 0) || (g == R2 / 2);
+    const int64_t rowA = g, rowB = self ? g : R2 - g;
+    const int t = threadIdx.x;
+    const int L8 = L / 8, hL = L / 2;
+    const int64_t half = N / 2;
+    const int nown = self ? 4 : 8;
+
+    // Lane t owns, for i < 4, the bin (A, p) with p = t + i L/8 < L/2, and for
+    // i >= 4 the bin (B, L-1-p); own_row/own_col give that bin, mirror() the
+    // position of the value it pairs with (in row B, or row A itself when the
+    // row pairs with itself).
+    auto own_row = [&](int i) -> int64_t { return i < 4 ? rowA : rowB; };
+    auto own_col = [&](int i) -> int { const int p = t + i * L8; return i < 4 ? p : L - 1 - p; };
+    auto mirror = [&](int i) -> int {
+        const int p = t + i * L8;
+        if (i >= 4) return L - 1 - p;        // the bin's own value in row B
+        if (self && g == 0) return (L - p) & (L - 1);
+        return L - 1 - p;
+    };
+    // data and weights (FP64: d, 4 df/S; mixed: whitened d, sqrt(4 df/S)) are
+    // read per walker: the tile's walkers share them through the cache
+    const T2* D = (const T2*)dsd;
+    const R* Wt = (const R*)dsw;
+
+    for (int wi = 0; wi < WT; ++wi) {
+        const int64_t w = (int64_t)blockIdx.y * WT + wi;
+        if (w >= B) break;
+        const double* c = wc + w * WC;
+        if (c[WC_VALID] == 0.0) {
+            if (t == 0) part[w * nparts + g] = 0.0;
+            continue;
         }
-        result = -0.5 * block_sum(acc, sh);
-    } else {
-        const float2* z = (const float2*)zv + w * N;
-        const float2* D = (const float2*)dsd;
-        const float* SW = (const float*)dsw;
-        float cr_s = 0.f, cr_c = 0.f, mm_s = 0.f, mm_c = 0.f;   // Kahan sums
-        const float fs = (float)scale;
-        for (int64_t k1 = threadIdx.x; k1 < hr; k1 += kLikeThreads) {
-            const int64_t b = k2 * hr + k1;
-            const float2 a = z[k2 * R1 + k1];
-            const int64_t pc = (k2 == 0) ? ((R1 - k1) & (R1 - 1)) : (R1 - 1 - k1);
-            const float2 bb = z[prow * R1 + pc];
-            float xr = 0.5f * (a.x + bb.x), xi = 0.5f * (a.y - bb.y);
-            float yr = 0.5f * (a.y + bb.y), yi = -0.5f * (a.x - bb.x);
-            if (hasdt) {
-                double cr, ci;
-                delay_rotation(k2 + R2 * k1, phi, &cr, &ci);
-                const float fr = (float)cr, fi = (float)ci;
-                float t = xr * fr - xi * fi; xi = xr * fi + xi * fr; xr = t;
-                t = yr * fr - yi * fi; yi = yr * fi + yi * fr; yr = t;
-            }
-            const float sc = fs * SW[b];
-            xr *= sc; xi *= sc; yr *= sc; yi *= sc;
-            const float2 d0 = D[b], d1 = D[half + b];
-            const float cross = d0.x * xr + d0.y * xi + d1.x * yr + d1.y * yi;
-            const float mm = xr * xr + xi * xi + yr * yr + yi * yi;
-            float y = cross - cr_c, t = cr_s + y;
-            cr_c = (t - cr_s) - y; cr_s = t;
-            y = mm - mm_c; t = mm_s + y;
-            mm_c = (t - mm_s) - y; mm_s = t;
+        const T2* zw = z + w * N;
+        // row A
+        for (int q = t; q < L; q += L8) {
+            const T2 v = zw[rowA * L + q];
+            sre[px(q)] = v.x;
+            sim[px(q)] = v.y;
         }
-        const double lane = ((double)cr_s - (double)cr_c) - 0.5 * ((double)mm_s - (double)mm_c);
-        result = block_sum(lane, sh);
+        __syncthreads();
+        lds_fft<R>(sre, sim, L, lgL, t, twL);
+        R ar[8], ai[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            ar[i] = sre[px(t + i * L8)];
+            ai[i] = sim[px(t + i * L8)];
+        }
+        if (!self) {
+            __syncthreads();
+            for (int q = t; q < L; q += L8) {
+                const T2 v = zw[rowB * L + q];
+                sre[px(q)] = v.x;
+                sim[px(q)] = v.y;
+            }
+            __syncthreads();
+            lds_fft<R>(sre, sim, L, lgL, t, twL);
+        }
+        const double scale = c[WC_G] * dt;
+        const bool hasdt = c[WC_HASDT] != 0.0;
+        const double phi = c[WC_PHI];
+        double lane_sum;
+        if (!MIXED) {
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                if (i >= nown) continue;
+                double zr, zi, mr, mi;            // bin value and its mirror
+                const int mp = px(mirror(i));
+                if (i < 4) { zr = ar[i]; zi = ai[i]; mr = sre[mp]; mi = sim[mp]; }
+                else { zr = sre[mp]; zi = sim[mp]; mr = ar[i]; mi = ai[i]; }
+                double xr = 0.5 * (zr + mr), xi = 0.5 * (zi - mi);     // X_I
+                double yr = 0.5 * (zi + mi), yi = -0.5 * (zr - mr);    // X_II
+                if (hasdt) {
+                    double cr, ci;
+                    delay_rotation(own_row(i) + R2 * own_col(i), phi, &cr, &ci);
+                    double u = xr * cr - xi * ci; xi = xr * ci + xi * cr; xr = u;
+                    u = yr * cr - yi * ci; yi = yr * ci + yi * cr; yr = u;
+                }
+                const int64_t b = own_row(i) * hL + own_col(i);
+                const T2 d0 = D[b], d1 = D[half + b];
+                const double r0 = d0.x - scale * xr, i0 = d0.y - scale * xi;
+                const double r1 = d1.x - scale * yr, i1 = d1.y - scale * yi;
+                acc += Wt[b] * (r0 * r0 + i0 * i0 + r1 * r1 + i1 * i1);
+            }
+            lane_sum = -0.5 * acc;
+        } else {
+            float cr_s = 0.f, cr_c = 0.f, mm_s = 0.f, mm_c = 0.f;   // Kahan sums
+            const float fs = (float)scale;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                if (i >= nown) continue;
+                float zr, zi, mr, mi;
+                const int mp = px(mirror(i));
+                if (i < 4) { zr = ar[i]; zi = ai[i]; mr = sre[mp]; mi = sim[mp]; }
+                else { zr = sre[mp]; zi = sim[mp]; mr = ar[i]; mi = ai[i]; }
+                float xr = 0.5f * (zr + mr), xi = 0.5f * (zi - mi);
+                float yr = 0.5f * (zi + mi), yi = -0.5f * (zr - mr);
+                if (hasdt) {
+                    double cr, ci;
+                    delay_rotation(own_row(i) + R2 * own_col(i), phi, &cr, &ci);
+                    const float fr = (float)cr, fi = (float)ci;
+                    float u = xr * fr - xi * fi; xi = xr * fi + xi * fr; xr = u;
+                    u = yr * fr - yi * fi; yi = yr * fi + yi * fr; yr = u;
+                }
+                const int64_t b = own_row(i) * hL + own_col(i);
+                const T2 d0 = D[b], d1 = D[half + b];
+                const float sc = fs * (float)Wt[b];
+                xr *= sc; xi *= sc; yr *= sc; yi *= sc;
+                const float cross = (float)d0.x * xr + (float)d0.y * xi +
+                                    (float)d1.x * yr + (float)d1.y * yi;
+                const float mm = xr * xr + xi * xi + yr * yr + yi * yi;
+                float y = cross - cr_c, u = cr_s + y;
+                cr_c = (u - cr_s) - y; cr_s = u;
+                y = mm - mm_c; u = mm_s + y;
+                mm_c = (u - mm_s) - y; mm_s = u;
+            }
+            lane_sum = ((double)cr_s - (double)cr_c) - 0.5 * ((double)mm_s - (double)mm_c);
+        }
+        const double s = block_sum(lane_sum, sh);
+        if (t == 0) part[w * nparts + g] = s;
+        // block_sum ends with a barrier: LDS may be overwritten by the next walker
     }
-    if (threadIdx.x == 0) part[w * R2 + k2] = result;
 }
 
 // lnL[w] = base + sum_k2 part[w][k2] (fixed order), -inf for invalid walkers
@@ -233,22 +301,36 @@ hipError_t launch_likelihood(const Plan& p, int64_t B, const void* ds, void* ws,
     const char* db = (const char*)ds;
     const double* wc = (const double*)(base + p.off_wc);
     double* part = (double*)(base + p.off_part);
-    dim3 grid((unsigned)p.R2, (unsigned)B);
+    const int L = (int)p.R1;
+    const int WT = (B >= 128) ? 8 : (B >= 16 ? 4 : 1);
+    const size_t lds = (size_t)padded_len(L) * 2 * (p.prec == EMRI_FP64 ? 8 : 4);
+    const int64_t nparts = p.R2 / 2 + 1;
+    dim3 grid((unsigned)nparts, (unsigned)((B + WT - 1) / WT));
+    const TwLayout tl = tw_layout(p);
+    const char* twb = base + p.off_tw;
+    hipError_t ae = (p.prec == EMRI_FP64)
+                        ? allow_lds((const void*)k_rows_like<double, false, 512>, lds)
+                        : allow_lds((const void*)k_rows_like<float, true, 512>, lds);
+    if (ae != hipSuccess) return ae;
+    if (L / 8 > 512) return hipErrorInvalidValue;   // rows are at most 2^12 points
+    const dim3 blk((unsigned)(L / 8));
+    const void* dsd = (const void*)(db + p.ds_off_d);
+    const void* dsw = (const void*)(db + p.ds_off_w);
     trace_mark(ST_LIKE, s, true);
     if (p.prec == EMRI_FP64)
-        hipLaunchKernelGGL(k_like<false>, grid, dim3(kLikeThreads), 0, s,
-                           (const void*)(base + p.off_z), p.N, p.R1, p.R2, p.dt, wc,
-                           (const void*)(db + p.ds_off_d), (const void*)(db + p.ds_off_w), part);
+        hipLaunchKernelGGL((k_rows_like<double, false, 512>), grid, blk, lds, s,
+                           (const double2*)(base + p.off_z), p.N, L, p.m1, p.R2, p.dt, wc, dsd,
+                           dsw, (const double2*)(twb + tl.oB), part, B, WT);
     else
-        hipLaunchKernelGGL(k_like<true>, grid, dim3(kLikeThreads), 0, s,
-                           (const void*)(base + p.off_z), p.N, p.R1, p.R2, p.dt, wc,
-                           (const void*)(db + p.ds_off_d), (const void*)(db + p.ds_off_w), part);
+        hipLaunchKernelGGL((k_rows_like<float, true, 512>), grid, blk, lds, s,
+                           (const float2*)(base + p.off_z), p.N, L, p.m1, p.R2, p.dt, wc, dsd,
+                           dsw, (const float2*)(twb + tl.fB), part, B, WT);
     trace_mark(ST_LIKE, s, false);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const double* norm = (p.prec == EMRI_FP64) ? nullptr : (const double*)(db + p.ds_off_norm);
     trace_mark(ST_WALKER_SUM, s, true);
-    hipLaunchKernelGGL(k_walker_sum, dim3((unsigned)B), dim3(256), 0, s, part, p.R2, wc, norm,
+    hipLaunchKernelGGL(k_walker_sum, dim3((unsigned)B), dim3(256), 0, s, part, nparts, wc, norm,
                        lnL);
     trace_mark(ST_WALKER_SUM, s, false);
     return hipGetLastError();

@@ -141,6 +141,7 @@ emri_status make_plan(const emri_cfg* cfg, int64_t B, Plan* p, const char** err)
     q.off_tw = o; o += align256(tl.bytes);
     q.off_wc = o; o += align256((size_t)B * WC * 8);
     q.off_orb = o; o += align256((size_t)B * (q.K + 1) * 10 * 8);
+    q.off_nv = o; o += align256((size_t)B * (q.K + 1) * q.nh * 6 * 8);
     q.off_co = o; o += align256((size_t)B * q.K * 16 * 8);
     q.off_ch = o; o += align256((size_t)B * q.K * q.nh * 12 * q.hsz);
     q.off_z = o; o += align256((size_t)B * q.N * q.esz);
@@ -152,6 +153,7 @@ emri_status make_plan(const emri_cfg* cfg, int64_t B, Plan* p, const char** err)
     q.ds_off_d = d; d += align256((size_t)2 * half * q.esz);
     q.ds_off_w = d; d += align256((size_t)half * (q.prec == EMRI_FP64 ? 8 : 4));
     q.ds_off_norm = d; d += 256;
+    q.ds_off_npart = d; d += align256((size_t)kNormParts * 8);
     q.ds_total = d;
     return EMRI_OK;
 }

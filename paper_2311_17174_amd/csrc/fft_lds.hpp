@@ -92,6 +92,7 @@ __device__ __forceinline__ void lds_stage(R* re, R* im, int L, int Ns, int t,
     const int stride = L / RR;
     const int tws = L / (Ns * RR);
     R vr[8], vi[8];
+    asm volatile("" ::: "memory");   // no hoisting of twiddle loads across stages
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int j = t + b * (L / 8);

@@ -6,6 +6,8 @@
 //   wc      [B][WC] fp64 walker constants (scalars + geometry), see WC_*
 //   orb     [B][K+1][10] fp64 orbit nodes: Y_k = (Phi, nu, gamma~, e, alpha)
 //           then dY/dt at t_k = k h
+//   nv      [B][K+1][n_harm][6] fp64 amplitude values and time derivatives
+//           at the orbit nodes
 //   co      [B][K][16] fp64 power-basis Hermite coefficients of Phi, nu,
 //           gamma~, alpha on each coarse interval (u = (t - t_k)/h in [0,1])
 //   ch      [B][K][n_harm][12] harmonic coefficients (fp64, or fp32 for the
@@ -47,6 +49,9 @@ enum {
     WC = 32
 };
 
+// partial sums of the data norm <d|d> (mixed path data set)
+constexpr int kNormParts = 256;
+
 // ---- physical constants (this library's own copy) -----------------------
 constexpr double kPi = 3.141592653589793238462643383279502884;
 constexpr double kSunSeconds = 4.925490947641267e-6;      // G Msun / c^3
@@ -78,9 +83,9 @@ struct Plan {
     size_t hsz;            // bytes per harmonic coefficient (8 or 4)
     // workspace (bytes, for B walkers)
     int64_t B;
-    size_t off_tw, off_wc, off_orb, off_co, off_ch, off_z, off_part, total;
+    size_t off_tw, off_wc, off_orb, off_nv, off_co, off_ch, off_z, off_part, total;
     // dataset buffer
-    size_t ds_off_d, ds_off_w, ds_off_norm, ds_total;
+    size_t ds_off_d, ds_off_w, ds_off_norm, ds_off_npart, ds_total;
 };
 
 // fills p; returns EMRI_OK or an error (message in err)

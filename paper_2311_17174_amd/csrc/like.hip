@@ -71,15 +71,17 @@ __device__ inline double block_sum(double v, double* sh)
     return r;  // valid in lane 0 of the block
 }
 
-// <d|d> in FP64 over bins 1..N/2-1 of both channels (one workgroup)
-__global__ void __launch_bounds__(1024) k_data_norm(const double* __restrict__ data,
-                                                    const double* __restrict__ psd, int64_t N,
-                                                    double df, double* __restrict__ out)
+// <d|d> in FP64 over bins 1..N/2-1 of both channels: kNormParts workgroups
+// write partials, one workgroup adds them in a fixed order
+__global__ void __launch_bounds__(256) k_data_norm_part(const double* __restrict__ data,
+                                                        const double* __restrict__ psd, int64_t N,
+                                                        double df, double* __restrict__ part)
 {
-    __shared__ double sh[16];
+    __shared__ double sh[4];
     const int64_t H = N / 2 + 1;
     double acc = 0.0;
-    for (int64_t k = 1 + threadIdx.x; k < N / 2; k += blockDim.x) {
+    for (int64_t k = 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < N / 2;
+         k += (int64_t)gridDim.x * blockDim.x) {
         const double S = psd[k];
         if (!(S > 0.0 && isfinite(S))) continue;
         const double d0r = data[2 * k], d0i = data[2 * k + 1];
@@ -87,6 +89,14 @@ __global__ void __launch_bounds__(1024) k_data_norm(const double* __restrict__ d
         acc += (4.0 * df / S) * (d0r * d0r + d0i * d0i + d1r * d1r + d1i * d1i);
     }
     const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) k_data_norm_sum(const double* __restrict__ part,
+                                                       double* __restrict__ out)
+{
+    __shared__ double sh[4];
+    const double s = block_sum(part[threadIdx.x], sh);
     if (threadIdx.x == 0) out[0] = s;
 }
 
@@ -106,8 +116,12 @@ hipError_t launch_dataset(const Plan& p, const double* data, const double* psd, 
                            (void*)(b + p.ds_off_d), (void*)(b + p.ds_off_w));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_data_norm, dim3(1), dim3(1024), 0, s, data, psd, p.N, df,
-                           (double*)(b + p.ds_off_norm));
+        hipLaunchKernelGGL(k_data_norm_part, dim3(kNormParts), dim3(256), 0, s, data, psd, p.N,
+                           df, (double*)(b + p.ds_off_npart));
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_data_norm_sum, dim3(1), dim3(kNormParts), 0, s,
+                           (const double*)(b + p.ds_off_npart), (double*)(b + p.ds_off_norm));
     }
     trace_mark(ST_DATASET, s, false);
     return hipGetLastError();
@@ -135,9 +149,12 @@ __device__ inline void delay_rotation(int64_t k, double phi, double* c, double* 
 // lane t owns the bins (A, p) for p < L/2, paired with (B, L-1-p), and the
 // bins (B, L-1-p) for p >= L/2, paired with (A, p).  Data and weights of the
 // lane's bins are read once per walker (the tile's walkers hit the cache).
-// One FP64 partial per (g, walker).
+// One FP64 partial per (g, walker).  Register budget 128 (4 waves per SIMD,
+// two workgroups per CU): occupancy matters more here than the few spills
+// it costs the FP64 variant.
 template <typename R, bool MIXED, int MAXT>
-__global__ void __launch_bounds__(MAXT) k_rows_like(const typename C2<R>::T* __restrict__ z,
+__global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(4)))
+k_rows_like(const typename C2<R>::T* __restrict__ z,
                                                     int64_t N, int L, int lgL, int64_t R2,
                                                     double dt, const double* __restrict__ wc,
                                                     const void* __restrict__ dsd,
@@ -154,7 +171,7 @@ __global__ void __launch_bounds__(MAXT) k_rows_like(const typename C2<R>::T* __r
     const int64_t nparts = R2 / 2 + 1;
     const bool self = (g == 0) || (g == R2 / 2);
     const int64_t rowA = g, rowB = self ? g : R2 - g;
-    const int t = threadIdx.x;
+    const int t0 = threadIdx.x;
     const int L8 = L / 8, hL = L / 2;
     const int64_t half = N / 2;
     const int nown = self ? 4 : 8;
@@ -163,6 +180,7 @@ __global__ void __launch_bounds__(MAXT) k_rows_like(const typename C2<R>::T* __r
     // i >= 4 the bin (B, L-1-p); own_row/own_col give that bin, mirror() the
     // position of the value it pairs with (in row B, or row A itself when the
     // row pairs with itself).
+    int t = t0;
     auto own_row = [&](int i) -> int64_t { return i < 4 ? rowA : rowB; };
     auto own_col = [&](int i) -> int { const int p = t + i * L8; return i < 4 ? p : L - 1 - p; };
     auto mirror = [&](int i) -> int {
@@ -179,6 +197,10 @@ __global__ void __launch_bounds__(MAXT) k_rows_like(const typename C2<R>::T* __r
     for (int wi = 0; wi < WT; ++wi) {
         const int64_t w = (int64_t)blockIdx.y * WT + wi;
         if (w >= B) break;
+        // opaque per iteration: keeps the per-bin index arithmetic inside the
+        // loop instead of holding it in registers across the transforms
+        t = t0;
+        asm volatile("" : "+v"(t));
         const double* c = wc + w * WC;
         if (c[WC_VALID] == 0.0) {
             if (t == 0) part[w * nparts + g] = 0.0;
@@ -235,6 +257,7 @@ __global__ void __launch_bounds__(MAXT) k_rows_like(const typename C2<R>::T* __r
                 const double r0 = d0.x - scale * xr, i0 = d0.y - scale * xi;
                 const double r1 = d1.x - scale * yr, i1 = d1.y - scale * yi;
                 acc += Wt[b] * (r0 * r0 + i0 * i0 + r1 * r1 + i1 * i1);
+                asm volatile("" ::: "memory");   // keep the bins' loads from piling up
             }
             lane_sum = -0.5 * acc;
         } else {
@@ -267,6 +290,7 @@ __global__ void __launch_bounds__(MAXT) k_rows_like(const typename C2<R>::T* __r
                 cr_c = (u - cr_s) - y; cr_s = u;
                 y = mm - mm_c; u = mm_s + y;
                 mm_c = (u - mm_s) - y; mm_s = u;
+                asm volatile("" ::: "memory");
             }
             lane_sum = ((double)cr_s - (double)cr_c) - 0.5 * ((double)mm_s - (double)mm_c);
         }

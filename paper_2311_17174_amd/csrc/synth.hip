@@ -1,10 +1,12 @@
 // synth.hip -- stage (b): time-domain AK waveform on the fine sampling grid.
 //
 // One workgroup of 256 lanes per (coarse interval k, walker w); each lane
-// produces SPT = 2^coarse_log2 / 256 samples j = k 2^cl + lane + 256 s, so a
-// wave's stores are 64 consecutive samples (coalesced).  Everything a wave
-// needs from the orbit and the amplitude tables is uniform over the interval
-// and is read with scalar loads.
+// produces SPT = 2^coarse_log2 / 256 consecutive samples j = k 2^cl +
+// lane SPT + s.  Everything a wave needs from the orbit and the amplitude
+// tables is uniform over the interval and is read with scalar loads.  When
+// the phases advance by less than 0.25 rad per sample (checked per interval
+// from the Hermite coefficients), a lane evaluates sin/cos once and rotates
+// by small-angle factors for its next samples.
 //
 // Per sample (Eq. (2) with the BC04 response; the oracle spells out the same
 // quantities with angles and atan2, here double angles come from the
@@ -26,36 +28,29 @@ template <typename R> struct V2;
 template <> struct V2<double> { using T = double2; };
 template <> struct V2<float> { using T = float2; };
 
-// sin/cos of a small angle d (|d| < 1e-2) by Taylor series to d^9
-template <typename R>
-__device__ inline void small_sincos(R d, R* s, R* c)
+// sin/cos of a small angle by Taylor series: |d| <= 0.3 gives full FP64
+// accuracy (the first omitted term is below 1e-19); the FP32 variant stops
+// at d^9 (below 1e-10 relative)
+__device__ __forceinline__ void small_sincos(double d, double* s, double* c)
 {
-    const R d2 = d * d;
-    *s = d * (R(1) - d2 * (R(1) / R(6) - d2 * (R(1) / R(120) - d2 * (R(1) / R(5040) - d2 * (R(1) / R(362880))))));
-    *c = R(1) - d2 * (R(0.5) - d2 * (R(1) / R(24) - d2 * (R(1) / R(720) - d2 * (R(1) / R(40320)))));
+    const double d2 = d * d;
+    *s = d * (1.0 - d2 * (1.0 / 6 - d2 * (1.0 / 120 - d2 * (1.0 / 5040 - d2 * (1.0 / 362880 -
+             d2 * (1.0 / 39916800 - d2 * (1.0 / 6227020800.0)))))));
+    *c = 1.0 - d2 * (0.5 - d2 * (1.0 / 24 - d2 * (1.0 / 720 - d2 * (1.0 / 40320 -
+             d2 * (1.0 / 3628800 - d2 * (1.0 / 479001600.0 - d2 * (1.0 / 87178291200.0)))))));
+}
+__device__ __forceinline__ void small_sincos(float d, float* s, float* c)
+{
+    const float d2 = d * d;
+    *s = d * (1.f - d2 * (1.f / 6 - d2 * (1.f / 120 - d2 * (1.f / 5040 - d2 * (1.f / 362880)))));
+    *c = 1.f - d2 * (0.5f - d2 * (1.f / 24 - d2 * (1.f / 720 - d2 * (1.f / 40320))));
 }
 
-// cos 2x, sin 2x for x = atan2(y, x0); (1, 0) when undefined, that is when
-// x0^2 + y^2 is below a threshold (only reached by degenerate geometry, where
-// rounding residues would otherwise pick an arbitrary angle): 1e-24 in FP64,
-// 1e-10 in FP32, where the residues themselves reach ~1e-14
+// degenerate-angle thresholds for the squared norm of a tangent pair: 1e-24 in
+// FP64, 1e-10 in FP32, where rounding residues themselves reach ~1e-14
 template <typename R> struct Degenerate;
 template <> struct Degenerate<double> { static constexpr double v = 1e-24; };
 template <> struct Degenerate<float> { static constexpr float v = 1e-10f; };
-
-template <typename R>
-__device__ inline void double_angle(R x0, R y, R* c2, R* s2)
-{
-    const R d = x0 * x0 + y * y;
-    if (d >= Degenerate<R>::v) {
-        const R id = R(1) / d;
-        *c2 = (x0 * x0 - y * y) * id;
-        *s2 = R(2) * x0 * y * id;
-    } else {
-        *c2 = R(1);
-        *s2 = R(0);
-    }
-}
 
 // sin/cos of an FP64 angle in precision R: FP64 uses the library sincos;
 // FP32 reduces the angle modulo 2 pi in FP64 first.
@@ -65,6 +60,27 @@ __device__ inline void angle_sincos(double a, float* s, float* c)
     double r = a * (0.5 / kPi);
     r -= rint(r);                      // r in [-1/2, 1/2]
     sincospif((float)(2.0 * r), s, c);
+}
+
+// e^{i a_s} for the SPT consecutive angles a_s of one lane: on a smooth
+// interval (every step |a_s - a_{s-1}| < 0.25 rad) one sincos, then
+// rotations by the small steps; otherwise one sincos per sample.
+template <typename R, int SPT>
+__device__ __forceinline__ void angle_run(const double (&a)[SPT], bool smooth, R (&c)[SPT],
+                                          R (&s)[SPT])
+{
+    angle_sincos(a[0], &s[0], &c[0]);
+#pragma unroll
+    for (int k = 1; k < SPT; ++k) {
+        if (smooth) {
+            R sd, cd;
+            small_sincos((R)(a[k] - a[k - 1]), &sd, &cd);
+            c[k] = c[k - 1] * cd - s[k - 1] * sd;
+            s[k] = s[k - 1] * cd + c[k - 1] * sd;
+        } else {
+            angle_sincos(a[k], &s[k], &c[k]);
+        }
+    }
 }
 
 template <typename R, typename HT, int SPT>
@@ -81,11 +97,12 @@ __global__ void __launch_bounds__(256) k_synth(int64_t K, int64_t Nv, int64_t N,
     const int lane = threadIdx.x;
     R2* zw = out + w * N;
     const int64_t j0 = k * L;
+    const int64_t jl = j0 + (int64_t)lane * SPT;      // this lane's first sample
     const double* c = wc + w * WC;
     const int64_t Kw = (int64_t)c[WC_KW];
     if (c[WC_VALID] == 0.0 || k >= Kw || j0 >= Nv) {
 #pragma unroll
-        for (int s = 0; s < SPT; ++s) zw[j0 + lane + 256 * s] = R2{R(0), R(0)};
+        for (int s = 0; s < SPT; ++s) zw[jl + s] = R2{R(0), R(0)};
         return;
     }
 
@@ -93,32 +110,37 @@ __global__ void __launch_bounds__(256) k_synth(int64_t K, int64_t Nv, int64_t N,
     const double* q = co + (w * K + k) * 16;
     const double dop = c[WC_DOP];
     const double cps = c[WC_CPS], sps = c[WC_SPS];
-    // detector azimuth at the start of the interval
-    double sb0, cb0;
+    double sb0, cb0;                                   // detector azimuth at j0
     sincospi(2.0 * (double)j0 * dt / kYearSeconds, &sb0, &cb0);
     const double dphi = 2.0 * kPi * dt / kYearSeconds;   // per sample
     const double invL = 1.0 / (double)L;
+    // largest per-sample step of Phi' (plus a Doppler margin), 2 gamma~, alpha
+    const double stepPhi = (fabs(q[1]) + 2.0 * fabs(q[2]) + 3.0 * fabs(q[3])) * invL + 1e-3;
+    const double stepG = 2.0 * (fabs(q[9]) + 2.0 * fabs(q[10]) + 3.0 * fabs(q[11])) * invL;
+    const double stepA = (fabs(q[13]) + 2.0 * fabs(q[14]) + 3.0 * fabs(q[15])) * invL;
+    const bool smooth = stepPhi < 0.25 && stepG < 0.25 && stepA < 0.25;
 
     // ---- per sample: phases ------------------------------------------------
     R u[SPT], cpb[SPT], spb[SPT];          // u, cos/sin of phibar
     R c1[SPT], s1[SPT];                     // e^{i Phi'}
+    double ph[SPT];
 #pragma unroll
     for (int s = 0; s < SPT; ++s) {
-        const int off = lane + 256 * s;
+        const int off = lane * SPT + s;
         const double ud = (double)off * invL;
         u[s] = (R)ud;
         const double Phi = ((q[3] * ud + q[2]) * ud + q[1]) * ud + q[0];
         const double nu = ((q[7] * ud + q[6]) * ud + q[5]) * ud + q[4];
         R sd, cd;
-        small_sincos<R>((R)(dphi * (double)off), &sd, &cd);
+        small_sincos((R)(dphi * (double)off), &sd, &cd);
         const R cb = (R)cb0 * cd - (R)sb0 * sd;
         const R sb = (R)sb0 * cd + (R)cb0 * sd;
         cpb[s] = cb;
         spb[s] = sb;
         const double cdel = (double)cb * cps + (double)sb * sps;   // cos(phibar - phi_S)
-        const double Phid = Phi + dop * nu * cdel;
-        angle_sincos(Phid, &s1[s], &c1[s]);
+        ph[s] = Phi + dop * nu * cdel;                              // Doppler-shifted phase
     }
+    angle_run<R, SPT>(ph, smooth, c1, s1);
 
     // ---- harmonic sum ------------------------------------------------------
     R Sa[SPT], Sb[SPT], Sc[SPT], cn[SPT], sn[SPT];
@@ -129,6 +151,7 @@ __global__ void __launch_bounds__(256) k_synth(int64_t K, int64_t Nv, int64_t N,
         sn[s] = s1[s];
     }
     const HT* hq = ch + (w * K + k) * (int64_t)nh * 12;
+#pragma unroll 2
     for (int n = 0; n < nh; ++n) {
         const HT* t = hq + 12 * n;
         const R a0 = (R)t[0], a1 = (R)t[1], a2 = (R)t[2], a3 = (R)t[3];
@@ -150,6 +173,17 @@ __global__ void __launch_bounds__(256) k_synth(int64_t K, int64_t Nv, int64_t N,
     }
 
     // ---- geometry, response, store -----------------------------------------
+    double gam2[SPT], alp[SPT];
+#pragma unroll
+    for (int s = 0; s < SPT; ++s) {
+        const double ud = (double)u[s];
+        gam2[s] = 2.0 * (((q[11] * ud + q[10]) * ud + q[9]) * ud + q[8]);
+        alp[s] = ((q[15] * ud + q[14]) * ud + q[13]) * ud + q[12];
+    }
+    R c2gv[SPT], s2gv[SPT], cav[SPT], sav[SPT];
+    angle_run<R, SPT>(gam2, smooth, c2gv, s2gv);
+    angle_run<R, SPT>(alp, smooth, cav, sav);
+
     const R Nx = (R)c[WC_NX], Ny = (R)c[WC_NY], Nz = (R)c[WC_NZ];
     const R Sx = (R)c[WC_SX], Sy = (R)c[WC_SY], Sz = (R)c[WC_SZ];
     const R E1x = (R)c[WC_E1X], E1y = (R)c[WC_E1Y], E1z = (R)c[WC_E1Z];
@@ -160,49 +194,56 @@ __global__ void __launch_bounds__(256) k_synth(int64_t K, int64_t Nv, int64_t N,
     // N x S, for sin(beta) = L . (N x S)
     const R NSx = Ny * Sz - Nz * Sy, NSy = Nz * Sx - Nx * Sz, NSz = Nx * Sy - Ny * Sx;
     const R h3 = (R)0.8660254037844386467637231707529362;  // sqrt(3)/2
+    const R thr = Degenerate<R>::v;
 #pragma unroll
     for (int s = 0; s < SPT; ++s) {
-        const int64_t j = j0 + lane + 256 * s;
+        const int64_t j = jl + s;
         if (j >= Nv) {
             zw[j] = R2{R(0), R(0)};
             continue;
         }
-        const double ud = (double)u[s];
-        const double gt = ((q[11] * ud + q[10]) * ud + q[9]) * ud + q[8];
-        const double al = ((q[15] * ud + q[14]) * ud + q[13]) * ud + q[12];
-        R sa, ca, s2g, c2g;
-        angle_sincos(al, &sa, &ca);
-        angle_sincos(2.0 * gt, &s2g, &c2g);
+        const R ca = cav[s], sa = sav[s];
         const R Lx = cl * Sx + sl * (ca * E1x + sa * E2x);
         const R Ly = cl * Sy + sl * (ca * E1y + sa * E2y);
         const R Lz = cl * Sz + sl * (ca * E1z);
         const R ci = Lx * Nx + Ly * Ny + Lz * Nz;
-        // beta: cos ~ N.S - c cos(lambda), sin ~ L.(N x S)
-        // (undefined, taken as 0, when L is parallel to S: sin(lambda) = 0)
-        R c2b = R(1), s2b = R(0);
-        if (sl != R(0)) double_angle<R>(NS - ci * cl, Lx * NSx + Ly * NSy + Lz * NSz, &c2b, &s2b);
-        const R c2 = c2g * c2b - s2g * s2b;     // cos 2 gamma
-        const R s2 = s2g * c2b + c2g * s2b;     // sin 2 gamma
-        const R ci2 = ci * ci;
-        const R hp = (R(1) + ci2) * (Sa[s] * c2 - Sb[s] * s2) + (R(1) - ci2) * Sc[s];
-        const R hx = R(-2) * ci * (Sb[s] * c2 + Sa[s] * s2);
-
-        // detector frame
+        // the three angles beta, phi_d - phibar and psi as tangent pairs
+        // (x, y) = (|.| cos, |.| sin); beta is undefined (0) when sin(lambda) = 0
+        const R bx = NS - ci * cl, by = Lx * NSx + Ly * NSy + Lz * NSz;
         const R cb = cpb[s], sb = spb[s];
         const R cdel = cb * Rcps + sb * Rsps;         // cos(phibar - phi_S)
         const R sdel = sb * Rcps - cb * Rsps;         // sin(phibar - phi_S)
         const R cthd = R(0.5) * cts - h3 * sts * cdel;
-        R c2d, s2d;
-        double_angle<R>(R(2) * sts * sdel, R(2) * h3 * cts + sts * cdel, &c2d, &s2d);
-        const R c2pb = cb * cb - sb * sb, s2pb = R(2) * sb * cb;
-        const R c2p = c2pb * c2d - s2pb * s2d;        // cos 2 phi_d
-        const R s2p = s2pb * c2d + c2pb * s2d;        // sin 2 phi_d
-        // polarisation angle psi: tan psi = (L.zd - c cos th_d) / (zd . (N x L))
+        const R dx = R(2) * sts * sdel, dy = R(2) * h3 * cts + sts * cdel;
         const R zx = -h3 * cb, zy = -h3 * sb, zz = R(0.5);
         const R Lzd = Lx * zx + Ly * zy + Lz * zz;
         const R NLx = Ny * Lz - Nz * Ly, NLy = Nz * Lx - Nx * Lz, NLz = Nx * Ly - Ny * Lx;
-        R c2s, s2s;
-        double_angle<R>(zx * NLx + zy * NLy + zz * NLz, Lzd - ci * cthd, &c2s, &s2s);
+        const R px_ = zx * NLx + zy * NLy + zz * NLz, py_ = Lzd - ci * cthd;
+        // one reciprocal for the three squared norms; a degenerate pair
+        // becomes (1, 0) (angle 0)
+        R nb = bx * bx + by * by, nd = dx * dx + dy * dy, np = px_ * px_ + py_ * py_;
+        const bool okb = (sl != R(0)) && nb >= thr, okd = nd >= thr, okp = np >= thr;
+        if (!okb) nb = R(1);
+        if (!okd) nd = R(1);
+        if (!okp) np = R(1);
+        const R inv = R(1) / (nb * nd * np);
+        const R ib = nd * np * inv, idd = nb * np * inv, ip = nb * nd * inv;
+        const R c2b = okb ? (bx * bx - by * by) * ib : R(1);
+        const R s2b = okb ? R(2) * bx * by * ib : R(0);
+        const R c2d = okd ? (dx * dx - dy * dy) * idd : R(1);
+        const R s2d = okd ? R(2) * dx * dy * idd : R(0);
+        const R c2s = okp ? (px_ * px_ - py_ * py_) * ip : R(1);
+        const R s2s = okp ? R(2) * px_ * py_ * ip : R(0);
+
+        const R c2g = c2gv[s], s2g = s2gv[s];
+        const R c2 = c2g * c2b - s2g * s2b;     // cos 2 gamma, gamma = gamma~ + beta
+        const R s2 = s2g * c2b + c2g * s2b;     // sin 2 gamma
+        const R ci2 = ci * ci;
+        const R hp = (R(1) + ci2) * (Sa[s] * c2 - Sb[s] * s2) + (R(1) - ci2) * Sc[s];
+        const R hx = R(-2) * ci * (Sb[s] * c2 + Sa[s] * s2);
+        const R c2pb = cb * cb - sb * sb, s2pb = R(2) * sb * cb;
+        const R c2p = c2pb * c2d - s2pb * s2d;        // cos 2 phi_d
+        const R s2p = s2pb * c2d + c2pb * s2d;        // sin 2 phi_d
         const R aa = R(0.5) * (R(1) + cthd * cthd);
         const R FpI = aa * c2p * c2s - cthd * s2p * s2s;
         const R FxI = aa * c2p * s2s + cthd * s2p * c2s;

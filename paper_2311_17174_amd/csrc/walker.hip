@@ -4,10 +4,12 @@
 //                   propagation delay, geometry constants, then the orbital
 //                   ODE of Eq. (1) by classical RK4 on the coarse grid, stopped
 //                   at the last node before the LSO (Sec. 3).
-//  k_tables         one lane per (walker, coarse interval, harmonic): Bessel
-//                   functions of the Peters-Mathews amplitudes at both ends of
-//                   the interval and their time derivatives, folded into cubic
-//                   Hermite polynomials in the interval coordinate u.
+//  k_nodes          one lane per (walker, orbit node, harmonic): Bessel
+//                   functions of the Peters-Mathews amplitudes and their time
+//                   derivatives at the node
+//  k_tables         one lane per (walker, coarse interval, harmonic): the
+//                   node values folded into cubic Hermite polynomials in the
+//                   interval coordinate u
 #include "internal.hpp"
 
 #include <math.h>
@@ -200,8 +202,11 @@ __device__ void bessel7(int n, double X, double J[7])
         return;
     }
     const int lo = n - 3 > 0 ? n - 3 : 0;
+    // start order: the relative error of the recurrence at the orders kept
+    // is ~(J_S / J_top)^2, negligible (< 1e-20 for X <= 64) for
+    // S = top + 10 + sqrt(40 top)
     const int top = max(n + 3, (int)ceil(X));
-    int S = top + 16 + (int)sqrt(200.0 * top);
+    int S = top + 10 + (int)sqrt(40.0 * top);
     S += S & 1;
     // window w[i] = J_{q+i} once order q has been produced
     double w0 = 1e-280, w1 = 0.0, w2 = 0.0, w3 = 0.0, w4 = 0.0, w5 = 0.0, w6 = 0.0;
@@ -269,10 +274,42 @@ __device__ inline void hermite_coeffs(double y0, double d0, double y1, double d1
     c[3] = 2.0 * (y0 - y1) + h * (d0 + d1);
 }
 
+// node values: for (walker, node k <= K_w, harmonic n) the three amplitudes
+// A n P_n, A n Q_n, 2 A J_n(ne) and their time derivatives, nv[w][k][n][6]
+__global__ void __launch_bounds__(256) k_nodes(int64_t K, int nh, const double* __restrict__ wc,
+                                               const double* __restrict__ orb,
+                                               double* __restrict__ nv)
+{
+    const int64_t w = blockIdx.y;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (K + 1) * nh) return;
+    const double* c = wc + w * WC;
+    if (c[WC_VALID] == 0.0) return;
+    const int64_t k = t / nh;
+    const int n = (int)(t - k * nh) + 1;
+    if (k > (int64_t)c[WC_KW]) return;
+    const double* o = orb + (w * (K + 1) + k) * 10;
+    const double Ms = c[WC_MS], mus = c[WC_MUS];
+    const double nu = o[1], e = o[3], dnu = o[6], de = o[8];
+    const double x13 = cbrt(2.0 * kPi * Ms * nu);
+    const double A = x13 * x13 * mus;
+    const double dA = (2.0 / 3.0) * A * dnu / nu;
+    double J[7];
+    bessel7(n, n * e, J);
+    const PM pm = pm_amplitudes(n, e, J);
+    double* q = nv + ((w * (K + 1) + k) * nh + (n - 1)) * 6;
+    q[0] = A * pm.a; q[1] = dA * pm.a + A * pm.da * de;
+    q[2] = A * pm.b; q[3] = dA * pm.b + A * pm.db * de;
+    q[4] = A * pm.c; q[5] = dA * pm.c + A * pm.dc * de;
+}
+
+// interval tables: for (walker, interval k < K_w, harmonic n) the power-basis
+// Hermite cubics of the three amplitudes, and (n = 1) of Phi, nu, gamma~, alpha
 template <typename HT>
 __global__ void __launch_bounds__(256) k_tables(int64_t K, int nh, double h,
                                                 const double* __restrict__ wc,
                                                 const double* __restrict__ orb,
+                                                const double* __restrict__ nv,
                                                 double* __restrict__ co, HT* __restrict__ ch)
 {
     const int64_t w = blockIdx.y;
@@ -282,13 +319,10 @@ __global__ void __launch_bounds__(256) k_tables(int64_t K, int nh, double h,
     if (c[WC_VALID] == 0.0) return;
     const int64_t k = t / nh;
     const int n = (int)(t - k * nh) + 1;
-    const int64_t Kw = (int64_t)c[WC_KW];
-    if (k >= Kw) return;
-    const double* o0 = orb + (w * (K + 1) + k) * 10;
-    const double* o1 = o0 + 10;
-    const double Ms = c[WC_MS], mus = c[WC_MUS];
-
+    if (k >= (int64_t)c[WC_KW]) return;
     if (n == 1) {  // orbital interpolants: Phi, nu, gamma~, alpha
+        const double* o0 = orb + (w * (K + 1) + k) * 10;
+        const double* o1 = o0 + 10;
         double* q = co + (w * K + k) * 16;
         const int comp[4] = {0, 1, 2, 4};
         for (int i = 0; i < 4; ++i) {
@@ -297,26 +331,12 @@ __global__ void __launch_bounds__(256) k_tables(int64_t K, int nh, double h,
             q[4 * i + 0] = cc[0]; q[4 * i + 1] = cc[1]; q[4 * i + 2] = cc[2]; q[4 * i + 3] = cc[3];
         }
     }
-
-    // A = (2 pi M nu)^{2/3} mu and the amplitudes at both nodes
-    double v[2][3], d[2][3];
-    for (int s = 0; s < 2; ++s) {
-        const double* o = s ? o1 : o0;
-        const double nu = o[1], e = o[3], dnu = o[6], de = o[8];
-        const double x13 = cbrt(2.0 * kPi * Ms * nu);
-        const double A = x13 * x13 * mus;
-        const double dA = (2.0 / 3.0) * A * dnu / nu;
-        double J[7];
-        bessel7(n, n * e, J);
-        const PM pm = pm_amplitudes(n, e, J);
-        v[s][0] = A * pm.a; d[s][0] = dA * pm.a + A * pm.da * de;
-        v[s][1] = A * pm.b; d[s][1] = dA * pm.b + A * pm.db * de;
-        v[s][2] = A * pm.c; d[s][2] = dA * pm.c + A * pm.dc * de;
-    }
+    const double* v0 = nv + ((w * (K + 1) + k) * nh + (n - 1)) * 6;
+    const double* v1 = v0 + (int64_t)nh * 6;            // node k + 1, same n
     HT* q = ch + ((w * K + k) * nh + (n - 1)) * 12;
     for (int i = 0; i < 3; ++i) {
         double cc[4];
-        hermite_coeffs(v[0][i], d[0][i], v[1][i], d[1][i], h, cc);
+        hermite_coeffs(v0[2 * i], v0[2 * i + 1], v1[2 * i], v1[2 * i + 1], h, cc);
         for (int j = 0; j < 4; ++j) q[4 * i + j] = (HT)cc[j];
     }
 }
@@ -368,16 +388,20 @@ hipError_t launch_tables(const Plan& p, int64_t B, void* ws, hipStream_t s)
 {
     char* base = (char*)ws;
     const double h = p.dt * (double)p.L;
+    const double* wc = (const double*)(base + p.off_wc);
+    const double* orb = (const double*)(base + p.off_orb);
+    double* nv = (double*)(base + p.off_nv);
+    trace_mark(ST_TABLES, s, true);
+    const int64_t nn = (p.K + 1) * p.nh;
+    hipLaunchKernelGGL(k_nodes, dim3((unsigned)((nn + 255) / 256), (unsigned)B), dim3(256), 0, s,
+                       p.K, p.nh, wc, orb, nv);
     const int64_t n = p.K * p.nh;
     dim3 grid((unsigned)((n + 255) / 256), (unsigned)B);
-    trace_mark(ST_TABLES, s, true);
     if (p.prec == EMRI_FP64)
-        hipLaunchKernelGGL(k_tables<double>, grid, dim3(256), 0, s, p.K, p.nh, h,
-                           (const double*)(base + p.off_wc), (const double*)(base + p.off_orb),
+        hipLaunchKernelGGL(k_tables<double>, grid, dim3(256), 0, s, p.K, p.nh, h, wc, orb, nv,
                            (double*)(base + p.off_co), (double*)(base + p.off_ch));
     else
-        hipLaunchKernelGGL(k_tables<float>, grid, dim3(256), 0, s, p.K, p.nh, h,
-                           (const double*)(base + p.off_wc), (const double*)(base + p.off_orb),
+        hipLaunchKernelGGL(k_tables<float>, grid, dim3(256), 0, s, p.K, p.nh, h, wc, orb, nv,
                            (double*)(base + p.off_co), (float*)(base + p.off_ch));
     trace_mark(ST_TABLES, s, false);
     return hipGetLastError();

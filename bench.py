@@ -53,6 +53,32 @@ def stage_work(stage: str, B: int, w, esz: int, valid_samples: int):
     return None, 0
 
 
+def profiled_traffic(stage: str):
+    """HBM bytes per launch of `stage` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size),
+    or None when the summary is missing or the kernel's sources have changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_B256_2p22_fp64.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    try:
+        block = text.split("```json", 1)[1].split("```", 1)[0]
+        rec = json.loads(block)["kernels"].get(stage)
+    except (IndexError, ValueError, KeyError):
+        return None
+    if not rec:
+        return None
+    files = {"synth": "synth.hip", "fft": "fft.hip", "fft_lds": "fft_lds.hpp", "like": "like.hip",
+             "walker": "walker.hip"}
+    for key, want in rec["source_sha256_16"].items():
+        src = os.path.join(ROOT, "paper_2311_17174_amd", "csrc", files[key])
+        if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != want:
+            return None
+    return rec["traffic_bytes"]
+
+
 def run_path(E, W, w, P, data, psd, steps, warmup):
     import torch
     cfg = E.Config.from_workload(w)
@@ -89,6 +115,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-walkers", type=int, default=0,
                     help="oracle sample size (default: one walker per host thread, <= 16)")
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (scale reference for "
+                         "HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for {args.gpus}); the "
@@ -99,6 +128,14 @@ def main():
     import torch
     from paper_2311_17174_amd import emri as E
     from paper_2311_17174_amd import workloads as W
+
+    if args.calibration_copy_mib:
+        n = args.calibration_copy_mib << 20
+        a = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     w64 = W.config2()
     wmx = W.config3()
@@ -158,11 +195,12 @@ def main():
     if kind == "byte":
         ach = amount / (dms * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None}
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": profiled_traffic(dom)}
     else:
         ach = amount / (dms * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": FP64_VECTOR_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_TFLOPS, "traffic": None}
+                "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_TFLOPS,
+                "traffic": profiled_traffic(dom)}
     roof["ms_per_launch"] = dms
 
     cpu = None

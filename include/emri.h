@@ -175,6 +175,57 @@ emri_status emri_trace_enable(int on);
 int emri_trace_read(double* ms, int64_t* launches, int n);
 const char* emri_trace_stage_name(int i);
 
+/* ---- serving loop ------------------------------------------------------
+ * A persistent request loop for many concurrent MCMC chains (the paper's
+ * vectorised walker matrix, Sec. 3, served to several chains at once).
+ * Requests of W walkers against a resident data set are packed with other
+ * pending requests of the same data set into batches (continuous batching:
+ * a request that arrives while others run joins the next batch that has a
+ * free stream and HBM), each batch is admitted only when its device block
+ * (parameters, results and workspace) fits in the caller's arena (admission
+ * by HBM footprint), and each batch runs as one hipGraph replay (captured
+ * once per device block and reused).  Batches run concurrently on several
+ * streams.  Per-walker results do not depend on how requests were batched. */
+typedef struct emri_server emri_server;
+
+typedef struct {
+    void* arena;          /* device memory owned by the caller: the HBM budget */
+    size_t arena_bytes;
+    int32_t n_streams;    /* batches in flight at once, 1..16 */
+    int32_t max_batch;    /* walkers per batch, multiple of 32, 32..4096;
+                             requests are at most this large */
+    int32_t use_graphs;   /* 1: launch batches as captured hipGraphs */
+    int32_t reserved;     /* must be 0 */
+} emri_server_cfg;
+
+typedef struct {
+    int64_t submitted, completed, rejected;
+    int64_t batches, graph_launches, graph_captures;
+    int64_t walkers, padded_walkers;  /* evaluated for requests / as padding */
+    size_t arena_in_use, arena_peak;
+} emri_server_stats;
+
+/* Starts the scheduler thread on the current device. */
+emri_status emri_server_create(const emri_server_cfg* cfg, emri_server** out);
+/* Finishes in-flight batches, fails pending requests, frees host resources. */
+emri_status emri_server_destroy(emri_server* s);
+/* Copies a data set (device data [2][N/2+1] complex fp64, psd [N/2+1]) into
+ * the arena in the likelihood's order; blocks until the copy is done. */
+emri_status emri_server_add_dataset(emri_server* s, const emri_cfg* cfg, const double* data,
+                                    const double* psd, int32_t* dataset_id);
+/* Queues W walkers: params is HOST memory [W][17], copied before the call
+ * returns; lnL is HOST memory [W], written when the request completes.
+ * EMRI_EWORKSPACE if the request could never fit in the arena. */
+emri_status emri_server_submit(emri_server* s, int32_t dataset_id, const double* params,
+                               int64_t W, double* lnL, uint64_t* ticket);
+/* Waits for a request (timeout_s < 0: forever).  On EMRI_OK lnL is written
+ * and *latency_s (if non-NULL) is the time from submit to completion; the
+ * ticket is then released.  EMRI_EINVAL for an unknown ticket; a timeout
+ * returns EMRI_EDEVICE with the request still queued. */
+emri_status emri_server_wait(emri_server* s, uint64_t ticket, double timeout_s,
+                             double* latency_s);
+emri_status emri_server_stats_get(emri_server* s, emri_server_stats* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -39,9 +39,13 @@ static hipEvent_t next_event()
     return g_events[g_next_event++];
 }
 
+static thread_local bool g_trace_suppress = false;
+
+void trace_suppress(bool on) { g_trace_suppress = on; }
+
 void trace_mark(int stage, hipStream_t s, bool begin)
 {
-    if (!g_trace_on) return;
+    if (!g_trace_on || g_trace_suppress) return;
     std::lock_guard<std::mutex> lk(g_trace_mu);
     hipEvent_t e = next_event();
     if (!e) return;
@@ -58,6 +62,23 @@ static emri_status fail(emri_status st, const char* msg)
 {
     g_err = msg ? msg : "";
     return st;
+}
+
+emri_status set_error(emri_status st, const char* msg) { return fail(st, msg); }
+
+static std::mutex g_lds_mu;
+static std::vector<std::pair<const void*, size_t>> g_lds_set;
+
+hipError_t allow_lds(const void* kernel, size_t bytes)
+{
+    if (bytes <= 64 * 1024) return hipSuccess;
+    std::lock_guard<std::mutex> lk(g_lds_mu);
+    for (auto& kv : g_lds_set)
+        if (kv.first == kernel && kv.second >= bytes) return hipSuccess;
+    const hipError_t e =
+        hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) g_lds_set.emplace_back(kernel, bytes);
+    return e;
 }
 
 static emri_status fail_hip(hipError_t e, const char* where)

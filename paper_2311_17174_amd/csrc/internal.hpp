@@ -131,11 +131,14 @@ void trace_mark(int stage, hipStream_t s, bool begin);
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// allow a kernel `bytes` of dynamic LDS (needed above 64 KiB)
-inline hipError_t allow_lds(const void* kernel, size_t bytes)
-{
-    if (bytes <= 64 * 1024) return hipSuccess;
-    return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
+// allow a kernel `bytes` of dynamic LDS (needed above 64 KiB); the attribute
+// is set once per kernel and size, so captured launch sequences make no
+// attribute calls after the first eager use
+hipError_t allow_lds(const void* kernel, size_t bytes);
+
+// record `msg` as the calling thread's last error and return `st`
+emri_status set_error(emri_status st, const char* msg);
+// while on, this thread's launches record no trace events (graph capture)
+void trace_suppress(bool on);
 
 }  // namespace emri

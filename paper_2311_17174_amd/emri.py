@@ -273,3 +273,105 @@ class Tracer:
             if self._cnt[i]:
                 out[lib.emri_trace_stage_name(i).decode()] = (self._ms[i], int(self._cnt[i]))
         return out
+
+
+# --------------------------------------------------------------------------
+# serving loop (emri_server_*)
+# --------------------------------------------------------------------------
+class _ServerCfg(ctypes.Structure):
+    _fields_ = [("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
+                ("n_streams", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("use_graphs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "rejected", "batches",
+                                              "graph_launches", "graph_captures", "walkers",
+                                              "padded_walkers")] + \
+               [("arena_in_use", ctypes.c_size_t), ("arena_peak", ctypes.c_size_t)]
+
+
+def _bind_server(L):
+    vp, i64, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64
+    sig = {
+        "emri_server_create": ([ctypes.POINTER(_ServerCfg), ctypes.POINTER(vp)], ctypes.c_int),
+        "emri_server_destroy": ([vp], ctypes.c_int),
+        "emri_server_add_dataset": ([vp, ctypes.POINTER(_Cfg), vp, vp,
+                                     ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+        "emri_server_submit": ([vp, ctypes.c_int32, vp, i64, vp, ctypes.POINTER(u64)],
+                               ctypes.c_int),
+        "emri_server_wait": ([vp, u64, ctypes.c_double, ctypes.POINTER(ctypes.c_double)],
+                             ctypes.c_int),
+        "emri_server_stats_get": ([vp, ctypes.POINTER(_ServerStats)], ctypes.c_int),
+    }
+    for name, (a, r) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = a
+        f.restype = r
+
+
+_bind_server(lib)
+EXPORTED = EXPORTED + ("emri_server_create", "emri_server_destroy", "emri_server_add_dataset",
+                       "emri_server_submit", "emri_server_wait", "emri_server_stats_get")
+
+
+class Server:
+    """Persistent likelihood server (continuous batching, HBM admission,
+    hipGraph launches).  The arena is a torch uint8 CUDA tensor that the
+    server sub-allocates; it must outlive the server."""
+
+    def __init__(self, arena: torch.Tensor, n_streams: int = 4, max_batch: int = 512,
+                 use_graphs: bool = True):
+        if not (arena.is_cuda and arena.dtype == torch.uint8):
+            raise TypeError("arena must be a CUDA uint8 tensor")
+        self._arena = arena
+        c = _ServerCfg(arena.data_ptr(), arena.numel(), n_streams, max_batch,
+                       1 if use_graphs else 0, 0)
+        h = ctypes.c_void_p()
+        _check(lib.emri_server_create(ctypes.byref(c), ctypes.byref(h)), "emri_server_create")
+        self._h = h
+        self._out = {}          # ticket -> host result array (kept alive until waited)
+
+    def add_dataset(self, data: torch.Tensor, psd: torch.Tensor, cfg: Config) -> int:
+        H = cfg.N // 2 + 1
+        dp = _dev(data, torch.float64, (2, H, 2), "data")
+        sp = _dev(psd, torch.float64, (H,), "psd")
+        torch.cuda.synchronize()
+        c = cfg.c()
+        i = ctypes.c_int32()
+        _check(lib.emri_server_add_dataset(self._h, ctypes.byref(c), dp, sp, ctypes.byref(i)),
+               "emri_server_add_dataset")
+        return i.value
+
+    def submit(self, dataset: int, params) -> int:
+        import numpy as np
+        P = np.ascontiguousarray(params, dtype=np.float64).reshape(-1, NPAR)
+        out = np.empty(P.shape[0], dtype=np.float64)
+        t = ctypes.c_uint64()
+        _check(lib.emri_server_submit(self._h, int(dataset), P.ctypes.data, P.shape[0],
+                                      out.ctypes.data, ctypes.byref(t)), "emri_server_submit")
+        self._out[t.value] = out
+        return t.value
+
+    def wait(self, ticket: int, timeout: float = -1.0):
+        """(lnL[W] numpy array, latency in seconds)."""
+        lat = ctypes.c_double()
+        _check(lib.emri_server_wait(self._h, ticket, float(timeout), ctypes.byref(lat)),
+               "emri_server_wait")
+        return self._out.pop(ticket), lat.value
+
+    def stats(self) -> dict:
+        s = _ServerStats()
+        _check(lib.emri_server_stats_get(self._h, ctypes.byref(s)), "emri_server_stats_get")
+        return {n: getattr(s, n) for n, _ in s._fields_}
+
+    def close(self):
+        if self._h:
+            _check(lib.emri_server_destroy(self._h), "emri_server_destroy")
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

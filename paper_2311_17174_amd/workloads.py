@@ -122,3 +122,47 @@ def gaussian_draws(N: int, seed: int) -> np.ndarray:
 def frequencies(N: int, dt: float) -> np.ndarray:
     """f_k = k / (N dt), k = 0..N/2."""
     return np.arange(N // 2 + 1, dtype=np.float64) / (N * dt)
+
+
+# ---------------------------------------------------------------------------
+# serving workload: several concurrent chains issuing likelihood requests
+# ---------------------------------------------------------------------------
+SERVING_T_OBS_YR = (0.5, 1.0, 2.0)          # 2^21, 2^22, 2^23 samples at 10 s
+
+
+def serving_chains(n_chains: int = 8):
+    """Injection row of each chain c, drawn from PCG64(100 + c): e0 ~ U[0.05,
+    0.5], a ~ U[0, 0.9], log10 M ~ U[log10 3e5, log10 3e6], mu = 10, the other
+    entries as config 1 (GR).  nu0 is the fraction 0.5 of the LSO frequency
+    nu_LSO(e0) = ((1 - e0^2)/(6 + 2 e0))^{3/2} / (2 pi G M / c^3) -- an input
+    choice for this workload (the same expression the validity check uses),
+    not part of the likelihood."""
+    tsun = 4.925490947641267e-6
+    rows = []
+    for c in range(n_chains):
+        r = np.random.Generator(np.random.PCG64(100 + c))
+        e0 = r.uniform(0.05, 0.5)
+        a = r.uniform(0.0, 0.9)
+        M = 10.0 ** r.uniform(np.log10(3e5), np.log10(3e6))
+        nu_lso = ((1 - e0 * e0) / (6 + 2 * e0)) ** 1.5 / (2 * np.pi * M * tsun)
+        rows.append(injection(M=M, mu=10.0, a=a, e0=e0, nu0=0.5 * nu_lso))
+    return np.array(rows)
+
+
+def serving_workload(chain_inj: np.ndarray, t_index: int, precision: str = "mixed") -> Workload:
+    T = SERVING_T_OBS_YR[t_index] * YEAR
+    N = 1 << (21 + t_index)
+    return Workload(f"serve_T{SERVING_T_OBS_YR[t_index]}yr", 0, T, 10.0, N, 30, 10, precision,
+                    chain_inj)
+
+
+def serving_requests(n: int, n_chains: int = 8, seed: int = 4, w_min: int = 16,
+                     w_max: int = 512):
+    """Request schedule: (gap in units of the mean inter-arrival time, chain,
+    T_obs index, walkers W, walker seed = request id); Poisson arrivals."""
+    r = np.random.Generator(np.random.PCG64(seed))
+    gaps = r.exponential(1.0, n)
+    chains = r.integers(0, n_chains, n)
+    tidx = r.integers(0, len(SERVING_T_OBS_YR), n)
+    Ws = r.integers(w_min, w_max + 1, n)
+    return [(float(gaps[i]), int(chains[i]), int(tidx[i]), int(Ws[i]), i) for i in range(n)]

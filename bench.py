@@ -9,6 +9,10 @@ HBM).  The workload is 256 walkers around the 1-yr injection, 2^22 samples,
 reported beside it.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2]
+
+The JSON line also carries the serving loop (mixed precision, 8 chains with
+resident data at 0.5/1/2 yr, Poisson arrivals at 0.8x the saturated rate):
+request latency p50/p99 and served lnL evals/s.
 """
 from __future__ import annotations
 
@@ -106,6 +110,100 @@ def run_path(E, W, w, P, data, psd, steps, warmup):
     return (t1 - t0), stages, np.array(lat), out.cpu().numpy()
 
 
+def run_serving(E, W, n_burst: int, n_requests: int, arena_gib: float, n_streams: int,
+                max_batch: int):
+    """Serving loop (mixed precision): 8 chains x 3 observation times of
+    resident data, Poisson request arrivals at 0.8x the saturated rate
+    measured first with a burst; returns the report dict."""
+    import threading
+    import queue
+    import torch
+    chains = W.serving_chains()
+    arena = torch.empty(int(arena_gib * (1 << 30)), dtype=torch.uint8, device="cuda")
+    srv = E.Server(arena, n_streams=n_streams, max_batch=max_batch, use_graphs=True)
+    ids = {}
+    for c in range(len(chains)):
+        for t in range(len(W.SERVING_T_OBS_YR)):
+            w = W.serving_workload(chains[c], t)
+            cfg = E.Config.from_workload(w)
+            psd = E.noise_psd(w.N, w.dt)
+            m = E.model_batch(torch.from_numpy(chains[c][None]).cuda(), cfg)[0]
+            g = torch.from_numpy(W.gaussian_draws(w.N, 1000 + 10 * c + t)).cuda()
+            sig = torch.sqrt(psd * (w.N * w.dt / 4.0))
+            sig[0] = 0.0
+            sig[-1] = 0.0
+            data = (torch.view_as_real(m).double() + sig[None, :, None] * g).contiguous()
+            ids[(c, t)] = (srv.add_dataset(data, psd, cfg), w, data, psd, cfg)
+            del m, g, sig
+    torch.cuda.synchronize()
+
+    def params_of(req):
+        gap, c, t, Wn, seed = req
+        return W.walkers(ids[(c, t)][1], B=Wn, seed=seed)
+
+    reqs = W.serving_requests(n_burst + n_requests)
+    burst, timed = reqs[:n_burst], reqs[n_burst:]
+    # saturated throughput: everything submitted at once
+    t0 = time.perf_counter()
+    tk = [srv.submit(ids[(r[1], r[2])][0], params_of(r)) for r in burst]
+    for t in tk:
+        srv.wait(t)
+    mu = n_burst / (time.perf_counter() - t0)
+    lam = 0.8 * mu
+    # open-loop Poisson arrivals at lam
+    arrivals = np.cumsum([r[0] for r in timed]) / lam
+    pre = [params_of(r) for r in timed]
+    q = queue.Queue()
+    lat = np.zeros(len(timed))
+    served = {}
+    sample = set(range(0, len(timed), max(1, len(timed) // 8)))
+
+    def collect():
+        for k in range(len(timed)):
+            i, t = q.get()
+            out, lat[i] = srv.wait(t)
+            if i in sample:
+                served[i] = out.copy()
+
+    th = threading.Thread(target=collect)
+    th.start()
+    start = time.perf_counter()
+    for i, r in enumerate(timed):
+        dtw = arrivals[i] - (time.perf_counter() - start)
+        if dtw > 0:
+            time.sleep(dtw)
+        q.put((i, srv.submit(ids[(r[1], r[2])][0], pre[i])))
+    th.join()
+    span = time.perf_counter() - start
+    st = srv.stats()
+    srv.close()
+    # the same walkers alone (eager emri_loglike_dataset) must give the same bits
+    same = True
+    for i, out in served.items():
+        r = timed[i]
+        _, w, data, psd, cfg = ids[(r[1], r[2])]
+        ds = E.dataset_init(data, psd, cfg)
+        alone = E.loglike_dataset(torch.from_numpy(pre[i]).cuda(), ds, cfg).cpu().numpy()
+        same = same and bool(np.array_equal(alone, out))
+    walkers = sum(r[3] for r in timed)
+    del arena
+    torch.cuda.empty_cache()
+    return {
+        "precision": "mixed", "chains": len(chains), "datasets": len(ids),
+        "requests": len(timed), "burst_requests": n_burst,
+        "saturated_requests_per_s": mu, "arrival_rate_per_s": lam,
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                       "p99": float(np.percentile(lat, 99) * 1e3),
+                       "mean": float(lat.mean() * 1e3)},
+        "evals_per_s": walkers / span, "mean_walkers_per_request": walkers / len(timed),
+        "alone_vs_mix_bitwise": same, "checked_requests": len(served),
+        "batches": st["batches"], "graph_launches": st["graph_launches"],
+        "graph_captures": st["graph_captures"], "padded_walkers": st["padded_walkers"],
+        "arena_gib": arena_gib, "arena_peak_gib": st["arena_peak"] / 2 ** 30,
+        "n_streams": n_streams, "max_batch": max_batch,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +213,11 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-walkers", type=int, default=0,
                     help="oracle sample size (default: one walker per host thread, <= 16)")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=300,
+                    help="timed serving requests (the full serving workload is 10000)")
+    ap.add_argument("--serve-burst", type=int, default=60)
+    ap.add_argument("--serve-arena-gib", type=float, default=160.0)
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (scale reference for "
                          "HBM byte counters)")
@@ -177,6 +280,16 @@ def main():
         }
         print(f"[bench] mixed: {mixed['value']:.1f} evals/s", file=sys.stderr, flush=True)
 
+    serving = None
+    if not args.no_serving:
+        torch.cuda.empty_cache()
+        print("[bench] serving loop", file=sys.stderr, flush=True)
+        serving = run_serving(E, W, args.serve_burst, args.serve_requests,
+                              args.serve_arena_gib, 4, 512)
+        print(f"[bench] serving: {serving['evals_per_s']:.1f} evals/s, p50 "
+              f"{serving['latency_ms']['p50']:.1f} ms, p99 {serving['latency_ms']['p99']:.1f} ms",
+              file=sys.stderr, flush=True)
+
     # roofline of the dominant kernel of the value path
     valid = w64.B * w64.n_valid
     dom = max(st64.items(), key=lambda kv: kv[1][0])[0]
@@ -236,6 +349,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "mixed": mixed,
+        "serving": serving,
         "stages": stages_out,
     }
     print(json.dumps(rec), flush=True)

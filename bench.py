@@ -294,17 +294,22 @@ def main():
     valid = w64.B * w64.n_valid
     dom = max(st64.items(), key=lambda kv: kv[1][0])[0]
     stages_out = {}
+    # work per step divided over the stage's launches per step (the batch call
+    # may split a stage into several launches); achieved = work / time summed
+    # over the stage's launches
     for name, (ms, launches) in st64.items():
         kind, amount = stage_work(name, w64.B, w64, 16, valid)
         per = ms / launches
-        ent = {"ms_per_launch": per, "launches_per_step": launches / args.steps}
+        lps = launches / args.steps
+        ent = {"ms_per_launch": per, "launches_per_step": lps}
         if kind == "flop":
-            ent["achieved_tflops"] = amount / (per * 1e-3) / 1e12
+            ent["achieved_tflops"] = amount / lps / (per * 1e-3) / 1e12
         elif kind == "byte":
-            ent["achieved_gbs"] = amount / (per * 1e-3) / 1e9
+            ent["achieved_gbs"] = amount / lps / (per * 1e-3) / 1e9
         stages_out[name] = ent
     kind, amount = stage_work(dom, w64.B, w64, 16, valid)
     dms = st64[dom][0] / st64[dom][1]
+    amount = amount / (st64[dom][1] / args.steps)          # per launch
     if kind == "byte":
         ach = amount / (dms * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
@@ -315,6 +320,7 @@ def main():
                 "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_TFLOPS,
                 "traffic": profiled_traffic(dom)}
     roof["ms_per_launch"] = dms
+    roof["launches_per_step"] = st64[dom][1] / args.steps
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -42,6 +42,8 @@
 #include <string.h>
 #ifdef _OPENMP
 #include <omp.h>
+#else
+static int omp_in_parallel(void) { return 1; }
 #endif
 
 /* ---- parameter row layout (17 doubles per walker) ---------------------- */
@@ -85,6 +87,8 @@ typedef struct {
     int32_t lo_only;     /* test hook: leading-order (Peters-Mathews) ODE    */
     int32_t pad;
 } oracle_cfg;
+
+int oracle_num_threads(void);
 
 static int64_t n_valid_of(const oracle_cfg *c) { return (int64_t)llround(c->T_obs / c->dt); }
 static int64_t n_intervals_of(const oracle_cfg *c)
@@ -450,9 +454,14 @@ static void walker_waveform(const double *p, const oracle_cfg *c, const double *
     double R = O_AU / O_CLIGHT; /* 1 AU in light seconds */
     double s3 = sqrt(3.0);
 
-    double *J = (double *)malloc((size_t)(nh + 3) * sizeof(double));
     int64_t jend = Kw * m;
     if (jend > Nv) jend = Nv;
+    /* samples are independent: spread them over threads unless this walker
+     * already runs inside a walker-parallel region */
+#pragma omp parallel if (!omp_in_parallel())
+    {
+    double *J = (double *)malloc((size_t)(nh + 3) * sizeof(double));
+#pragma omp for schedule(static)
     for (int64_t j = 0; j < jend; ++j) {
         int64_t k = j / m;
         double u = (double)(j - k * m) / (double)m;
@@ -518,6 +527,7 @@ static void walker_waveform(const double *p, const oracle_cfg *c, const double *
         }
     }
     free(J);
+    }
 }
 
 static int cfg_ok(const oracle_cfg *c)
@@ -532,7 +542,7 @@ int oracle_waveform(const double *params, int64_t B, const oracle_cfg *c, double
 {
     if (!cfg_ok(c)) return -1;
     int64_t K = n_intervals_of(c);
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) if (B >= oracle_num_threads())
     for (int64_t w = 0; w < B; ++w) {
         double s[8];
         const double *p = params + w * NPAR;
@@ -694,7 +704,7 @@ int oracle_loglike(const double *params, int64_t B, const double *data /* [2][N/
 {
     if (!cfg_ok(c)) return -1;
     int64_t N = c->N, H = N / 2 + 1;
-#pragma omp parallel
+#pragma omp parallel if (B >= oracle_num_threads())
     {
         double *sx = (double *)malloc((size_t)(2 * N) * sizeof(double));
         double *sX = (double *)malloc((size_t)(2 * N + 4 * H) * sizeof(double));

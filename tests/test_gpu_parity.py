@@ -270,3 +270,35 @@ def test_noise_psd_parity(E):
     ref = O.psd_bc04(W.frequencies(N, dt))
     assert np.isinf(got[0]) and np.isinf(ref[0])
     np.testing.assert_allclose(got[1:], ref[1:], rtol=4e-15)   # a few ulps
+
+
+def test_config5_stress_chunked(E):
+    """Config 5 (B=1024, 2 yr at dt = 5 s, 2^24 samples, 40 harmonics; the
+    injection plunges at ~0.6 yr) through workspaces that hold a quarter and a
+    half of the batch: FP64 and mixed on the same inputs for every walker,
+    the oracle on sampled walkers."""
+    w64, wmx = W.config5("fp64"), W.config5("mixed")
+    P = W.walkers(w64)
+    say("config5 oracle data")
+    d, S = oracle_dataset(w64, True)
+    dd, ss = to_device_data(d, S)
+    out = {}
+    for w, part in ((w64, 256), (wmx, 512)):
+        cfg = E.Config.from_workload(w)
+        ws = torch.empty(E.dataset_bytes(cfg) + 256 + E.workspace_bytes(cfg, part),
+                         dtype=torch.uint8, device="cuda")
+        out[w.precision] = E.loglike_batch(gpu_params(P), dd, ss, cfg, ws=ws).cpu().numpy()
+        del ws
+        torch.cuda.empty_cache()
+    a, b = out["fp64"], out["mixed"]
+    assert np.all(np.isfinite(a)) and np.all(np.isfinite(b))
+    rel = np.abs(a - b) / np.abs(a)
+    say("config5 mixed vs fp64: max rel", rel.max(), "max abs", np.abs(a - b).max())
+    assert rel.max() <= 1e-4
+    idx = np.array([0, 333, 1023])
+    say("config5 oracle lnL for", idx)
+    ref = O.loglike(P[idx], d, S, ocfg(w64))
+    r64 = np.abs(a[idx] - ref) / np.abs(ref)
+    rmx = np.abs(b[idx] - ref) / np.abs(ref)
+    say("config5 rel err fp64", r64, "mixed", rmx)
+    assert np.all(r64 <= 1e-10) and np.all(rmx <= 1e-4)

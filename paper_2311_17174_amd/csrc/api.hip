@@ -139,10 +139,10 @@ emri_status make_plan(const emri_cfg* cfg, int64_t B, Plan* p, const char** err)
     q.R2 = (int64_t)1 << q.m2;
     q.esz = (q.prec == EMRI_FP64) ? 16 : 8;
     q.hsz = (q.prec == EMRI_FP64) ? 8 : 4;
-    // columns per pass-A workgroup: rows of ta * esz = 64 bytes by default
-    // (EMRI_FFT_TA_BYTES overrides, for tuning), within 1024 lanes and the
-    // 160 KiB of LDS a workgroup may hold
-    size_t run_bytes = 64;
+    // columns per pass-A workgroup: rows of ta * esz = 128 bytes (FP64) or
+    // 64 bytes (FP32) by default (EMRI_FFT_TA_BYTES overrides, for tuning),
+    // within 1024 lanes and the 160 KiB of LDS a workgroup may hold
+    size_t run_bytes = (q.prec == EMRI_FP64) ? 128 : 64;
     if (const char* env = getenv("EMRI_FFT_TA_BYTES")) run_bytes = (size_t)atoi(env);
     int ta = (int)(run_bytes / q.esz);
     if (ta < 1) ta = 1;
@@ -150,7 +150,7 @@ emri_status make_plan(const emri_cfg* cfg, int64_t B, Plan* p, const char** err)
     auto lds_a = [&](int t) {   // ta padded columns (fft_lds.hpp), re and im
         const int L = (int)q.R2;
         const int pl = ((L + (L >> 4)) + 15) & ~15;
-        return (size_t)t * (pl + (t > 1 ? 16 / t : 0)) * q.esz;
+        return (size_t)t * (pl + (t > 1 ? (int)(128 / q.hsz) / t : 0)) * q.esz;
     };
     while (ta > 1 && (ta * q.R2 / 8 > 1024 || lds_a(ta) > 160 * 1024)) ta /= 2;
     q.TA = ta;

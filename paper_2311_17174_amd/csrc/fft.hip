@@ -80,11 +80,15 @@ hipError_t launch_twiddles(const Plan& p, void* ws, hipStream_t s)
     return hipGetLastError();
 }
 
-// column stride (per re/im array) of a pass-A tile: a padded column, plus a
-// skew of 16/TA slots so the TA columns of one row fall in distinct banks
+// column stride (per re/im array) of a pass-A tile: a padded column plus a
+// skew.  Lanes run column-fastest (TA columns, then L/8 positions), so the
+// 16 lanes that share one 128-byte LDS access cycle (FP64; 32 for FP32) cover
+// TA columns times 16/TA (32/TA) consecutive positions: a skew of that many
+// slots puts the columns in disjoint banks.
+template <typename R>
 __host__ __device__ inline int col_stride(int L, int TA)
 {
-    return padded_len(L) + (TA > 1 ? 16 / TA : 0);
+    return padded_len(L) + (TA > 1 ? (int)(128 / sizeof(R)) / TA : 0);
 }
 
 // XCD-aware tile order: the hardware hands consecutive workgroups to the 8
@@ -96,8 +100,13 @@ __device__ inline int64_t xcd_tile(int64_t bid, int64_t nb)
     return (bid & 7) * (nb >> 3) + (bid >> 3);
 }
 
-// pass A: TA columns of length L (= R2) per workgroup, TA * L / 8 lanes.
-// in and out may alias (the tile's read and write sets coincide).
+// pass A: TA columns of length L (= R2) per workgroup, TA * L / 8 lanes;
+// lane (col, t) = (tid mod TA, tid / TA) loads the positions t + i L/8 of
+// its column straight into registers (runs of TA adjacent columns per row:
+// coalesced), runs the first radix-8 stage there, the middle stages in LDS,
+// and the last one back into registers, from which it applies the four-step
+// twiddle and stores.  in and out may alias (the tile's read and write sets
+// coincide, and every read precedes the first barrier).
 template <typename R, int MAXT>
 __global__ void __launch_bounds__(MAXT) k_fft_cols(const typename C2<R>::T* in,
                                                    typename C2<R>::T* out, int64_t N, int64_t R1,
@@ -109,39 +118,41 @@ __global__ void __launch_bounds__(MAXT) k_fft_cols(const typename C2<R>::T* in,
     using T2 = typename C2<R>::T;
     extern __shared__ unsigned char smem_raw[];
     R* sre = (R*)smem_raw;
-    const int LP = col_stride(L, TA);
+    const int LP = col_stride<R>(L, TA);
     R* sim = sre + TA * LP;
     const int64_t w = blockIdx.y;
     const int64_t c0 = xcd_tile(blockIdx.x, gridDim.x) * TA;
     const T2* src = in + w * N;
     T2* dst = out + w * N;
-    const int nt = blockDim.x;
-    const int tmask = TA - 1;
     int tsh = 0;
     while ((1 << tsh) < TA) ++tsh;
-    for (int q = threadIdx.x; q < TA * L; q += nt) {
-        const int cc = q & tmask, r = q >> tsh;
-        const T2 v = src[c0 + cc + R1 * (int64_t)r];
-        sre[cc * LP + px(r)] = v.x;
-        sim[cc * LP + px(r)] = v.y;
+    const int col = threadIdx.x & (TA - 1), t = threadIdx.x >> tsh;
+    const int L8 = L / 8;
+    const int64_t cg = c0 + col;
+    R xr[8], xi[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const T2 v = src[cg + R1 * (int64_t)(t + i * L8)];
+        xr[i] = v.x;
+        xi[i] = v.y;
     }
-    __syncthreads();
-    const int lanes = L / 8;
-    const int col = threadIdx.x / lanes, t = threadIdx.x - col * lanes;
-    lds_fft<R>(sre + col * LP, sim + col * LP, L, lgL, t, twL);
+    fft_regs<R, true>(sre + col * LP, sim + col * LP, L, lgL, t, twL, xr, xi);
     const int64_t lomask = ((int64_t)1 << s_lo) - 1;
-    for (int q = threadIdx.x; q < TA * L; q += nt) {
-        const int cc = q & tmask, k2 = q >> tsh;
-        R xr = sre[cc * LP + px(k2)], xi = sim[cc * LP + px(k2)];
-        const int64_t e = (c0 + cc) * (int64_t)k2;      // < N
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int k2 = t + i * L8;
+        const int64_t e = cg * (int64_t)k2;      // < N
         const T2 a = thi[e >> s_lo], b = tlo[e & lomask];
         const R wr = a.x * b.x - a.y * b.y, wi = a.x * b.y + a.y * b.x;
-        cmul(xr, xi, wr, wi);
-        dst[c0 + cc + R1 * (int64_t)k2] = T2{xr, xi};
+        R yr = xr[i], yi = xi[i];
+        cmul(yr, yi, wr, wi);
+        dst[cg + R1 * (int64_t)k2] = T2{yr, yi};
     }
 }
 
-// pass B: one row of length L (= R1) per workgroup, L / 8 lanes, in place
+// pass B: one row of length L (= R1) per workgroup, L / 8 lanes, in place;
+// lane t keeps the positions t + i L/8 in registers for the first and last
+// radix stages
 template <typename R, int MAXT>
 __global__ void __launch_bounds__(MAXT) k_fft_rows(typename C2<R>::T* z, int64_t N, int L,
                                                    int lgL,
@@ -153,14 +164,17 @@ __global__ void __launch_bounds__(MAXT) k_fft_rows(typename C2<R>::T* z, int64_t
     R* sim = sre + padded_len(L);
     const int64_t w = blockIdx.y;
     T2* row = z + w * N + (int64_t)blockIdx.x * L;
-    for (int q = threadIdx.x; q < L; q += blockDim.x) {
-        const T2 v = row[q];
-        sre[px(q)] = v.x;
-        sim[px(q)] = v.y;
+    const int t = threadIdx.x, L8 = L / 8;
+    R xr[8], xi[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const T2 v = row[t + i * L8];
+        xr[i] = v.x;
+        xi[i] = v.y;
     }
-    __syncthreads();
-    lds_fft<R>(sre, sim, L, lgL, threadIdx.x, twL);
-    for (int q = threadIdx.x; q < L; q += blockDim.x) row[q] = T2{sre[px(q)], sim[px(q)]};
+    fft_regs<R, true>(sre, sim, L, lgL, t, twL, xr, xi);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) row[t + i * L8] = T2{xr[i], xi[i]};
 }
 
 template <typename R>
@@ -178,7 +192,7 @@ static hipError_t fft_typed(const Plan& p, int64_t B, const void* in, void* ws, 
     const T2* thi = (const T2*)(twb + (f64 ? t.ohi : t.fhi));
     T2* z = (T2*)(base + p.off_z);
     const int LA = (int)p.R2, LB = (int)p.R1;
-    const size_t ldsA = (size_t)p.TA * col_stride(LA, p.TA) * 2 * sizeof(R);
+    const size_t ldsA = (size_t)p.TA * col_stride<R>(LA, p.TA) * 2 * sizeof(R);
     const size_t ldsB = (size_t)padded_len(LB) * 2 * sizeof(R);
     hipError_t ae = allow_lds((const void*)k_fft_cols<R, 512>, ldsA);
     if (ae == hipSuccess) ae = allow_lds((const void*)k_fft_cols<R, 1024>, ldsA);

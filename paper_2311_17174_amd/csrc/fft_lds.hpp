@@ -7,6 +7,9 @@
 // lanes transform one column: radix-8 Stockham stages (one radix-4 or radix-2
 // stage for the remainder), twiddles W_L^e from a device table, three table
 // loads per radix-8 butterfly (w, w^2, w^4; the other powers by products).
+// The first stage runs on values the lanes loaded into registers, and the
+// last may leave its outputs there, so an L-point transform with S stages
+// makes S-1 round trips through LDS.
 #pragma once
 
 #include "internal.hpp"
@@ -147,11 +150,12 @@ __device__ __forceinline__ void lds_stage(R* re, R* im, int L, int Ns, int t,
     __syncthreads();
 }
 
-// L-point FFT (L = 2^lgL >= 8) of one padded column in LDS, by lane t of
-// L/8.  Every lane of the workgroup must call it (it contains barriers).
+// L-point FFT (L = 2^lgL >= 8) of one padded column already in LDS, every
+// stage through LDS, by lane t of L/8.  Every lane of the workgroup must
+// call it (it contains barriers).
 template <typename R>
 __device__ __forceinline__ void lds_fft(R* re, R* im, int L, int lgL, int t,
-                        const typename C2<R>::T* __restrict__ tw)
+                                        const typename C2<R>::T* __restrict__ tw)
 {
     const int n8 = lgL / 3, rem = lgL - 3 * n8;
     int Ns = 1;
@@ -161,6 +165,109 @@ __device__ __forceinline__ void lds_fft(R* re, R* im, int L, int lgL, int t,
     }
     if (rem == 2) lds_stage<R, 4>(re, im, L, Ns, t, tw);
     else if (rem == 1) lds_stage<R, 2>(re, im, L, Ns, t, tw);
+}
+
+// Last Stockham stage (radix RR, Ns = L/RR) from LDS into registers: lane t
+// receives the outputs at positions t + i L/8, i = 0..7, in x[i].
+template <typename R, int RR>
+__device__ __forceinline__ void last_stage_to_regs(const R* re, const R* im, int L, int t,
+                                                   const typename C2<R>::T* __restrict__ tw,
+                                                   R (&xr)[8], R (&xi)[8])
+{
+    using T2 = typename C2<R>::T;
+    constexpr int NB = 8 / RR;
+    const int stride = L / RR;       // = Ns of this stage: tws = 1
+    R vr[8], vi[8];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = t + b * (L / 8);   // j < Ns: k = j
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+            vr[b * RR + r] = re[px(j + r * stride)];
+            vi[b * RR + r] = im[px(j + r * stride)];
+        }
+        if (j > 0) {
+            R wr[8], wi[8];
+            const T2 w1 = tw[j];
+            wr[1] = w1.x; wi[1] = w1.y;
+            if constexpr (RR >= 4) {
+                const T2 w2 = tw[2 * j];
+                wr[2] = w2.x; wi[2] = w2.y;
+                wr[3] = w1.x * w2.x - w1.y * w2.y; wi[3] = w1.x * w2.y + w1.y * w2.x;
+            }
+            if constexpr (RR == 8) {
+                const T2 w4 = tw[4 * j];
+                wr[4] = w4.x; wi[4] = w4.y;
+                wr[5] = w1.x * w4.x - w1.y * w4.y; wi[5] = w1.x * w4.y + w1.y * w4.x;
+                wr[6] = wr[2] * w4.x - wi[2] * w4.y; wi[6] = wr[2] * w4.y + wi[2] * w4.x;
+                wr[7] = wr[3] * w4.x - wi[3] * w4.y; wi[7] = wr[3] * w4.y + wi[3] * w4.x;
+            }
+#pragma unroll
+            for (int r = 1; r < RR; ++r) cmul(vr[b * RR + r], vi[b * RR + r], wr[r], wi[r]);
+        }
+    }
+    if constexpr (RR == 8) {
+        dft8(vr, vi);
+    } else if constexpr (RR == 4) {
+        dft4(vr, vi);
+        dft4(vr + 4, vi + 4);
+    } else {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) dft2(vr[2 * b], vi[2 * b], vr[2 * b + 1], vi[2 * b + 1]);
+    }
+    // output q of butterfly b sits at t + (b + q NB) L/8
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int q = 0; q < RR; ++q) {
+            xr[b + q * NB] = vr[b * RR + q];
+            xi[b + q * NB] = vi[b * RR + q];
+        }
+}
+
+// L-point FFT (L = 2^lgL >= 8) of one column whose lane t holds, on entry,
+// the elements at positions t + i L/8 (i = 0..7) in x.  The first radix-8
+// stage runs on those registers, the middle stages in LDS; with OUT_REGS the
+// last stage leaves the outputs at positions t + i L/8 in x, otherwise the
+// transform is left in LDS (padded).  Every lane of the workgroup must call
+// it; with OUT_REGS the caller synchronises before LDS is written again.
+template <typename R, bool OUT_REGS>
+__device__ __forceinline__ void fft_regs(R* re, R* im, int L, int lgL, int t,
+                                         const typename C2<R>::T* __restrict__ tw, R (&xr)[8],
+                                         R (&xi)[8])
+{
+    const int n8 = lgL / 3, rem = lgL - 3 * n8;
+    const int nst = n8 + (rem ? 1 : 0);
+    dft8(xr, xi);                          // stage 1: Ns = 1, no twiddles
+    if (nst == 1) {                        // L = 8: outputs already at t + i
+        if (!OUT_REGS) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) { re[px(r)] = xr[r]; im[px(r)] = xi[r]; }
+            __syncthreads();
+        }
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        re[px(8 * t + r)] = xr[r];
+        im[px(8 * t + r)] = xi[r];
+    }
+    __syncthreads();
+    int Ns = 8;
+    for (int st = 1; st < nst - 1; ++st) {   // middle stages are radix 8
+        lds_stage<R, 8>(re, im, L, Ns, t, tw);
+        Ns *= 8;
+    }
+    const int RR = (rem == 0) ? 8 : (rem == 2 ? 4 : 2);
+    if (OUT_REGS) {
+        if (RR == 8) last_stage_to_regs<R, 8>(re, im, L, t, tw, xr, xi);
+        else if (RR == 4) last_stage_to_regs<R, 4>(re, im, L, t, tw, xr, xi);
+        else last_stage_to_regs<R, 2>(re, im, L, t, tw, xr, xi);
+    } else {
+        if (RR == 8) lds_stage<R, 8>(re, im, L, Ns, t, tw);
+        else if (RR == 4) lds_stage<R, 4>(re, im, L, Ns, t, tw);
+        else lds_stage<R, 2>(re, im, L, Ns, t, tw);
+    }
 }
 
 }  // namespace emri

@@ -144,8 +144,9 @@ __device__ inline void delay_rotation(int64_t k, double phi, double* c, double* 
 // Fused pass B + inner product.  Workgroup (g, walker tile): rows g and
 // R2 - g of the column-transformed signal (rows 0 and R2/2 pair with
 // themselves), L = R1 points each, L/8 lanes.  For each walker of the tile:
-// row A is transformed in LDS and lane t keeps its 8 values (positions
-// p = t + i L/8) in registers; row B is transformed in the same LDS; then
+// row A is transformed with its first and last stages in registers, and lane
+// t keeps its 8 values (positions p = t + i L/8) there; row B is transformed
+// into LDS; then
 // lane t owns the bins (A, p) for p < L/2, paired with (B, L-1-p), and the
 // bins (B, L-1-p) for p >= L/2, paired with (A, p).  Data and weights of the
 // lane's bins are read once per walker (the tile's walkers hit the cache).
@@ -207,29 +208,47 @@ k_rows_like(const typename C2<R>::T* __restrict__ z,
             continue;
         }
         const T2* zw = z + w * N;
-        // row A
-        for (int q = t; q < L; q += L8) {
-            const T2 v = zw[rowA * L + q];
-            sre[px(q)] = v.x;
-            sim[px(q)] = v.y;
-        }
-        __syncthreads();
-        lds_fft<R>(sre, sim, L, lgL, t, twL);
+        // row A: lane t loads positions t + i L/8 into registers; a row that
+        // pairs with another leaves its transform in registers, a self-paired
+        // row leaves it in LDS (its mirror values are read from there)
         R ar[8], ai[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            ar[i] = sre[px(t + i * L8)];
-            ai[i] = sim[px(t + i * L8)];
+            const T2 v = zw[rowA * L + t + i * L8];
+            ar[i] = v.x;
+            ai[i] = v.y;
         }
         if (!self) {
+            fft_regs<R, true>(sre, sim, L, lgL, t, twL, ar, ai);
             __syncthreads();
-            for (int q = t; q < L; q += L8) {
-                const T2 v = zw[rowB * L + q];
-                sre[px(q)] = v.x;
-                sim[px(q)] = v.y;
+            if constexpr (sizeof(R) == 8) {
+                // FP64: row B goes through LDS from the start; holding its 8
+                // values in registers beside row A's costs more in spills
+                // than the LDS round trip it saves
+                for (int q = t; q < L; q += L8) {
+                    const T2 v = zw[rowB * L + q];
+                    sre[px(q)] = v.x;
+                    sim[px(q)] = v.y;
+                }
+                __syncthreads();
+                lds_fft<R>(sre, sim, L, lgL, t, twL);
+            } else {
+                R br[8], bi[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const T2 v = zw[rowB * L + t + i * L8];
+                    br[i] = v.x;
+                    bi[i] = v.y;
+                }
+                fft_regs<R, false>(sre, sim, L, lgL, t, twL, br, bi);
             }
-            __syncthreads();
-            lds_fft<R>(sre, sim, L, lgL, t, twL);
+        } else {
+            fft_regs<R, false>(sre, sim, L, lgL, t, twL, ar, ai);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                ar[i] = sre[px(t + i * L8)];
+                ai[i] = sim[px(t + i * L8)];
+            }
         }
         const double scale = c[WC_G] * dt;
         const bool hasdt = c[WC_HASDT] != 0.0;

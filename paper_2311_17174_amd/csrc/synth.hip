@@ -83,8 +83,12 @@ __device__ __forceinline__ void angle_run(const double (&a)[SPT], bool smooth, R
     }
 }
 
+// up to 4 samples per lane the register budget is capped at 128 (4 waves
+// per SIMD; a few spills outside the harmonic loop are cheaper than the
+// lost occupancy); longer runs keep their registers
 template <typename R, typename HT, int SPT>
-__global__ void __launch_bounds__(256) k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPT <= 4 ? 4 : 1)))
+k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
                                                double dt, const double* __restrict__ wc,
                                                const double* __restrict__ co,
                                                const HT* __restrict__ ch,
@@ -143,12 +147,19 @@ __global__ void __launch_bounds__(256) k_synth(int64_t K, int64_t Nv, int64_t N,
     angle_run<R, SPT>(ph, smooth, c1, s1);
 
     // ---- harmonic sum ------------------------------------------------------
-    R Sa[SPT], Sb[SPT], Sc[SPT], cn[SPT], sn[SPT];
+    // cos/sin(n Phi') for n = 1..nh: FP64 by the three-term recurrence
+    // x_{n+1} = 2 cos(Phi') x_n - x_{n-1} (one FMA per value; the error
+    // injected at step m is carried forward at most (n - m + 1)-fold, so
+    // below nh^2 ulp in all), FP32 by complex rotation (error ~ n ulp)
+    R Sa[SPT], Sb[SPT], Sc[SPT], cn[SPT], sn[SPT], cq[SPT], sq[SPT], tc[SPT];
 #pragma unroll
     for (int s = 0; s < SPT; ++s) {
         Sa[s] = Sb[s] = Sc[s] = R(0);
         cn[s] = c1[s];
         sn[s] = s1[s];
+        cq[s] = R(1);
+        sq[s] = R(0);
+        tc[s] = R(2) * c1[s];
     }
     const HT* hq = ch + (w * K + k) * (int64_t)nh * 12;
 #pragma unroll 2
@@ -166,9 +177,18 @@ __global__ void __launch_bounds__(256) k_synth(int64_t K, int64_t Nv, int64_t N,
             Sa[s] += ua * cn[s];
             Sb[s] += ub * sn[s];
             Sc[s] += uc * cn[s];
-            const R cc = cn[s] * c1[s] - sn[s] * s1[s];
-            sn[s] = sn[s] * c1[s] + cn[s] * s1[s];
-            cn[s] = cc;
+            if constexpr (sizeof(R) == 8) {
+                const R cc = tc[s] * cn[s] - cq[s];
+                const R ss = tc[s] * sn[s] - sq[s];
+                cq[s] = cn[s];
+                sq[s] = sn[s];
+                cn[s] = cc;
+                sn[s] = ss;
+            } else {
+                const R cc = cn[s] * c1[s] - sn[s] * s1[s];
+                sn[s] = sn[s] * c1[s] + cn[s] * s1[s];
+                cn[s] = cc;
+            }
         }
     }
 

@@ -50,15 +50,19 @@ __device__ double comoving_integral(double z, const GL8& g)
 // ---------------------------------------------------------------------------
 struct Rhs { double dPhi, dnu, dgt, de, dal; };
 
-__device__ inline Rhs ak_rhs(double nu, double e, double Ms, double mus, double a, double cl)
+// x13 = cbrt(2 pi M nu) is passed in: the state after a step shares it with
+// the plunge test.  Constant divisors are applied as reciprocal products and
+// 1/eps as rsqrt(eps)^2 (a few ulp from the quotients; no IEEE division on
+// the step's dependency chain).
+__device__ inline Rhs ak_rhs_x(double nu, double x13, double e, double Ms, double mus, double a,
+                               double cl)
 {
     const double x = 2.0 * kPi * Ms * nu;
-    const double x13 = cbrt(x);
     const double x23 = x13 * x13;
     const double e2 = e * e, e4 = e2 * e2, e6 = e4 * e2;
     const double eps = 1.0 - e2;
-    const double ie = 1.0 / eps;
     const double rse = rsqrt(eps);          // eps^{-1/2}
+    const double ie = rse * rse;
     const double ie2 = ie * ie, ie4 = ie2 * ie2;
     const double acl = a * cl;
     const double M2 = Ms * Ms;
@@ -76,22 +80,29 @@ __device__ inline Rhs ak_rhs(double nu, double e, double Ms, double mus, double 
             12.0 * kPi * nu * acl * x * ie * rse;
     const double x83 = x * x * x23;         // x^{8/3}
     double br = (304.0 + 121.0 * e2) * eps * (1.0 + 12.0 * x23) -
-                (x23 / 56.0) * (133640.0 + 108984.0 * e2 - 25211.0 * e4);
-    r.de = -(e / 15.0) * (mus / M2) * ie2 * ie * rse * x83 * br +
+                (x23 * (1.0 / 56.0)) * (133640.0 + 108984.0 * e2 - 25211.0 * e4);
+    r.de = -(e * (1.0 / 15.0)) * (mus / M2) * ie2 * ie * rse * x83 * br +
            e * (mus / M2) * acl * x113 * ie4 *
                (1364.0 / 5.0 + (5032.0 / 15.0) * e2 + (263.0 / 10.0) * e4);
     r.dal = 4.0 * kPi * nu * a * x * ie * rse;
     return r;
 }
 
-// before the last stable orbit: nu < nu_LSO(e) of Sec. 3, on a sane state
-__device__ inline bool before_lso(double Phi, double nu, double gt, double e, double al, double Ms)
+__device__ inline Rhs ak_rhs(double nu, double e, double Ms, double mus, double a, double cl)
 {
+    return ak_rhs_x(nu, cbrt(2.0 * kPi * Ms * nu), e, Ms, mus, a, cl);
+}
+
+// before the last stable orbit: nu < nu_LSO(e) of Sec. 3, on a sane state;
+// *x13 receives cbrt(2 pi M nu)
+__device__ inline bool before_lso(double Phi, double nu, double gt, double e, double al, double Ms,
+                                  double* x13)
+{
+    *x13 = cbrt(2.0 * kPi * Ms * nu);
     if (!(isfinite(Phi) && isfinite(nu) && isfinite(gt) && isfinite(e) && isfinite(al)))
         return false;
     if (!(nu > 0.0 && e >= 0.0 && e < 1.0)) return false;
-    const double x13 = cbrt(2.0 * kPi * Ms * nu);
-    return x13 * x13 * (6.0 + 2.0 * e) < (1.0 - e) * (1.0 + e);
+    return *x13 * *x13 * (6.0 + 2.0 * e) < (1.0 - e) * (1.0 + e);
 }
 
 // ---------------------------------------------------------------------------
@@ -116,7 +127,8 @@ __global__ void __launch_bounds__(64) k_walker_setup(const double* __restrict__ 
     ok = ok && mu > 0.0 && mu < M && a >= 0.0 && a <= 1.0 && e0 >= 0.0 && e0 < 1.0 &&
          nu0 > 0.0 && dl > 0.0 && at > -1.0 && cl >= -1.0 && cl <= 1.0;
     const double Ms = M * kSunSeconds, mus = mu * kSunSeconds;
-    ok = ok && before_lso(p[5], nu0, p[6], e0, p[7], Ms);
+    double x13_0;
+    ok = ok && before_lso(p[5], nu0, p[6], e0, p[7], Ms, &x13_0);
     if (!ok) return;
 
     // distance, redshift, Eq. (6), delay, overall factor
@@ -180,8 +192,9 @@ __global__ void __launch_bounds__(64) k_walker_setup(const double* __restrict__ 
         Y2 += h6 * (f.dgt + 2.0 * k2.dgt + 2.0 * k3.dgt + k4.dgt);
         Y3 += h6 * (f.de + 2.0 * k2.de + 2.0 * k3.de + k4.de);
         Y4 += h6 * (f.dal + 2.0 * k2.dal + 2.0 * k3.dal + k4.dal);
-        if (!before_lso(Y0, Y1, Y2, Y3, Y4, Ms)) { Kw = k; break; }
-        f = ak_rhs(Y1, Y3, Ms, mus, a, cl);
+        double x13;
+        if (!before_lso(Y0, Y1, Y2, Y3, Y4, Ms, &x13)) { Kw = k; break; }
+        f = ak_rhs_x(Y1, x13, Y3, Ms, mus, a, cl);
         double* q = o + (k + 1) * 10;
         q[0] = Y0; q[1] = Y1; q[2] = Y2; q[3] = Y3; q[4] = Y4;
         q[5] = f.dPhi; q[6] = f.dnu; q[7] = f.dgt; q[8] = f.de; q[9] = f.dal;

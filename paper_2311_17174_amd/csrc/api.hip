@@ -9,8 +9,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <map>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace emri {
@@ -185,15 +187,105 @@ static emri_status check_launch(hipError_t e, const char* where)
     return EMRI_OK;
 }
 
+// ---- orbit-segment pipeline -------------------------------------------------
+// The orbit integration is sequential in time and runs one lane per walker:
+// alone it would leave the GPU nearly idle.  It is cut into S segments of
+// coarse steps; the caller's stream integrates them in turn while an
+// auxiliary stream builds the tables and synthesises the samples of each
+// finished segment.  One auxiliary stream (non-blocking, default priority)
+// and its events per (device, caller stream), created on first use and kept
+// until the process ends.  Every wait refers to an event recorded earlier in
+// host order, and the caller's stream waits for the auxiliary stream before
+// returning, so the pair behaves as one stream to the caller (also under
+// stream capture, where the auxiliary stream joins and leaves the capture).
+struct Pipe {
+    hipStream_t aux = nullptr;
+    hipEvent_t seg[kMaxSeg] = {};
+    hipEvent_t join = nullptr;
+};
+static std::mutex g_pipe_mu;
+static std::map<std::pair<int, hipStream_t>, Pipe> g_pipes;
+
+static emri_status get_pipe(hipStream_t s, Pipe** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "pipeline: hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_pipe_mu);
+    auto it = g_pipes.find({dev, s});
+    if (it != g_pipes.end()) {
+        *out = &it->second;
+        return EMRI_OK;
+    }
+    Pipe q;
+    e = hipStreamCreateWithFlags(&q.aux, hipStreamNonBlocking);
+    for (int i = 0; i < kMaxSeg && e == hipSuccess; ++i)
+        e = hipEventCreateWithFlags(&q.seg[i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&q.join, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        for (int i = 0; i < kMaxSeg; ++i)
+            if (q.seg[i]) (void)hipEventDestroy(q.seg[i]);
+        if (q.join) (void)hipEventDestroy(q.join);
+        if (q.aux) (void)hipStreamDestroy(q.aux);
+        return fail_hip(e, "pipeline: stream/event creation");
+    }
+    *out = &g_pipes.emplace(std::make_pair(dev, s), q).first->second;
+    return EMRI_OK;
+}
+
+// number of orbit segments: about 384 coarse steps each, at most 8
+// (EMRI_ORBIT_SEGMENTS overrides, 1 .. 16, for tuning and tests)
+static int orbit_segments(const Plan& p)
+{
+    int64_t S = p.K / 384;
+    if (const char* env = getenv("EMRI_ORBIT_SEGMENTS")) S = atoi(env);
+    else if (S > 8) S = 8;
+    if (S > kMaxSeg) S = kMaxSeg;
+    if (S > p.K) S = p.K;
+    return S < 1 ? 1 : (int)S;
+}
+
 // walkers [0, B) of params, workspace planned for at least B walkers
 static emri_status run_waveforms(const Plan& p, const double* params, int64_t B, void* ws,
                                  void* out, hipStream_t s)
 {
+    const int S = orbit_segments(p);
+    const int64_t KT = p.N / p.L;            // synthesis intervals, zero tail included
+    auto kb = [&](int i) { return p.K * i / S; };
     emri_status st;
-    if ((st = check_launch(launch_walker_setup(p, params, B, ws, s), "walker setup"))) return st;
-    if ((st = check_launch(launch_tables(p, B, ws, s), "amplitude tables"))) return st;
-    if ((st = check_launch(launch_synth(p, B, ws, out, s), "synthesis"))) return st;
-    return EMRI_OK;
+    if (S == 1) {
+        if ((st = check_launch(launch_walker_setup(p, params, B, ws, p.K, s), "walker setup")))
+            return st;
+        if ((st = check_launch(launch_tables(p, B, ws, 0, p.K, 0, s), "amplitude tables")))
+            return st;
+        return check_launch(launch_synth(p, B, ws, out, 0, KT, 0, s), "synthesis");
+    }
+    Pipe* pp = nullptr;
+    if ((st = get_pipe(s, &pp))) return st;
+    st = check_launch(launch_walker_setup(p, params, B, ws, kb(1), s), "walker setup");
+    bool forked = false;
+    for (int i = 0; i < S && st == EMRI_OK; ++i) {
+        if (i > 0 &&
+            (st = check_launch(launch_walker_resume(p, B, ws, kb(i), kb(i + 1), i, s), "orbit")))
+            break;
+        if ((st = check_launch(hipEventRecord(pp->seg[i], s), "pipeline: event record"))) break;
+        if ((st = check_launch(hipStreamWaitEvent(pp->aux, pp->seg[i], 0), "pipeline: wait")))
+            break;
+        forked = true;
+        if ((st = check_launch(launch_tables(p, B, ws, kb(i), kb(i + 1), i, pp->aux),
+                               "amplitude tables")))
+            break;
+        if ((st = check_launch(launch_synth(p, B, ws, out, kb(i), i == S - 1 ? KT : kb(i + 1), i,
+                                            pp->aux),
+                               "synthesis")))
+            break;
+    }
+    if (forked) {   // join, also after a failed launch
+        const hipError_t e1 = hipEventRecord(pp->join, pp->aux);
+        const hipError_t e2 = (e1 == hipSuccess) ? hipStreamWaitEvent(s, pp->join, 0) : e1;
+        if (st == EMRI_OK) st = check_launch(e2, "pipeline: join");
+    }
+    return st;
 }
 
 // largest chunk <= B whose plan fits in `bytes`

@@ -46,7 +46,9 @@ enum {
     WC_KW = 25,     // index of the last orbit node before the LSO
     WC_Z = 26, WC_XI = 27, WC_DT = 28, WC_D = 29,
     WC_HASDT = 30,  // 1 if Delta T != 0
-    WC = 32
+    WC_KSEG = 32,   // 16 slots: K_w as known after orbit segment i (the
+                    // segment's end when the orbit is still before the LSO)
+    WC = 48
 };
 
 // partial sums of the data norm <d|d> (mixed path data set)
@@ -101,10 +103,22 @@ struct TwLayout {
 TwLayout tw_layout(const Plan& p);
 
 // ---- launchers (return hipSuccess or the launch error) -------------------
+// the orbit is integrated in segments [k_i, k_{i+1}) of coarse steps so that
+// the amplitude tables and synthesis of finished segments overlap the rest
+// of the integration; kMaxSeg bounds their number
+constexpr int kMaxSeg = 16;
+// walker constants and orbit segment 0 (steps [0, k1))
 hipError_t launch_walker_setup(const Plan& p, const double* params, int64_t B, void* ws,
-                               hipStream_t s);
-hipError_t launch_tables(const Plan& p, int64_t B, void* ws, hipStream_t s);
-hipError_t launch_synth(const Plan& p, int64_t B, void* ws, void* out, hipStream_t s);
+                               int64_t k1, hipStream_t s);
+// orbit segment seg >= 1: steps [k0, k1) from the stored node k0
+hipError_t launch_walker_resume(const Plan& p, int64_t B, void* ws, int64_t k0, int64_t k1,
+                                int seg, hipStream_t s);
+// node amplitudes and interval tables of segment seg (intervals [k0, k1))
+hipError_t launch_tables(const Plan& p, int64_t B, void* ws, int64_t k0, int64_t k1, int seg,
+                         hipStream_t s);
+// samples of the intervals [k0, k1) (k1 may reach N / L: zero tail)
+hipError_t launch_synth(const Plan& p, int64_t B, void* ws, void* out, int64_t k0, int64_t k1,
+                        int seg, hipStream_t s);
 hipError_t launch_twiddles(const Plan& p, void* ws, hipStream_t s);
 hipError_t launch_fft(const Plan& p, int64_t B, void* ws, hipStream_t s);  // z -> z (transposed)
 // FFT reading `in` ([B][N] complex, NULL: the workspace signal), result in z

@@ -1,6 +1,7 @@
 // synth.hip -- stage (b): time-domain AK waveform on the fine sampling grid.
 //
-// One workgroup of 256 lanes per (coarse interval k, walker w); each lane
+// One workgroup of 256 lanes per (coarse interval k, walker w), over the
+// intervals [k0, k1) of one orbit segment; each lane
 // produces SPT = 2^coarse_log2 / 256 consecutive samples j = k 2^cl +
 // lane SPT + s.  Everything a wave needs from the orbit and the amplitude
 // tables is uniform over the interval and is read with scalar loads.  When
@@ -89,6 +90,7 @@ __device__ __forceinline__ void angle_run(const double (&a)[SPT], bool smooth, R
 template <typename R, typename HT, int SPT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPT <= 4 ? 4 : 1)))
 k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
+                                               int64_t k0, int seg,
                                                double dt, const double* __restrict__ wc,
                                                const double* __restrict__ co,
                                                const HT* __restrict__ ch,
@@ -96,14 +98,14 @@ k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
 {
     using R2 = typename V2<R>::T;
     constexpr int L = 256 * SPT;
-    const int64_t k = blockIdx.x;
+    const int64_t k = k0 + blockIdx.x;
     const int64_t w = blockIdx.y;
     const int lane = threadIdx.x;
     R2* zw = out + w * N;
     const int64_t j0 = k * L;
     const int64_t jl = j0 + (int64_t)lane * SPT;      // this lane's first sample
     const double* c = wc + w * WC;
-    const int64_t Kw = (int64_t)c[WC_KW];
+    const int64_t Kw = (int64_t)c[WC_KSEG + seg];
     if (c[WC_VALID] == 0.0 || k >= Kw || j0 >= Nv) {
 #pragma unroll
         for (int s = 0; s < SPT; ++s) zw[jl + s] = R2{R(0), R(0)};
@@ -275,31 +277,40 @@ k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
 
 template <typename R, typename HT>
 static hipError_t synth_dispatch(const Plan& p, int64_t B, const char* base, void* out,
-                                 hipStream_t s)
+                                 int64_t k0, int64_t k1, int seg, hipStream_t s)
 {
-    dim3 grid((unsigned)(p.N / p.L), (unsigned)B);
+    dim3 grid((unsigned)(k1 - k0), (unsigned)B);
     using R2 = typename V2<R>::T;
     const double* wc = (const double*)(base + p.off_wc);
     const double* co = (const double*)(base + p.off_co);
     const HT* ch = (const HT*)(base + p.off_ch);
     R2* o = (R2*)out;
+#define EMRI_SYNTH(SPT)                                                                        \
+    hipLaunchKernelGGL((k_synth<R, HT, SPT>), grid, dim3(256), 0, s, p.K, p.Nv, p.N, p.nh, k0, \
+                       seg, p.dt, wc, co, ch, o)
     switch (p.cl) {
-    case 8:  hipLaunchKernelGGL((k_synth<R, HT, 1>), grid, dim3(256), 0, s, p.K, p.Nv, p.N, p.nh, p.dt, wc, co, ch, o); break;
-    case 9:  hipLaunchKernelGGL((k_synth<R, HT, 2>), grid, dim3(256), 0, s, p.K, p.Nv, p.N, p.nh, p.dt, wc, co, ch, o); break;
-    case 10: hipLaunchKernelGGL((k_synth<R, HT, 4>), grid, dim3(256), 0, s, p.K, p.Nv, p.N, p.nh, p.dt, wc, co, ch, o); break;
-    case 11: hipLaunchKernelGGL((k_synth<R, HT, 8>), grid, dim3(256), 0, s, p.K, p.Nv, p.N, p.nh, p.dt, wc, co, ch, o); break;
-    case 12: hipLaunchKernelGGL((k_synth<R, HT, 16>), grid, dim3(256), 0, s, p.K, p.Nv, p.N, p.nh, p.dt, wc, co, ch, o); break;
+    case 8: EMRI_SYNTH(1); break;
+    case 9: EMRI_SYNTH(2); break;
+    case 10: EMRI_SYNTH(4); break;
+    case 11: EMRI_SYNTH(8); break;
+    case 12: EMRI_SYNTH(16); break;
     default: return hipErrorInvalidValue;
     }
+#undef EMRI_SYNTH
     return hipGetLastError();
 }
 
-hipError_t launch_synth(const Plan& p, int64_t B, void* ws, void* out, hipStream_t s)
+hipError_t launch_synth(const Plan& p, int64_t B, void* ws, void* out, int64_t k0, int64_t k1,
+                        int seg, hipStream_t s)
 {
+    if (seg < 0 || seg >= kMaxSeg || k0 < 0 || k1 < k0 || k1 > p.N / p.L)
+        return hipErrorInvalidValue;
+    if (k1 == k0) return hipSuccess;
     const char* base = (const char*)ws;
     trace_mark(ST_SYNTH, s, true);
-    const hipError_t e = (p.prec == EMRI_FP64) ? synth_dispatch<double, double>(p, B, base, out, s)
-                                               : synth_dispatch<float, float>(p, B, base, out, s);
+    const hipError_t e =
+        (p.prec == EMRI_FP64) ? synth_dispatch<double, double>(p, B, base, out, k0, k1, seg, s)
+                              : synth_dispatch<float, float>(p, B, base, out, k0, k1, seg, s);
     trace_mark(ST_SYNTH, s, false);
     return e;
 }

@@ -108,11 +108,43 @@ __device__ inline bool before_lso(double Phi, double nu, double gt, double e, do
 // ---------------------------------------------------------------------------
 // k_walker_setup: one lane per walker
 // ---------------------------------------------------------------------------
+// RK4 steps k0 .. k1-1 from the state Y at node k0 with derivative f;
+// writes nodes k0+1 .. to o (10 values each: Y, then dY/dt) and returns the
+// index of the last node before the LSO (k1 if every step stays before it)
+__device__ __forceinline__ int64_t rk4_steps(double& Y0, double& Y1, double& Y2, double& Y3,
+                                             double& Y4, Rhs f, int64_t k0, int64_t k1, double h,
+                                             double Ms, double mus, double a, double cl,
+                                             double* __restrict__ o)
+{
+    const double hh = 0.5 * h, h6 = h / 6.0;
+    for (int64_t k = k0; k < k1; ++k) {
+        const Rhs k2 = ak_rhs(Y1 + hh * f.dnu, Y3 + hh * f.de, Ms, mus, a, cl);
+        const Rhs k3 = ak_rhs(Y1 + hh * k2.dnu, Y3 + hh * k2.de, Ms, mus, a, cl);
+        const Rhs k4 = ak_rhs(Y1 + h * k3.dnu, Y3 + h * k3.de, Ms, mus, a, cl);
+        Y0 += h6 * (f.dPhi + 2.0 * k2.dPhi + 2.0 * k3.dPhi + k4.dPhi);
+        Y1 += h6 * (f.dnu + 2.0 * k2.dnu + 2.0 * k3.dnu + k4.dnu);
+        Y2 += h6 * (f.dgt + 2.0 * k2.dgt + 2.0 * k3.dgt + k4.dgt);
+        Y3 += h6 * (f.de + 2.0 * k2.de + 2.0 * k3.de + k4.de);
+        Y4 += h6 * (f.dal + 2.0 * k2.dal + 2.0 * k3.dal + k4.dal);
+        double x13;
+        if (!before_lso(Y0, Y1, Y2, Y3, Y4, Ms, &x13)) return k;
+        f = ak_rhs_x(Y1, x13, Y3, Ms, mus, a, cl);
+        double* q = o + (k + 1) * 10;
+        q[0] = Y0; q[1] = Y1; q[2] = Y2; q[3] = Y3; q[4] = Y4;
+        q[5] = f.dPhi; q[6] = f.dnu; q[7] = f.dgt; q[8] = f.de; q[9] = f.dal;
+    }
+    return k1;
+}
+
+// The orbit kernels run one lane per walker, a few waves for the whole batch,
+// beside the table and synthesis kernels of earlier segments: they raise
+// their waves' issue priority so those do not stretch the integration.
 __global__ void __launch_bounds__(64) k_walker_setup(const double* __restrict__ params, int64_t B,
                                                      int64_t K, double h, double Ndt, GL8 gl,
-                                                     double* __restrict__ wc,
+                                                     int64_t k1, double* __restrict__ wc,
                                                      double* __restrict__ orb)
 {
+    __builtin_amdgcn_s_setprio(3);
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= B) return;
     const double* p = params + w * EMRI_NPAR;
@@ -181,26 +213,37 @@ __global__ void __launch_bounds__(64) k_walker_setup(const double* __restrict__ 
     Rhs f = ak_rhs(Y1, Y3, Ms, mus, a, cl);
     o[0] = Y0; o[1] = Y1; o[2] = Y2; o[3] = Y3; o[4] = Y4;
     o[5] = f.dPhi; o[6] = f.dnu; o[7] = f.dgt; o[8] = f.de; o[9] = f.dal;
-    int64_t Kw = K;
-    const double hh = 0.5 * h, h6 = h / 6.0;
-    for (int64_t k = 0; k < K; ++k) {
-        const Rhs k2 = ak_rhs(Y1 + hh * f.dnu, Y3 + hh * f.de, Ms, mus, a, cl);
-        const Rhs k3 = ak_rhs(Y1 + hh * k2.dnu, Y3 + hh * k2.de, Ms, mus, a, cl);
-        const Rhs k4 = ak_rhs(Y1 + h * k3.dnu, Y3 + h * k3.de, Ms, mus, a, cl);
-        Y0 += h6 * (f.dPhi + 2.0 * k2.dPhi + 2.0 * k3.dPhi + k4.dPhi);
-        Y1 += h6 * (f.dnu + 2.0 * k2.dnu + 2.0 * k3.dnu + k4.dnu);
-        Y2 += h6 * (f.dgt + 2.0 * k2.dgt + 2.0 * k3.dgt + k4.dgt);
-        Y3 += h6 * (f.de + 2.0 * k2.de + 2.0 * k3.de + k4.de);
-        Y4 += h6 * (f.dal + 2.0 * k2.dal + 2.0 * k3.dal + k4.dal);
-        double x13;
-        if (!before_lso(Y0, Y1, Y2, Y3, Y4, Ms, &x13)) { Kw = k; break; }
-        f = ak_rhs_x(Y1, x13, Y3, Ms, mus, a, cl);
-        double* q = o + (k + 1) * 10;
-        q[0] = Y0; q[1] = Y1; q[2] = Y2; q[3] = Y3; q[4] = Y4;
-        q[5] = f.dPhi; q[6] = f.dnu; q[7] = f.dgt; q[8] = f.de; q[9] = f.dal;
-    }
+    const int64_t Kw = rk4_steps(Y0, Y1, Y2, Y3, Y4, f, 0, k1, h, Ms, mus, a, cl, o);
+    c[WC_KSEG] = (double)Kw;
     c[WC_KW] = (double)Kw;
     c[WC_VALID] = 1.0;
+}
+
+// orbit segment seg >= 1: steps [k0, k1) from node k0 (stored by segment
+// seg - 1), unless the orbit reached the LSO before k0
+__global__ void __launch_bounds__(64) k_walker_resume(int64_t B, int64_t K, double h, int64_t k0,
+                                                      int64_t k1, int seg,
+                                                      double* __restrict__ wc,
+                                                      double* __restrict__ orb)
+{
+    __builtin_amdgcn_s_setprio(3);
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= B) return;
+    double* c = wc + w * WC;
+    if (c[WC_VALID] == 0.0) return;
+    const int64_t Kp = (int64_t)c[WC_KSEG + seg - 1];
+    if (Kp < k0) {
+        c[WC_KSEG + seg] = (double)Kp;
+        return;
+    }
+    const double Ms = c[WC_MS], mus = c[WC_MUS], a = c[WC_A], cl = c[WC_CL];
+    double* o = orb + w * (K + 1) * 10;
+    const double* q = o + k0 * 10;
+    double Y0 = q[0], Y1 = q[1], Y2 = q[2], Y3 = q[3], Y4 = q[4];
+    const Rhs f{q[5], q[6], q[7], q[8], q[9]};
+    const int64_t Kw = rk4_steps(Y0, Y1, Y2, Y3, Y4, f, k0, k1, h, Ms, mus, a, cl, o);
+    c[WC_KSEG + seg] = (double)Kw;
+    c[WC_KW] = (double)Kw;
 }
 
 // ---------------------------------------------------------------------------
@@ -287,20 +330,22 @@ __device__ inline void hermite_coeffs(double y0, double d0, double y1, double d1
     c[3] = 2.0 * (y0 - y1) + h * (d0 + d1);
 }
 
-// node values: for (walker, node k <= K_w, harmonic n) the three amplitudes
-// A n P_n, A n Q_n, 2 A J_n(ne) and their time derivatives, nv[w][k][n][6]
-__global__ void __launch_bounds__(256) k_nodes(int64_t K, int nh, const double* __restrict__ wc,
+// node values: for (walker, node k in [n0, n1), k <= K_w, harmonic n) the
+// three amplitudes A n P_n, A n Q_n, 2 A J_n(ne) and their time derivatives,
+// nv[w][k][n][6]
+__global__ void __launch_bounds__(256) k_nodes(int64_t K, int nh, int64_t n0, int64_t n1, int seg,
+                                               const double* __restrict__ wc,
                                                const double* __restrict__ orb,
                                                double* __restrict__ nv)
 {
     const int64_t w = blockIdx.y;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (K + 1) * nh) return;
+    if (t >= (n1 - n0) * nh) return;
     const double* c = wc + w * WC;
     if (c[WC_VALID] == 0.0) return;
-    const int64_t k = t / nh;
-    const int n = (int)(t - k * nh) + 1;
-    if (k > (int64_t)c[WC_KW]) return;
+    const int64_t k = n0 + t / nh;
+    const int n = (int)(t - (k - n0) * nh) + 1;
+    if (k > (int64_t)c[WC_KSEG + seg]) return;
     const double* o = orb + (w * (K + 1) + k) * 10;
     const double Ms = c[WC_MS], mus = c[WC_MUS];
     const double nu = o[1], e = o[3], dnu = o[6], de = o[8];
@@ -316,23 +361,23 @@ __global__ void __launch_bounds__(256) k_nodes(int64_t K, int nh, const double* 
     q[4] = A * pm.c; q[5] = dA * pm.c + A * pm.dc * de;
 }
 
-// interval tables: for (walker, interval k < K_w, harmonic n) the power-basis
+// interval tables: for (walker, interval k in [k0, k1), k < K_w, harmonic n) the power-basis
 // Hermite cubics of the three amplitudes, and (n = 1) of Phi, nu, gamma~, alpha
 template <typename HT>
-__global__ void __launch_bounds__(256) k_tables(int64_t K, int nh, double h,
-                                                const double* __restrict__ wc,
+__global__ void __launch_bounds__(256) k_tables(int64_t K, int nh, double h, int64_t k0, int64_t k1,
+                                                int seg, const double* __restrict__ wc,
                                                 const double* __restrict__ orb,
                                                 const double* __restrict__ nv,
                                                 double* __restrict__ co, HT* __restrict__ ch)
 {
     const int64_t w = blockIdx.y;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= K * nh) return;
+    if (t >= (k1 - k0) * nh) return;
     const double* c = wc + w * WC;
     if (c[WC_VALID] == 0.0) return;
-    const int64_t k = t / nh;
-    const int n = (int)(t - k * nh) + 1;
-    if (k >= (int64_t)c[WC_KW]) return;
+    const int64_t k = k0 + t / nh;
+    const int n = (int)(t - (k - k0) * nh) + 1;
+    if (k >= (int64_t)c[WC_KSEG + seg]) return;
     if (n == 1) {  // orbital interpolants: Phi, nu, gamma~, alpha
         const double* o0 = orb + (w * (K + 1) + k) * 10;
         const double* o1 = o0 + 10;
@@ -383,7 +428,7 @@ static GL8 make_gl8()
 }
 
 hipError_t launch_walker_setup(const Plan& p, const double* params, int64_t B, void* ws,
-                               hipStream_t s)
+                               int64_t k1, hipStream_t s)
 {
     static const GL8 gl = make_gl8();
     char* base = (char*)ws;
@@ -391,31 +436,53 @@ hipError_t launch_walker_setup(const Plan& p, const double* params, int64_t B, v
     dim3 grid((unsigned)((B + 63) / 64));
     trace_mark(ST_SETUP, s, true);
     hipLaunchKernelGGL(k_walker_setup, grid, dim3(64), 0, s, params, B, p.K, h,
-                       (double)p.N * p.dt, gl, (double*)(base + p.off_wc),
+                       (double)p.N * p.dt, gl, k1, (double*)(base + p.off_wc),
                        (double*)(base + p.off_orb));
     trace_mark(ST_SETUP, s, false);
     return hipGetLastError();
 }
 
-hipError_t launch_tables(const Plan& p, int64_t B, void* ws, hipStream_t s)
+hipError_t launch_walker_resume(const Plan& p, int64_t B, void* ws, int64_t k0, int64_t k1,
+                                int seg, hipStream_t s)
 {
+    if (seg < 1 || seg >= kMaxSeg || k0 < 0 || k1 < k0 || k1 > p.K) return hipErrorInvalidValue;
+    char* base = (char*)ws;
+    const double h = p.dt * (double)p.L;
+    dim3 grid((unsigned)((B + 63) / 64));
+    trace_mark(ST_SETUP, s, true);
+    hipLaunchKernelGGL(k_walker_resume, grid, dim3(64), 0, s, B, p.K, h, k0, k1, seg,
+                       (double*)(base + p.off_wc), (double*)(base + p.off_orb));
+    trace_mark(ST_SETUP, s, false);
+    return hipGetLastError();
+}
+
+hipError_t launch_tables(const Plan& p, int64_t B, void* ws, int64_t k0, int64_t k1, int seg,
+                         hipStream_t s)
+{
+    if (seg < 0 || seg >= kMaxSeg || k0 < 0 || k1 < k0 || k1 > p.K) return hipErrorInvalidValue;
     char* base = (char*)ws;
     const double h = p.dt * (double)p.L;
     const double* wc = (const double*)(base + p.off_wc);
     const double* orb = (const double*)(base + p.off_orb);
     double* nv = (double*)(base + p.off_nv);
     trace_mark(ST_TABLES, s, true);
-    const int64_t nn = (p.K + 1) * p.nh;
+    // nodes k0 .. k1; node k0 of a later segment was the previous one's last
+    const int64_t n0 = (seg == 0) ? 0 : k0 + 1, n1 = k1 + 1;
+    const int64_t nn = (n1 - n0) * p.nh;
     hipLaunchKernelGGL(k_nodes, dim3((unsigned)((nn + 255) / 256), (unsigned)B), dim3(256), 0, s,
-                       p.K, p.nh, wc, orb, nv);
-    const int64_t n = p.K * p.nh;
+                       p.K, p.nh, n0, n1, seg, wc, orb, nv);
+    const int64_t n = (k1 - k0) * p.nh;
     dim3 grid((unsigned)((n + 255) / 256), (unsigned)B);
-    if (p.prec == EMRI_FP64)
-        hipLaunchKernelGGL(k_tables<double>, grid, dim3(256), 0, s, p.K, p.nh, h, wc, orb, nv,
-                           (double*)(base + p.off_co), (double*)(base + p.off_ch));
-    else
-        hipLaunchKernelGGL(k_tables<float>, grid, dim3(256), 0, s, p.K, p.nh, h, wc, orb, nv,
-                           (double*)(base + p.off_co), (float*)(base + p.off_ch));
+    if (n > 0) {
+        if (p.prec == EMRI_FP64)
+            hipLaunchKernelGGL(k_tables<double>, grid, dim3(256), 0, s, p.K, p.nh, h, k0, k1, seg,
+                               wc, orb, nv, (double*)(base + p.off_co),
+                               (double*)(base + p.off_ch));
+        else
+            hipLaunchKernelGGL(k_tables<float>, grid, dim3(256), 0, s, p.K, p.nh, h, k0, k1, seg,
+                               wc, orb, nv, (double*)(base + p.off_co),
+                               (float*)(base + p.off_ch));
+    }
     trace_mark(ST_TABLES, s, false);
     return hipGetLastError();
 }

@@ -202,6 +202,35 @@ def test_batch_invariance_and_chunking(E):
     assert np.array_equal(again, full)
 
 
+@pytest.mark.parametrize("segs", [2, 5, 16])
+def test_orbit_segments_bitwise(E, monkeypatch, segs):
+    """The orbit integrated in segments, with the tables and samples of each
+    finished segment built on a second stream, gives the same bits as one
+    segment: edge walkers, and fast inspirals that reach the LSO inside a
+    middle segment."""
+    w = plunge_workload(8)
+    P = np.concatenate([W.walkers(w, B=3), edge_walkers(w)])
+    _, kw = O.orbit(P[:3], ocfg(w))
+    say("segments", segs, "plunge nodes", kw, "of", w.n_intervals)
+    cfg = E.Config.from_workload(w)
+    monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", "1")
+    ref = E.waveform_batch(gpu_params(P), cfg).cpu().numpy()
+    monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", str(segs))
+    got = E.waveform_batch(gpu_params(P), cfg).cpu().numpy()
+    assert np.array_equal(got, ref)
+    # likelihood through the same pipeline, twice (events and streams reused)
+    ws = W.small("fp64", n_harm=6)
+    Q = edge_walkers(ws)
+    d, S = oracle_dataset(ws, True)
+    dd, ss = to_device_data(d, S)
+    cs = E.Config.from_workload(ws)
+    monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", "1")
+    one = E.loglike_batch(gpu_params(Q), dd, ss, cs).cpu().numpy()
+    monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", str(segs))
+    for _ in range(2):
+        assert np.array_equal(E.loglike_batch(gpu_params(Q), dd, ss, cs).cpu().numpy(), one)
+
+
 # ---------------------------------------------------------- full-size cases
 def test_config1_full_parity(E):
     """Config 1 (FP64, B=32, 30 days, 2^18 samples, 16 harmonics): every walker."""

@@ -43,7 +43,12 @@ def alone(E, cfg, dd, ss, P):
                              cfg).cpu().numpy()
 
 
-def test_served_equals_alone_in_the_mix(E):
+@pytest.mark.parametrize("segs", [None, "3"])
+def test_served_equals_alone_in_the_mix(E, monkeypatch, segs):
+    """segs = "3": the captured graphs hold the orbit-segment pipeline's
+    second stream (fork and join inside the capture)"""
+    if segs:
+        monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", segs)
     sets = two_datasets(E)
     arena = torch.empty(3 << 30, dtype=torch.uint8, device="cuda")
     reqs = []

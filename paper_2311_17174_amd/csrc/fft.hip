@@ -29,23 +29,33 @@ TwLayout tw_layout(const Plan& p)
     t.nB = p.R1;
     t.nlo = (int64_t)1 << p.s_lo;
     t.nhi = p.N >> p.s_lo;
+    // pass-A output twiddle W_N^{c k2}, k2 = t + i R2/16, as the product
+    // Tb[t][c] Ts[i][c] with Tb[t][c] = W_N^{c t}, Ts[i][c] = W_N^{c i R2/16}
+    t.nTb = (p.R2 / 16) * p.R1;
+    t.nTs = 16 * p.R1;
     size_t o = 0;
     t.oA = o; o += align256(t.nA * 16);
     t.oB = o; o += align256(t.nB * 16);
     t.olo = o; o += align256(t.nlo * 16);
     t.ohi = o; o += align256(t.nhi * 16);
+    t.oTb = o; o += align256(t.nTb * 16);
+    t.oTs = o; o += align256(t.nTs * 16);
     t.fA = o; o += align256(t.nA * 8);
     t.fB = o; o += align256(t.nB * 8);
     t.flo = o; o += align256(t.nlo * 8);
     t.fhi = o; o += align256(t.nhi * 8);
+    t.fTb = o; o += align256(t.nTb * 8);
+    t.fTs = o; o += align256(t.nTs * 8);
     t.bytes = o;
     return t;
 }
 
-// table entry i of one of four tables: W_den^{i * mul} = exp(-2 pi i i mul / den)
-__global__ void k_twiddles(int64_t nA, int64_t nB, int64_t nlo, int64_t nhi, int64_t N,
-                           int s_lo, double2* tA, double2* tB, double2* tlo, double2* thi,
-                           float2* fA, float2* fB, float2* flo, float2* fhi)
+// entry i of the concatenated tables: W^{num} = exp(-2 pi i num / den)
+__global__ void k_twiddles(int64_t nA, int64_t nB, int64_t nlo, int64_t nhi, int64_t nTb,
+                           int64_t nTs, int64_t N, int64_t R1, int64_t R2, int s_lo,
+                           double2* tA, double2* tB, double2* tlo, double2* thi, double2* tTb,
+                           double2* tTs, float2* fA, float2* fB, float2* flo, float2* fhi,
+                           float2* fTb, float2* fTs)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double2* d;
@@ -58,6 +68,12 @@ __global__ void k_twiddles(int64_t nA, int64_t nB, int64_t nlo, int64_t nhi, int
         d = thi; f = fhi;
         // exponent i 2^s_lo of W_N, reduced: (i 2^s_lo) / N = i / (N >> s_lo)
         num = (double)i; den = (double)(N >> s_lo);
+    } else if ((i -= nhi) < nTb) {
+        d = tTb; f = fTb;
+        num = (double)((i / R1) * (i % R1)); den = (double)N;        // c t < N
+    } else if ((i -= nTb) < nTs) {
+        d = tTs; f = fTs;
+        num = (double)((i / R1) * (R2 / 16) * (i % R1)); den = (double)N;   // < N
     } else return;
     double s, c;
     sincospi(-2.0 * num / den, &s, &c);
@@ -69,13 +85,14 @@ hipError_t launch_twiddles(const Plan& p, void* ws, hipStream_t s)
 {
     const TwLayout t = tw_layout(p);
     char* b = (char*)ws + p.off_tw;
-    const int64_t n = t.nA + t.nB + t.nlo + t.nhi;
+    const int64_t n = t.nA + t.nB + t.nlo + t.nhi + t.nTb + t.nTs;
     trace_mark(ST_TWIDDLE, s, true);
     hipLaunchKernelGGL(k_twiddles, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, t.nA,
-                       t.nB, t.nlo, t.nhi, p.N, p.s_lo, (double2*)(b + t.oA),
-                       (double2*)(b + t.oB), (double2*)(b + t.olo), (double2*)(b + t.ohi),
+                       t.nB, t.nlo, t.nhi, t.nTb, t.nTs, p.N, p.R1, p.R2, p.s_lo,
+                       (double2*)(b + t.oA), (double2*)(b + t.oB), (double2*)(b + t.olo),
+                       (double2*)(b + t.ohi), (double2*)(b + t.oTb), (double2*)(b + t.oTs),
                        (float2*)(b + t.fA), (float2*)(b + t.fB), (float2*)(b + t.flo),
-                       (float2*)(b + t.fhi));
+                       (float2*)(b + t.fhi), (float2*)(b + t.fTb), (float2*)(b + t.fTs));
     trace_mark(ST_TWIDDLE, s, false);
     return hipGetLastError();
 }
@@ -150,6 +167,53 @@ __global__ void __launch_bounds__(MAXT) k_fft_cols(const typename C2<R>::T* in,
     }
 }
 
+// pass A with 16 values per lane: TA columns per workgroup, TA * L / 16
+// lanes, lane (col, t) = (tid mod TA, tid / TA) holding the positions
+// t + i L/16 of its column.  SPLIT: re and im share one LDS array in turn.
+template <typename R, int MAXT, bool SPLIT>
+__global__ void __launch_bounds__(MAXT) k_fft_cols16(const typename C2<R>::T* in,
+                                                     typename C2<R>::T* out, int64_t N,
+                                                     int64_t R1, int L, int lgL, int TA, int s_lo,
+                                                     const typename C2<R>::T* __restrict__ twL,
+                                                     const typename C2<R>::T* __restrict__ tTb,
+                                                     const typename C2<R>::T* __restrict__ tTs)
+{
+    using T2 = typename C2<R>::T;
+    extern __shared__ unsigned char smem_raw[];
+    R* sre = (R*)smem_raw;
+    const int LP = col_stride<R>(L, TA);
+    R* sim = SPLIT ? sre : sre + TA * LP;
+    (void)s_lo;
+    const int64_t w = blockIdx.y;
+    const int64_t c0 = xcd_tile(blockIdx.x, gridDim.x) * TA;
+    const T2* src = in + w * N;
+    T2* dst = out + w * N;
+    int tsh = 0;
+    while ((1 << tsh) < TA) ++tsh;
+    const int col = threadIdx.x & (TA - 1), t = threadIdx.x >> tsh;
+    const int L16 = L / 16;
+    const int64_t cg = c0 + col;
+    R xr[16], xi[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const T2 v = src[cg + R1 * (int64_t)(t + i * L16)];
+        xr[i] = v.x;
+        xi[i] = v.y;
+    }
+    const T2 bt = tTb[(int64_t)t * R1 + cg];        // W_N^{cg t}
+    fft16_regs<R, SPLIT>(sre + col * LP, sim + col * LP, L, lgL, t, twL, xr, xi);
+    const int RL = last_radix16(lgL);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int i = slot_pos16(s, RL);
+        const T2 st = tTs[(int64_t)i * R1 + cg];     // W_N^{cg i L/16}
+        const R wr = bt.x * st.x - bt.y * st.y, wi = bt.x * st.y + bt.y * st.x;
+        R yr = xr[s], yi = xi[s];
+        cmul(yr, yi, wr, wi);
+        dst[cg + R1 * (int64_t)(t + i * L16)] = T2{yr, yi};
+    }
+}
+
 // pass B: one row of length L (= R1) per workgroup, L / 8 lanes, in place;
 // lane t keeps the positions t + i L/8 in registers for the first and last
 // radix stages
@@ -190,27 +254,44 @@ static hipError_t fft_typed(const Plan& p, int64_t B, const void* in, void* ws, 
     const T2* tB = (const T2*)(twb + (f64 ? t.oB : t.fB));
     const T2* tlo = (const T2*)(twb + (f64 ? t.olo : t.flo));
     const T2* thi = (const T2*)(twb + (f64 ? t.ohi : t.fhi));
+    const T2* tTb = (const T2*)(twb + (f64 ? t.oTb : t.fTb));
+    const T2* tTs = (const T2*)(twb + (f64 ? t.oTs : t.fTs));
     T2* z = (T2*)(base + p.off_z);
     const int LA = (int)p.R2, LB = (int)p.R1;
-    const size_t ldsA = (size_t)p.TA * col_stride<R>(LA, p.TA) * 2 * sizeof(R);
+    const size_t ldsA =
+        (size_t)p.TA * col_stride<R>(LA, p.TA) * (p.split ? 1 : 2) * sizeof(R);
     const size_t ldsB = (size_t)padded_len(LB) * 2 * sizeof(R);
-    hipError_t ae = allow_lds((const void*)k_fft_cols<R, 512>, ldsA);
-    if (ae == hipSuccess) ae = allow_lds((const void*)k_fft_cols<R, 1024>, ldsA);
+    const void* kA;
+    const int ntA = p.TA * LA / p.colsE, ntB = LB / 8;
+    if (ntA > 1024 || ntB > 512 || LA < p.colsE) return hipErrorInvalidValue;
+    if (p.colsE == 16) {
+        if (p.split) kA = ntA <= 512 ? (const void*)k_fft_cols16<R, 512, true>
+                                     : (const void*)k_fft_cols16<R, 1024, true>;
+        else kA = ntA <= 512 ? (const void*)k_fft_cols16<R, 512, false>
+                             : (const void*)k_fft_cols16<R, 1024, false>;
+    } else {
+        kA = ntA <= 512 ? (const void*)k_fft_cols<R, 512> : (const void*)k_fft_cols<R, 1024>;
+    }
+    hipError_t ae = allow_lds(kA, ldsA);
     if (ae == hipSuccess && rows) ae = allow_lds((const void*)k_fft_rows<R, 512>, ldsB);
     if (ae != hipSuccess) return ae;
-    const int ntA = p.TA * LA / 8, ntB = LB / 8;
-    if (ntA > 1024 || ntB > 512) return hipErrorInvalidValue;
     const T2* src = (const T2*)(in ? in : z);
     trace_mark(ST_FFT_COLS, s, true);
-    if (ntA <= 512)
-        hipLaunchKernelGGL((k_fft_cols<R, 512>), dim3((unsigned)(p.R1 / p.TA), (unsigned)B),
-                           dim3((unsigned)ntA), ldsA, s, src, z, p.N, p.R1, LA, p.m2, p.TA,
-                           p.s_lo, tA, tlo, thi);
-    else
-        hipLaunchKernelGGL((k_fft_cols<R, 1024>), dim3((unsigned)(p.R1 / p.TA), (unsigned)B),
-                           dim3((unsigned)ntA), ldsA, s, src, z, p.N, p.R1, LA, p.m2, p.TA,
-                           p.s_lo, tA, tlo, thi);
+    {
+        // the pass-A kernels share one signature; arguments by address
+        const T2* a_in = src;
+        T2* a_out = z;
+        int64_t a_N = p.N, a_R1 = p.R1;
+        int a_L = LA, a_lgL = p.m2, a_TA = p.TA, a_slo = p.s_lo;
+        const T2* a_tw = tA;
+        const T2* a_tlo = (p.colsE == 16) ? tTb : tlo;   // the 16-per-lane kernel takes
+        const T2* a_thi = (p.colsE == 16) ? tTs : thi;   // the two factor tables
+        void* args[] = {&a_in, &a_out, &a_N, &a_R1, &a_L, &a_lgL, &a_TA, &a_slo, &a_tw, &a_tlo, &a_thi};
+        ae = hipLaunchKernel(kA, dim3((unsigned)(p.R1 / p.TA), (unsigned)B), dim3((unsigned)ntA),
+                             args, ldsA, s);
+    }
     trace_mark(ST_FFT_COLS, s, false);
+    if (ae != hipSuccess) return ae;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !rows) return e;
     trace_mark(ST_FFT_ROWS, s, true);

@@ -270,4 +270,211 @@ __device__ __forceinline__ void fft_regs(R* re, R* im, int L, int lgL, int t,
     }
 }
 
+// ===========================================================================
+// 16 values per lane.  A column of L = 2^lgL >= 16 points is transformed by
+// L/16 lanes: radix-16 Stockham stages, then one radix-2/4/8 stage for the
+// remainder.  Lane t holds, on entry, the positions t + i L/16 (i = 0..15),
+// runs the first stage on them, exchanges through LDS between stages, and
+// keeps the last stage's outputs (again positions t + i L/16) in registers.
+// ===========================================================================
+
+// 16-point DFT in registers, natural order in and out, as 4 x 4:
+// X[k1 + 4 k2] = sum_n2 W4^{n2 k2} W16^{n2 k1} sum_n1 a[4 n1 + n2] W4^{n1 k1}
+template <typename R>
+__device__ __forceinline__ void dft16(R* xr, R* xi)
+{
+    const R c1 = (R)0.92387953251128675612818318939678828682;   // cos(pi/8)
+    const R s1 = (R)0.38268343236508977172845998403039886676;   // sin(pi/8)
+    const R h = (R)0.70710678118654752440084436210484903928;
+    R yr[16], yi[16];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+        R tr[4] = {xr[n2], xr[4 + n2], xr[8 + n2], xr[12 + n2]};
+        R ti[4] = {xi[n2], xi[4 + n2], xi[8 + n2], xi[12 + n2]};
+        dft4(tr, ti);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) { yr[4 * k1 + n2] = tr[k1]; yi[4 * k1 + n2] = ti[k1]; }
+    }
+    // y[4 k1 + n2] *= W16^{n2 k1}, W16^m = cos(2 pi m/16) - i sin(2 pi m/16)
+    cmul(yr[5], yi[5], c1, -s1);                                  // m = 1
+    { const R a = yr[6], b = yi[6]; yr[6] = h * (a + b); yi[6] = h * (b - a); }    // m = 2
+    cmul(yr[7], yi[7], s1, -c1);                                  // m = 3
+    { const R a = yr[9], b = yi[9]; yr[9] = h * (a + b); yi[9] = h * (b - a); }    // m = 2
+    { const R a = yr[10]; yr[10] = yi[10]; yi[10] = -a; }         // m = 4
+    { const R a = yr[11], b = yi[11]; yr[11] = h * (b - a); yi[11] = -h * (a + b); } // m = 6
+    cmul(yr[13], yi[13], s1, -c1);                                // m = 3
+    { const R a = yr[14], b = yi[14]; yr[14] = h * (b - a); yi[14] = -h * (a + b); } // m = 6
+    cmul(yr[15], yi[15], -c1, s1);                                // m = 9
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        R tr[4] = {yr[4 * k1], yr[4 * k1 + 1], yr[4 * k1 + 2], yr[4 * k1 + 3]};
+        R ti[4] = {yi[4 * k1], yi[4 * k1 + 1], yi[4 * k1 + 2], yi[4 * k1 + 3]};
+        dft4(tr, ti);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) { xr[k1 + 4 * k2] = tr[k2]; xi[k1 + 4 * k2] = ti[k2]; }
+    }
+}
+
+// radix-RR DFTs of the lane's 16/RR butterflies (slots b RR .. b RR + RR-1)
+template <typename R, int RR>
+__device__ __forceinline__ void dft_slots16(R (&xr)[16], R (&xi)[16])
+{
+    if constexpr (RR == 16) {
+        dft16(xr, xi);
+    } else if constexpr (RR == 8) {
+        dft8(xr, xi);
+        dft8(xr + 8, xi + 8);
+    } else if constexpr (RR == 4) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) dft4(xr + 4 * b, xi + 4 * b);
+    } else {
+#pragma unroll
+        for (int b = 0; b < 8; ++b) dft2(xr[2 * b], xi[2 * b], xr[2 * b + 1], xi[2 * b + 1]);
+    }
+}
+
+// twiddles of a stage with Ns > 1: input r of butterfly b times w^r,
+// w = W_L^{k tws}; w, w^2, w^4, w^8 from the table, the other powers as
+// products (at most three factors), applied as they are formed
+template <typename R, int RR>
+__device__ __forceinline__ void twiddle_slots16(R (&xr)[16], R (&xi)[16], int L, int Ns, int t,
+                                                const typename C2<R>::T* __restrict__ tw)
+{
+    using T2 = typename C2<R>::T;
+    constexpr int NB = 16 / RR;
+    const int tws = L / (Ns * RR);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = t + b * (L / 16);
+        const int k = j & (Ns - 1);
+        if (k == 0) continue;
+        R* vr = xr + b * RR;
+        R* vi = xi + b * RR;
+        const T2 w1 = tw[k * tws];
+        cmul(vr[1], vi[1], w1.x, w1.y);
+        if constexpr (RR >= 4) {
+            const T2 w2 = tw[2 * k * tws];
+            cmul(vr[2], vi[2], w2.x, w2.y);
+            const R w3r = w1.x * w2.x - w1.y * w2.y, w3i = w1.x * w2.y + w1.y * w2.x;
+            cmul(vr[3], vi[3], w3r, w3i);
+            if constexpr (RR >= 8) {
+                const T2 w4 = tw[4 * k * tws];
+                cmul(vr[4], vi[4], w4.x, w4.y);
+                const R w5r = w1.x * w4.x - w1.y * w4.y, w5i = w1.x * w4.y + w1.y * w4.x;
+                cmul(vr[5], vi[5], w5r, w5i);
+                const R w6r = w2.x * w4.x - w2.y * w4.y, w6i = w2.x * w4.y + w2.y * w4.x;
+                cmul(vr[6], vi[6], w6r, w6i);
+                const R w7r = w3r * w4.x - w3i * w4.y, w7i = w3r * w4.y + w3i * w4.x;
+                cmul(vr[7], vi[7], w7r, w7i);
+                if constexpr (RR == 16) {
+                    const T2 w8 = tw[8 * k * tws];
+                    cmul(vr[8], vi[8], w8.x, w8.y);
+                    const R a[7][2] = {{w1.x, w1.y}, {w2.x, w2.y}, {w3r, w3i}, {w4.x, w4.y},
+                                       {w5r, w5i}, {w6r, w6i}, {w7r, w7i}};
+#pragma unroll
+                    for (int r = 0; r < 7; ++r) {
+                        const R pr = a[r][0] * w8.x - a[r][1] * w8.y;
+                        const R pi = a[r][0] * w8.y + a[r][1] * w8.x;
+                        cmul(vr[9 + r], vi[9 + r], pr, pi);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// stage outputs to LDS: output r of butterfly b (j = t + b L/16, k = j mod
+// Ns) goes to position (j - k) RR + k + r Ns
+template <typename R, int RR>
+__device__ __forceinline__ void put_slots16(R* buf, const R (&x)[16], int L, int Ns, int t)
+{
+#pragma unroll
+    for (int b = 0; b < 16 / RR; ++b) {
+        const int j = t + b * (L / 16);
+        const int k = j & (Ns - 1);
+        const int base = (j - k) * RR + k;
+#pragma unroll
+        for (int r = 0; r < RR; ++r) buf[px(base + r * Ns)] = x[b * RR + r];
+    }
+}
+
+// stage inputs from LDS: input r of butterfly b sits at position j + r L/RR
+template <typename R, int RR>
+__device__ __forceinline__ void get_slots16(const R* buf, R (&x)[16], int L, int t)
+{
+#pragma unroll
+    for (int b = 0; b < 16 / RR; ++b) {
+        const int j = t + b * (L / 16);
+#pragma unroll
+        for (int r = 0; r < RR; ++r) x[b * RR + r] = buf[px(j + r * (L / RR))];
+    }
+}
+
+// exchange between a stage of radix RA (outputs) and one of radix RB
+// (inputs).  SPLIT passes the real parts first and then the imaginary
+// parts through one array (half the LDS, two more barriers); otherwise re
+// and im go through two arrays at once.  Starts with a barrier, so the
+// caller's previous reads of the arrays are complete before they are reused.
+template <typename R, int RA, int RB, bool SPLIT>
+__device__ __forceinline__ void exchange16(R* re, R* im, R (&xr)[16], R (&xi)[16], int L, int Ns,
+                                           int t)
+{
+    __syncthreads();
+    if constexpr (SPLIT) {
+        put_slots16<R, RA>(re, xr, L, Ns, t);
+        __syncthreads();
+        get_slots16<R, RB>(re, xr, L, t);
+        __syncthreads();
+        put_slots16<R, RA>(re, xi, L, Ns, t);
+        __syncthreads();
+        get_slots16<R, RB>(re, xi, L, t);
+    } else {
+        put_slots16<R, RA>(re, xr, L, Ns, t);
+        put_slots16<R, RA>(im, xi, L, Ns, t);
+        __syncthreads();
+        get_slots16<R, RB>(re, xr, L, t);
+        get_slots16<R, RB>(im, xi, L, t);
+    }
+}
+
+// radix of the last stage of an L = 2^lgL point transform (16 if lgL is a
+// multiple of 4), and the position index i (position t + i L/16) that slot
+// s holds after it: s = b RR + r holds i = b + r 16/RR
+__host__ __device__ inline int last_radix16(int lgL) { return 1 << ((lgL & 3) ? (lgL & 3) : 4); }
+__device__ __forceinline__ int slot_pos16(int s, int RL) { return (s % RL) * (16 / RL) + s / RL; }
+
+// The whole L-point transform (L = 2^lgL, 16 <= L <= 4096) of lane t's
+// column: on entry x holds positions t + i L/16 (i = 0..15); on exit slot s
+// holds the transform at position t + slot_pos16(s, last_radix16(lgL)) L/16.
+// Stage radices: 16 as often as fits, then the remainder (2, 4 or 8).
+// Every lane of the workgroup must call it with the same L (barriers).
+template <typename R, bool SPLIT>
+__device__ __forceinline__ void fft16_regs(R* re, R* im, int L, int lgL, int t,
+                                           const typename C2<R>::T* __restrict__ tw,
+                                           R (&xr)[16], R (&xi)[16])
+{
+    const int n16 = lgL / 4, rem = lgL - 4 * n16;
+    dft_slots16<R, 16>(xr, xi);              // stage 1: Ns = 1, no twiddles
+    int Ns = 16;                             // product of the radices so far
+    for (int st = 1; st < n16; ++st) {
+        exchange16<R, 16, 16, SPLIT>(re, im, xr, xi, L, Ns / 16, t);
+        twiddle_slots16<R, 16>(xr, xi, L, Ns, t, tw);
+        dft_slots16<R, 16>(xr, xi);
+        Ns *= 16;
+    }
+    if (rem == 1) {
+        exchange16<R, 16, 2, SPLIT>(re, im, xr, xi, L, Ns / 16, t);
+        twiddle_slots16<R, 2>(xr, xi, L, Ns, t, tw);
+        dft_slots16<R, 2>(xr, xi);
+    } else if (rem == 2) {
+        exchange16<R, 16, 4, SPLIT>(re, im, xr, xi, L, Ns / 16, t);
+        twiddle_slots16<R, 4>(xr, xi, L, Ns, t, tw);
+        dft_slots16<R, 4>(xr, xi);
+    } else if (rem == 3) {
+        exchange16<R, 16, 8, SPLIT>(re, im, xr, xi, L, Ns / 16, t);
+        twiddle_slots16<R, 8>(xr, xi, L, Ns, t, tw);
+        dft_slots16<R, 8>(xr, xi);
+    }
+}
+
 }  // namespace emri

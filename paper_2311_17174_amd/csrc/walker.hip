@@ -247,9 +247,18 @@ __global__ void __launch_bounds__(64) k_walker_resume(int64_t B, int64_t K, doub
 }
 
 // ---------------------------------------------------------------------------
-// Bessel functions J_{n-3..n+3}(X), X >= 0, by downward recurrence
-// J_{q-1} = (2q/X) J_q - J_{q+1} from a high even order, normalised with
-// J_0 + 2 (J_2 + J_4 + ...) = 1.  A sliding window of seven orders is kept.
+// Bessel functions J_{n-3..n+3}(X), X = n e >= 0, by Miller's downward
+// recurrence J_{q-1} = (2q/X) J_q - J_{q+1} from a trial start, normalised
+// with J_0 + 2 (J_2 + J_4 + ...) = 1.
+//
+// Start order S: above the turning point the recurrence amplifies the
+// unwanted solution against J by at least (2k - X)/X per step, and the
+// relative error of the orders kept is about the inverse square of the
+// product of those factors from top = max(n + 3, ceil X) to S.  S is the
+// first order where that product exceeds 1e11 (error ~1e-22), capped at
+// top + 10 + sqrt(40 top).  The recurrence runs in three loops: down to
+// order n + 3 (two values live), the seven orders kept, then down to 0;
+// each step is one product, one FMA and the norm update.
 // ---------------------------------------------------------------------------
 __device__ void bessel7(int n, double X, double J[7])
 {
@@ -257,42 +266,64 @@ __device__ void bessel7(int n, double X, double J[7])
         for (int i = 0; i < 7; ++i) J[i] = (n - 3 + i == 0) ? 1.0 : 0.0;
         return;
     }
-    const int lo = n - 3 > 0 ? n - 3 : 0;
-    // start order: the relative error of the recurrence at the orders kept
-    // is ~(J_S / J_top)^2, negligible (< 1e-20 for X <= 64) for
-    // S = top + 10 + sqrt(40 top)
-    const int top = max(n + 3, (int)ceil(X));
-    int S = top + 10 + (int)sqrt(40.0 * top);
-    S += S & 1;
-    // window w[i] = J_{q+i} once order q has been produced
-    double w0 = 1e-280, w1 = 0.0, w2 = 0.0, w3 = 0.0, w4 = 0.0, w5 = 0.0, w6 = 0.0;
-    double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0, s6 = 0;
-    double norm = (S & 1) ? 0.0 : 2.0 * w0;  // S even: J_S enters the sum
-    const double iX2 = 2.0 / X;
-    for (int q = S; q >= 1; --q) {
-        const double next = (q * iX2) * w0 - w1;  // J_{q-1}
-        w6 = w5; w5 = w4; w4 = w3; w3 = w2; w2 = w1; w1 = w0; w0 = next;
-        const int o = q - 1;
-        if (o > 0 && !(o & 1)) norm += 2.0 * w0;
-        if (fabs(w0) > 1e200) {  // keep the saved window on the running scale
+    const int hi = n + 3, lo = n - 3;
+    const int top = max(hi, (int)ceil(X));
+    const double iX = 1.0 / X, iX2 = 2.0 * iX;
+    const int cap = top + 10 + (int)sqrt(40.0 * top);
+    int S = top;
+    double prod = 1.0;
+    while (S < cap && prod < 1e11) {
+        ++S;
+        prod *= (2.0 * S - X) * iX;
+    }
+    S += S & 1;                       // even: J_S enters the norm
+    // a = J_q, b = J_{q+1} (unnormalised), dq = q; the order produced next,
+    // q - 1, enters the norm with weight m (2 for even orders, 0 for odd)
+    double a = 1e-280, b = 0.0, dq = (double)S, m = 0.0, norm = 2.0 * a;
+    double w[7] = {0, 0, 0, 0, 0, 0, 0};
+    auto step = [&]() {
+        const double next = (dq * iX2) * a - b;
+        dq -= 1.0;
+        b = a;
+        a = next;
+        norm = fma(m, a, norm);
+        m = 2.0 - m;
+    };
+    auto rescale = [&]() {            // keep the values on the running scale
+        if (fabs(a) > 1e200) {
             const double r = 1e-200;
-            w0 *= r; w1 *= r; w2 *= r; w3 *= r; w4 *= r; w5 *= r; w6 *= r; norm *= r;
-            if (o < lo) { s0 *= r; s1 *= r; s2 *= r; s3 *= r; s4 *= r; s5 *= r; s6 *= r; }
+            a *= r; b *= r; norm *= r;
+#pragma unroll
+            for (int k = 0; k < 7; ++k) w[k] *= r;
         }
-        if (o == lo) { s0 = w0; s1 = w1; s2 = w2; s3 = w3; s4 = w4; s5 = w5; s6 = w6; }
+    };
+    for (int q = S; q > hi; --q) {
+        step();
+        rescale();
     }
-    norm += w0;  // J_0
+    w[6] = a;                         // J_{n+3}
+#pragma unroll
+    for (int i = 5; i >= 0; --i) {
+        if (lo + i >= 0) {
+            step();
+            w[i] = a;                 // J_{n-3+i}
+            rescale();
+        }
+    }
+    for (int o = lo - 1; o >= 0; --o) {
+        step();
+        rescale();
+    }
+    norm -= a;                        // a = J_0 was counted twice
+    // orders below zero (n < 3): J_{-k} = (-1)^k J_k
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        const int o = lo + i;
+        if (o < 0) w[i] = ((-o) & 1 ? -1.0 : 1.0) * w[-o - lo];
+    }
     const double in = 1.0 / norm;
-    if (n >= 3) {
-        J[0] = s0 * in; J[1] = s1 * in; J[2] = s2 * in; J[3] = s3 * in;
-        J[4] = s4 * in; J[5] = s5 * in; J[6] = s6 * in;
-    } else if (n == 2) {  // orders -1..5 from J_0..J_6
-        J[0] = -s1 * in; J[1] = s0 * in; J[2] = s1 * in; J[3] = s2 * in;
-        J[4] = s3 * in; J[5] = s4 * in; J[6] = s5 * in;
-    } else {              // n == 1: orders -2..4
-        J[0] = s2 * in; J[1] = -s1 * in; J[2] = s0 * in; J[3] = s1 * in;
-        J[4] = s2 * in; J[5] = s3 * in; J[6] = s4 * in;
-    }
+#pragma unroll
+    for (int i = 0; i < 7; ++i) J[i] = w[i] * in;
 }
 
 // values and e-derivatives of n P_n, n Q_n, 2 J_n at (n, e); A factor applied

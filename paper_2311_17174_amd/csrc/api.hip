@@ -157,12 +157,7 @@ emri_status make_plan(const emri_cfg* cfg, int64_t B, Plan* p, const char** err)
     int ta = (int)(run_bytes / q.esz);
     if (ta < 1) ta = 1;
     while (ta > 16) ta /= 2;
-    auto lds_a = [&](int t) {   // ta padded columns (fft_lds.hpp), re and im
-        const int L = (int)q.R2;
-        const int pl = ((L + (L >> 4)) + 15) & ~15;
-        const size_t arrays = q.split ? 1 : 2;
-        return (size_t)t * (pl + (t > 1 ? (int)(128 / q.hsz) / t : 0)) * q.hsz * arrays;
-    };
+    auto lds_a = [&](int t) { return cols_lds_bytes(q.prec, q.R2, t, q.split); };
     while (ta > 1 && (ta * q.R2 / q.colsE > 1024 || lds_a(ta) > 160 * 1024)) ta /= 2;
     q.TA = ta;
     q.s_lo = (m + 1) / 2;

@@ -105,7 +105,18 @@ hipError_t launch_twiddles(const Plan& p, void* ws, hipStream_t s)
 template <typename R>
 __host__ __device__ inline int col_stride(int L, int TA)
 {
-    return padded_len(L) + (TA > 1 ? (int)(128 / sizeof(R)) / TA : 0);
+#ifndef EMRI_LDS_CYCLE_BYTES
+#define EMRI_LDS_CYCLE_BYTES 128
+#endif
+    return padded_len<R>(L) + (TA > 1 ? (int)(EMRI_LDS_CYCLE_BYTES / sizeof(R)) / TA : 0);
+}
+
+// LDS bytes of a pass-A tile of TA columns of R2 points
+size_t cols_lds_bytes(int prec, int64_t R2, int TA, int split)
+{
+    const size_t arrays = split ? 1 : 2;
+    if (prec == EMRI_FP64) return (size_t)TA * col_stride<double>((int)R2, TA) * arrays * 8;
+    return (size_t)TA * col_stride<float>((int)R2, TA) * arrays * 4;
 }
 
 // XCD-aware tile order: the hardware hands consecutive workgroups to the 8
@@ -225,7 +236,7 @@ __global__ void __launch_bounds__(MAXT) k_fft_rows(typename C2<R>::T* z, int64_t
     using T2 = typename C2<R>::T;
     extern __shared__ unsigned char smem_raw[];
     R* sre = (R*)smem_raw;
-    R* sim = sre + padded_len(L);
+    R* sim = sre + padded_len<R>(L);
     const int64_t w = blockIdx.y;
     T2* row = z + w * N + (int64_t)blockIdx.x * L;
     const int t = threadIdx.x, L8 = L / 8;
@@ -260,7 +271,7 @@ static hipError_t fft_typed(const Plan& p, int64_t B, const void* in, void* ws, 
     const int LA = (int)p.R2, LB = (int)p.R1;
     const size_t ldsA =
         (size_t)p.TA * col_stride<R>(LA, p.TA) * (p.split ? 1 : 2) * sizeof(R);
-    const size_t ldsB = (size_t)padded_len(LB) * 2 * sizeof(R);
+    const size_t ldsB = (size_t)padded_len<R>(LB) * 2 * sizeof(R);
     const void* kA;
     const int ntA = p.TA * LA / p.colsE, ntB = LB / 8;
     if (ntA > 1024 || ntB > 512 || LA < p.colsE) return hipErrorInvalidValue;

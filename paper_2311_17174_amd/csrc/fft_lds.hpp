@@ -2,7 +2,7 @@
 // passes (fft.hip) and the fused row-FFT + likelihood kernel (like.hip).
 //
 // A column of L = 2^lgL complex values lives in LDS as two arrays re[], im[]
-// indexed through px(i) = i + i/16 (one pad slot per 16 elements), which makes
+// indexed through px<R>(i) = i + i/16 (one pad slot per 16 elements), which makes
 // the stride-8 writes of the first radix-8 stage bank-conflict free.  L/8
 // lanes transform one column: radix-8 Stockham stages (one radix-4 or radix-2
 // stage for the remainder), twiddles W_L^e from a device table, three table
@@ -20,9 +20,21 @@ template <typename R> struct C2;
 template <> struct C2<double> { using T = double2; };
 template <> struct C2<float> { using T = float2; };
 
-__device__ __host__ inline int px(int i) { return i + (i >> 4); }
+// pad one slot per 2^PadShift<R> elements
+#ifndef EMRI_PAD_F64
+#define EMRI_PAD_F64 4
+#endif
+#ifndef EMRI_PAD_F32
+#define EMRI_PAD_F32 4
+#endif
+template <typename R> struct PadShift;
+template <> struct PadShift<double> { static constexpr int v = EMRI_PAD_F64; };
+template <> struct PadShift<float> { static constexpr int v = EMRI_PAD_F32; };
+template <typename R>
+__device__ __host__ inline int px(int i) { return i + (i >> PadShift<R>::v); }
 // LDS elements (per re or im array) of a padded column of length L
-__host__ __device__ inline int padded_len(int L) { return ((L + (L >> 4)) + 15) & ~15; }
+template <typename R>
+__host__ __device__ inline int padded_len(int L) { return ((L + (L >> PadShift<R>::v)) + 15) & ~15; }
 
 // ---------------------------------------------------------------------------
 // small DFTs in registers, natural order out: b_q = sum_t a_t W_R^{t q}
@@ -102,8 +114,8 @@ __device__ __forceinline__ void lds_stage(R* re, R* im, int L, int Ns, int t,
         const int k = j & (Ns - 1);
 #pragma unroll
         for (int r = 0; r < RR; ++r) {
-            vr[b * RR + r] = re[px(j + r * stride)];
-            vi[b * RR + r] = im[px(j + r * stride)];
+            vr[b * RR + r] = re[px<R>(j + r * stride)];
+            vi[b * RR + r] = im[px<R>(j + r * stride)];
         }
         if (k > 0) {
             // twiddle powers w^r, r = 1..RR-1, w = W_L^{k tws}
@@ -143,8 +155,8 @@ __device__ __forceinline__ void lds_stage(R* re, R* im, int L, int Ns, int t,
         const int base = (j - k) * RR + k;
 #pragma unroll
         for (int r = 0; r < RR; ++r) {
-            re[px(base + r * Ns)] = vr[b * RR + r];
-            im[px(base + r * Ns)] = vi[b * RR + r];
+            re[px<R>(base + r * Ns)] = vr[b * RR + r];
+            im[px<R>(base + r * Ns)] = vi[b * RR + r];
         }
     }
     __syncthreads();
@@ -183,8 +195,8 @@ __device__ __forceinline__ void last_stage_to_regs(const R* re, const R* im, int
         const int j = t + b * (L / 8);   // j < Ns: k = j
 #pragma unroll
         for (int r = 0; r < RR; ++r) {
-            vr[b * RR + r] = re[px(j + r * stride)];
-            vi[b * RR + r] = im[px(j + r * stride)];
+            vr[b * RR + r] = re[px<R>(j + r * stride)];
+            vi[b * RR + r] = im[px<R>(j + r * stride)];
         }
         if (j > 0) {
             R wr[8], wi[8];
@@ -242,15 +254,15 @@ __device__ __forceinline__ void fft_regs(R* re, R* im, int L, int lgL, int t,
     if (nst == 1) {                        // L = 8: outputs already at t + i
         if (!OUT_REGS) {
 #pragma unroll
-            for (int r = 0; r < 8; ++r) { re[px(r)] = xr[r]; im[px(r)] = xi[r]; }
+            for (int r = 0; r < 8; ++r) { re[px<R>(r)] = xr[r]; im[px<R>(r)] = xi[r]; }
             __syncthreads();
         }
         return;
     }
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-        re[px(8 * t + r)] = xr[r];
-        im[px(8 * t + r)] = xi[r];
+        re[px<R>(8 * t + r)] = xr[r];
+        im[px<R>(8 * t + r)] = xi[r];
     }
     __syncthreads();
     int Ns = 8;
@@ -394,7 +406,7 @@ __device__ __forceinline__ void put_slots16(R* buf, const R (&x)[16], int L, int
         const int k = j & (Ns - 1);
         const int base = (j - k) * RR + k;
 #pragma unroll
-        for (int r = 0; r < RR; ++r) buf[px(base + r * Ns)] = x[b * RR + r];
+        for (int r = 0; r < RR; ++r) buf[px<R>(base + r * Ns)] = x[b * RR + r];
     }
 }
 
@@ -406,7 +418,7 @@ __device__ __forceinline__ void get_slots16(const R* buf, R (&x)[16], int L, int
     for (int b = 0; b < 16 / RR; ++b) {
         const int j = t + b * (L / 16);
 #pragma unroll
-        for (int r = 0; r < RR; ++r) x[b * RR + r] = buf[px(j + r * (L / RR))];
+        for (int r = 0; r < RR; ++r) x[b * RR + r] = buf[px<R>(j + r * (L / RR))];
     }
 }
 

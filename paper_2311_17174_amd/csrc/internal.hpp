@@ -105,6 +105,8 @@ struct TwLayout {
     size_t bytes;
 };
 TwLayout tw_layout(const Plan& p);
+// LDS bytes of a pass-A tile of TA columns of R2 points
+size_t cols_lds_bytes(int prec, int64_t R2, int TA, int split);
 
 // ---- launchers (return hipSuccess or the launch error) -------------------
 // the orbit is integrated in segments [k_i, k_{i+1}) of coarse steps so that

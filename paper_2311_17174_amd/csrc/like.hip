@@ -23,6 +23,8 @@
 // fixed order (results do not depend on how walkers are batched).
 #include "fft_lds.hpp"
 
+#include <stdlib.h>
+
 namespace emri {
 
 // ---------------------------------------------------------------------------
@@ -149,7 +151,8 @@ __device__ inline void delay_rotation(int64_t k, double phi, double* c, double* 
 // into LDS; then
 // lane t owns the bins (A, p) for p < L/2, paired with (B, L-1-p), and the
 // bins (B, L-1-p) for p >= L/2, paired with (A, p).  Data and weights of the
-// lane's bins are read once per walker (the tile's walkers hit the cache).
+// lane's bins are read once per walker; the walker tiles of a row pair run
+// together on one XCD (see the mapping below), so they hit that XCD's L2.
 // One FP64 partial per (g, walker).  Register budget 128 (4 waves per SIMD,
 // two workgroups per CU): occupancy matters more here than the few spills
 // it costs the FP64 variant.
@@ -167,9 +170,17 @@ k_rows_like(const typename C2<R>::T* __restrict__ z,
     extern __shared__ unsigned char smem_raw[];
     __shared__ double sh[16];
     R* sre = (R*)smem_raw;
-    R* sim = sre + padded_len(L);
-    const int64_t g = blockIdx.x;
+    R* sim = sre + padded_len<R>(L);
+    // workgroup -> (row pair g, walker tile): the hardware deals consecutive
+    // workgroups to the 8 XCDs in turn; XCD x takes the row pairs g = x mod 8
+    // and, for each, all walker tiles one after the other, so the tiles of a
+    // row pair run together on one XCD and share its data through that L2
     const int64_t nparts = R2 / 2 + 1;
+    const int64_t ntiles = (B + WT - 1) / WT;
+    const int64_t lid = blockIdx.x >> 3;
+    const int64_t g = (int64_t)(blockIdx.x & 7) + 8 * (lid / ntiles);
+    const int64_t tile = lid % ntiles;
+    if (g >= nparts) return;
     const bool self = (g == 0) || (g == R2 / 2);
     const int64_t rowA = g, rowB = self ? g : R2 - g;
     const int t0 = threadIdx.x;
@@ -196,7 +207,7 @@ k_rows_like(const typename C2<R>::T* __restrict__ z,
     const R* Wt = (const R*)dsw;
 
     for (int wi = 0; wi < WT; ++wi) {
-        const int64_t w = (int64_t)blockIdx.y * WT + wi;
+        const int64_t w = tile * WT + wi;
         if (w >= B) break;
         // opaque per iteration: keeps the per-bin index arithmetic inside the
         // loop instead of holding it in registers across the transforms
@@ -227,8 +238,8 @@ k_rows_like(const typename C2<R>::T* __restrict__ z,
                 // than the LDS round trip it saves
                 for (int q = t; q < L; q += L8) {
                     const T2 v = zw[rowB * L + q];
-                    sre[px(q)] = v.x;
-                    sim[px(q)] = v.y;
+                    sre[px<R>(q)] = v.x;
+                    sim[px<R>(q)] = v.y;
                 }
                 __syncthreads();
                 lds_fft<R>(sre, sim, L, lgL, t, twL);
@@ -246,8 +257,8 @@ k_rows_like(const typename C2<R>::T* __restrict__ z,
             fft_regs<R, false>(sre, sim, L, lgL, t, twL, ar, ai);
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                ar[i] = sre[px(t + i * L8)];
-                ai[i] = sim[px(t + i * L8)];
+                ar[i] = sre[px<R>(t + i * L8)];
+                ai[i] = sim[px<R>(t + i * L8)];
             }
         }
         const double scale = c[WC_G] * dt;
@@ -260,7 +271,7 @@ k_rows_like(const typename C2<R>::T* __restrict__ z,
             for (int i = 0; i < 8; ++i) {
                 if (i >= nown) continue;
                 double zr, zi, mr, mi;            // bin value and its mirror
-                const int mp = px(mirror(i));
+                const int mp = px<R>(mirror(i));
                 if (i < 4) { zr = ar[i]; zi = ai[i]; mr = sre[mp]; mi = sim[mp]; }
                 else { zr = sre[mp]; zi = sim[mp]; mr = ar[i]; mi = ai[i]; }
                 double xr = 0.5 * (zr + mr), xi = 0.5 * (zi - mi);     // X_I
@@ -286,7 +297,7 @@ k_rows_like(const typename C2<R>::T* __restrict__ z,
             for (int i = 0; i < 8; ++i) {
                 if (i >= nown) continue;
                 float zr, zi, mr, mi;
-                const int mp = px(mirror(i));
+                const int mp = px<R>(mirror(i));
                 if (i < 4) { zr = ar[i]; zi = ai[i]; mr = sre[mp]; mi = sim[mp]; }
                 else { zr = sre[mp]; zi = sim[mp]; mr = ar[i]; mi = ai[i]; }
                 float xr = 0.5f * (zr + mr), xi = 0.5f * (zi - mi);
@@ -345,10 +356,13 @@ hipError_t launch_likelihood(const Plan& p, int64_t B, const void* ds, void* ws,
     const double* wc = (const double*)(base + p.off_wc);
     double* part = (double*)(base + p.off_part);
     const int L = (int)p.R1;
-    const int WT = (B >= 128) ? 8 : (B >= 16 ? 4 : 1);
-    const size_t lds = (size_t)padded_len(L) * 2 * (p.prec == EMRI_FP64 ? 8 : 4);
+    int WT = (B >= 128) ? 8 : (B >= 16 ? 4 : 1);
+    if (const char* env = getenv("EMRI_LIKE_WT")) WT = atoi(env) > 0 ? atoi(env) : WT;
+    const size_t lds = (p.prec == EMRI_FP64) ? (size_t)padded_len<double>(L) * 2 * 8
+                                             : (size_t)padded_len<float>(L) * 2 * 4;
     const int64_t nparts = p.R2 / 2 + 1;
-    dim3 grid((unsigned)nparts, (unsigned)((B + WT - 1) / WT));
+    const int64_t ntiles = (B + WT - 1) / WT;
+    dim3 grid((unsigned)(((nparts + 7) / 8) * 8 * ntiles));
     const TwLayout tl = tw_layout(p);
     const char* twb = base + p.off_tw;
     hipError_t ae = (p.prec == EMRI_FP64)

@@ -143,6 +143,72 @@ __device__ inline void delay_rotation(int64_t k, double phi, double* c, double* 
     sincospi(-2.0 * f, s, c);
 }
 
+// Per-lane accumulation of the inner product over the lane's bins.  A bin
+// is given by its packed value z = Z_k and the value m = Z_{N-k} it pairs
+// with; X_I = (z + conj m)/2, X_II = (z - conj m)/(2i), times the propagation
+// factor (g dt) e^{-2 pi i k phi}, weighed against the data of bin b.
+// FP64: -1/2 W |d - x|^2 summed in FP64.  Mixed: whitened FP32 data d~ and
+// sqrt(W); Kahan sums of <d~|x~> and |x~|^2, combined in FP64.
+template <typename R, bool MIXED> struct BinAcc;
+
+template <typename R> struct BinAcc<R, false> {
+    double acc = 0.0;
+    __device__ __forceinline__ void add(R zr, R zi, R mr, R mi, int64_t k, int64_t b,
+                                        double scale, bool hasdt, double phi,
+                                        const typename C2<R>::T* __restrict__ D,
+                                        const R* __restrict__ Wt, int64_t half)
+    {
+        double xr = 0.5 * (zr + mr), xi = 0.5 * (zi - mi);     // X_I
+        double yr = 0.5 * (zi + mi), yi = -0.5 * (zr - mr);    // X_II
+        if (hasdt) {
+            double cr, ci;
+            delay_rotation(k, phi, &cr, &ci);
+            double u = xr * cr - xi * ci; xi = xr * ci + xi * cr; xr = u;
+            u = yr * cr - yi * ci; yi = yr * ci + yi * cr; yr = u;
+        }
+        const typename C2<R>::T d0 = D[b], d1 = D[half + b];
+        const double r0 = d0.x - scale * xr, i0 = d0.y - scale * xi;
+        const double r1 = d1.x - scale * yr, i1 = d1.y - scale * yi;
+        acc += Wt[b] * (r0 * r0 + i0 * i0 + r1 * r1 + i1 * i1);
+        asm volatile("" ::: "memory");   // keep the bins' loads from piling up
+    }
+    __device__ __forceinline__ double lane_sum() const { return -0.5 * acc; }
+};
+
+template <typename R> struct BinAcc<R, true> {
+    float cr_s = 0.f, cr_c = 0.f, mm_s = 0.f, mm_c = 0.f;   // Kahan sums
+    __device__ __forceinline__ void add(R zr, R zi, R mr, R mi, int64_t k, int64_t b,
+                                        double scale, bool hasdt, double phi,
+                                        const typename C2<R>::T* __restrict__ D,
+                                        const R* __restrict__ Wt, int64_t half)
+    {
+        float xr = 0.5f * (zr + mr), xi = 0.5f * (zi - mi);
+        float yr = 0.5f * (zi + mi), yi = -0.5f * (zr - mr);
+        if (hasdt) {
+            double cr, ci;
+            delay_rotation(k, phi, &cr, &ci);
+            const float fr = (float)cr, fi = (float)ci;
+            float u = xr * fr - xi * fi; xi = xr * fi + xi * fr; xr = u;
+            u = yr * fr - yi * fi; yi = yr * fi + yi * fr; yr = u;
+        }
+        const typename C2<R>::T d0 = D[b], d1 = D[half + b];
+        const float sc = (float)scale * (float)Wt[b];
+        xr *= sc; xi *= sc; yr *= sc; yi *= sc;
+        const float cross = (float)d0.x * xr + (float)d0.y * xi +
+                            (float)d1.x * yr + (float)d1.y * yi;
+        const float mm = xr * xr + xi * xi + yr * yr + yi * yi;
+        float y = cross - cr_c, u = cr_s + y;
+        cr_c = (u - cr_s) - y; cr_s = u;
+        y = mm - mm_c; u = mm_s + y;
+        mm_c = (u - mm_s) - y; mm_s = u;
+        asm volatile("" ::: "memory");
+    }
+    __device__ __forceinline__ double lane_sum() const
+    {
+        return ((double)cr_s - (double)cr_c) - 0.5 * ((double)mm_s - (double)mm_c);
+    }
+};
+
 // Fused pass B + inner product.  Workgroup (g, walker tile): rows g and
 // R2 - g of the column-transformed signal (rows 0 and R2/2 pair with
 // themselves), L = R1 points each, L/8 lanes.  For each walker of the tile:
@@ -264,67 +330,123 @@ k_rows_like(const typename C2<R>::T* __restrict__ z,
         const double scale = c[WC_G] * dt;
         const bool hasdt = c[WC_HASDT] != 0.0;
         const double phi = c[WC_PHI];
-        double lane_sum;
-        if (!MIXED) {
-            double acc = 0.0;
+        BinAcc<R, MIXED> acc;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                if (i >= nown) continue;
-                double zr, zi, mr, mi;            // bin value and its mirror
-                const int mp = px<R>(mirror(i));
-                if (i < 4) { zr = ar[i]; zi = ai[i]; mr = sre[mp]; mi = sim[mp]; }
-                else { zr = sre[mp]; zi = sim[mp]; mr = ar[i]; mi = ai[i]; }
-                double xr = 0.5 * (zr + mr), xi = 0.5 * (zi - mi);     // X_I
-                double yr = 0.5 * (zi + mi), yi = -0.5 * (zr - mr);    // X_II
-                if (hasdt) {
-                    double cr, ci;
-                    delay_rotation(own_row(i) + R2 * own_col(i), phi, &cr, &ci);
-                    double u = xr * cr - xi * ci; xi = xr * ci + xi * cr; xr = u;
-                    u = yr * cr - yi * ci; yi = yr * ci + yi * cr; yr = u;
-                }
-                const int64_t b = own_row(i) * hL + own_col(i);
-                const T2 d0 = D[b], d1 = D[half + b];
-                const double r0 = d0.x - scale * xr, i0 = d0.y - scale * xi;
-                const double r1 = d1.x - scale * yr, i1 = d1.y - scale * yi;
-                acc += Wt[b] * (r0 * r0 + i0 * i0 + r1 * r1 + i1 * i1);
-                asm volatile("" ::: "memory");   // keep the bins' loads from piling up
-            }
-            lane_sum = -0.5 * acc;
-        } else {
-            float cr_s = 0.f, cr_c = 0.f, mm_s = 0.f, mm_c = 0.f;   // Kahan sums
-            const float fs = (float)scale;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                if (i >= nown) continue;
-                float zr, zi, mr, mi;
-                const int mp = px<R>(mirror(i));
-                if (i < 4) { zr = ar[i]; zi = ai[i]; mr = sre[mp]; mi = sim[mp]; }
-                else { zr = sre[mp]; zi = sim[mp]; mr = ar[i]; mi = ai[i]; }
-                float xr = 0.5f * (zr + mr), xi = 0.5f * (zi - mi);
-                float yr = 0.5f * (zi + mi), yi = -0.5f * (zr - mr);
-                if (hasdt) {
-                    double cr, ci;
-                    delay_rotation(own_row(i) + R2 * own_col(i), phi, &cr, &ci);
-                    const float fr = (float)cr, fi = (float)ci;
-                    float u = xr * fr - xi * fi; xi = xr * fi + xi * fr; xr = u;
-                    u = yr * fr - yi * fi; yi = yr * fi + yi * fr; yr = u;
-                }
-                const int64_t b = own_row(i) * hL + own_col(i);
-                const T2 d0 = D[b], d1 = D[half + b];
-                const float sc = fs * (float)Wt[b];
-                xr *= sc; xi *= sc; yr *= sc; yi *= sc;
-                const float cross = (float)d0.x * xr + (float)d0.y * xi +
-                                    (float)d1.x * yr + (float)d1.y * yi;
-                const float mm = xr * xr + xi * xi + yr * yr + yi * yi;
-                float y = cross - cr_c, u = cr_s + y;
-                cr_c = (u - cr_s) - y; cr_s = u;
-                y = mm - mm_c; u = mm_s + y;
-                mm_c = (u - mm_s) - y; mm_s = u;
-                asm volatile("" ::: "memory");
-            }
-            lane_sum = ((double)cr_s - (double)cr_c) - 0.5 * ((double)mm_s - (double)mm_c);
+        for (int i = 0; i < 8; ++i) {
+            if (i >= nown) continue;
+            R zr, zi, mr, mi;                 // bin value and its mirror
+            const int mp = px<R>(mirror(i));
+            if (i < 4) { zr = ar[i]; zi = ai[i]; mr = sre[mp]; mi = sim[mp]; }
+            else { zr = sre[mp]; zi = sim[mp]; mr = ar[i]; mi = ai[i]; }
+            acc.add(zr, zi, mr, mi, own_row(i) + R2 * own_col(i), own_row(i) * hL + own_col(i),
+                    scale, hasdt, phi, D, Wt, half);
         }
+        const double lane_sum = acc.lane_sum();
         const double s = block_sum(lane_sum, sh);
+        if (t == 0) part[w * nparts + g] = s;
+        // block_sum ends with a barrier: LDS may be overwritten by the next walker
+    }
+}
+
+// The same with 16 values per lane (L/16 lanes; radix-16 transforms with two
+// LDS exchanges per row): both rows stay in registers through their
+// transforms, so it suits FP32; row B's spectrum (row A's for a row that
+// pairs with itself) is then written to LDS for the mirror reads.  Lane t
+// holds positions p = t + slot_pos16(s) L/16; it owns (A, p) for p < L/2 and
+// (B, L-1-p) for p >= L/2 (only p < L/2 in a self-paired row).  Register
+// budget 128 (4 waves per SIMD, four workgroups per CU): faster than the
+// spill-free 156 registers at three.
+template <typename R, bool MIXED, int MAXT>
+__global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(4)))
+k_rows_like16(const typename C2<R>::T* __restrict__ z, int64_t N, int L, int lgL, int64_t R2,
+              double dt, const double* __restrict__ wc, const void* __restrict__ dsd,
+              const void* __restrict__ dsw, const typename C2<R>::T* __restrict__ twL,
+              double* __restrict__ part, int64_t B, int WT)
+{
+    using T2 = typename C2<R>::T;
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ double sh[16];
+    R* sre = (R*)smem_raw;
+    R* sim = sre + padded_len<R>(L);
+    // workgroup -> (row pair g, walker tile), XCD-grouped as in k_rows_like
+    const int64_t nparts = R2 / 2 + 1;
+    const int64_t ntiles = (B + WT - 1) / WT;
+    const int64_t lid = blockIdx.x >> 3;
+    const int64_t g = (int64_t)(blockIdx.x & 7) + 8 * (lid / ntiles);
+    const int64_t tile = lid % ntiles;
+    if (g >= nparts) return;
+    const bool self = (g == 0) || (g == R2 / 2);
+    const int64_t rowA = g, rowB = self ? g : R2 - g;
+    const int t0 = threadIdx.x;
+    const int L16 = L / 16, hL = L / 2;
+    const int64_t half = N / 2;
+    const int RL = last_radix16(lgL);
+    const T2* D = (const T2*)dsd;
+    const R* Wt = (const R*)dsw;
+
+    for (int wi = 0; wi < WT; ++wi) {
+        const int64_t w = tile * WT + wi;
+        if (w >= B) break;
+        int t = t0;
+        asm volatile("" : "+v"(t));
+        const double* c = wc + w * WC;
+        if (c[WC_VALID] == 0.0) {
+            if (t == 0) part[w * nparts + g] = 0.0;
+            continue;
+        }
+        const T2* zw = z + w * N;
+        R ar[16], ai[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const T2 v = zw[rowA * L + t + i * L16];
+            ar[i] = v.x;
+            ai[i] = v.y;
+        }
+        fft16_regs<R, false>(sre, sim, L, lgL, t, twL, ar, ai);
+        if (!self) {
+            R br[16], bi[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const T2 v = zw[rowB * L + t + i * L16];
+                br[i] = v.x;
+                bi[i] = v.y;
+            }
+            fft16_regs<R, false>(sre, sim, L, lgL, t, twL, br, bi);
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                const int p = t + slot_pos16(s, RL) * L16;
+                sre[px<R>(p)] = br[s];
+                sim[px<R>(p)] = bi[s];
+            }
+        } else {
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                const int p = t + slot_pos16(s, RL) * L16;
+                sre[px<R>(p)] = ar[s];
+                sim[px<R>(p)] = ai[s];
+            }
+        }
+        __syncthreads();
+        const double scale = c[WC_G] * dt;
+        const bool hasdt = c[WC_HASDT] != 0.0;
+        const double phi = c[WC_PHI];
+        BinAcc<R, MIXED> acc;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int p = t + slot_pos16(s, RL) * L16;
+            if (p < hL) {
+                const int mp = (self && g == 0) ? ((L - p) & (L - 1)) : (L - 1 - p);
+                acc.add(ar[s], ai[s], sre[px<R>(mp)], sim[px<R>(mp)], rowA + R2 * p,
+                        rowA * hL + p, scale, hasdt, phi, D, Wt, half);
+            } else if (!self) {
+                const int q = L - 1 - p;
+                acc.add(sre[px<R>(q)], sim[px<R>(q)], ar[s], ai[s], rowB + R2 * q, rowB * hL + q,
+                        scale, hasdt, phi, D, Wt, half);
+            }
+        }
+        const double s = block_sum(acc.lane_sum(), sh);
         if (t == 0) part[w * nparts + g] = s;
         // block_sum ends with a barrier: LDS may be overwritten by the next walker
     }
@@ -365,24 +487,35 @@ hipError_t launch_likelihood(const Plan& p, int64_t B, const void* ds, void* ws,
     dim3 grid((unsigned)(((nparts + 7) / 8) * 8 * ntiles));
     const TwLayout tl = tw_layout(p);
     const char* twb = base + p.off_tw;
-    hipError_t ae = (p.prec == EMRI_FP64)
-                        ? allow_lds((const void*)k_rows_like<double, false, 512>, lds)
-                        : allow_lds((const void*)k_rows_like<float, true, 512>, lds);
+    // FP32 rows take 16 values per lane (EMRI_LIKE_E=8 selects the 8-per-lane
+    // kernel); FP64 keeps 8: two rows of 16 FP64 values do not fit 128 VGPRs
+    int E = (p.prec == EMRI_FP64) ? 8 : 16;
+    if (const char* env = getenv("EMRI_LIKE_E")) E = (atoi(env) == 8) ? 8 : E;
+    const void* kern;
+    if (p.prec == EMRI_FP64) kern = (const void*)k_rows_like<double, false, 512>;
+    else if (E == 16) kern = (const void*)k_rows_like16<float, true, 256>;
+    else kern = (const void*)k_rows_like<float, true, 512>;
+    hipError_t ae = allow_lds(kern, lds);
     if (ae != hipSuccess) return ae;
-    if (L / 8 > 512) return hipErrorInvalidValue;   // rows are at most 2^12 points
-    const dim3 blk((unsigned)(L / 8));
+    if (L / E > 512 || L < 16) return hipErrorInvalidValue;   // rows of 2^7 .. 2^12 points
+    const dim3 blk((unsigned)(L / E));
     const void* dsd = (const void*)(db + p.ds_off_d);
     const void* dsw = (const void*)(db + p.ds_off_w);
     trace_mark(ST_LIKE, s, true);
-    if (p.prec == EMRI_FP64)
-        hipLaunchKernelGGL((k_rows_like<double, false, 512>), grid, blk, lds, s,
-                           (const double2*)(base + p.off_z), p.N, L, p.m1, p.R2, p.dt, wc, dsd,
-                           dsw, (const double2*)(twb + tl.oB), part, B, WT);
-    else
-        hipLaunchKernelGGL((k_rows_like<float, true, 512>), grid, blk, lds, s,
-                           (const float2*)(base + p.off_z), p.N, L, p.m1, p.R2, p.dt, wc, dsd,
-                           dsw, (const float2*)(twb + tl.fB), part, B, WT);
+    {
+        const void* a_z = (const void*)(base + p.off_z);
+        int64_t a_N = p.N, a_R2 = p.R2, a_B = B;
+        int a_L = L, a_lgL = p.m1, a_WT = WT;
+        double a_dt = p.dt;
+        const double* a_wc = wc;
+        const void* a_tw = (const void*)(twb + (p.prec == EMRI_FP64 ? tl.oB : tl.fB));
+        double* a_part = part;
+        void* args[] = {&a_z, &a_N, &a_L, &a_lgL, &a_R2, &a_dt, &a_wc, (void*)&dsd,
+                        (void*)&dsw, &a_tw, &a_part, &a_B, &a_WT};
+        ae = hipLaunchKernel(kern, grid, blk, args, lds, s);
+    }
     trace_mark(ST_LIKE, s, false);
+    if (ae != hipSuccess) return ae;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const double* norm = (p.prec == EMRI_FP64) ? nullptr : (const double*)(db + p.ds_off_norm);

@@ -115,6 +115,44 @@ def test_amplitude_table_error_converges():
 
 
 # ----------------------------------------------------------------------- FFT
+def _waveform_and_lnl(E, w, P):
+    cfg = E.Config.from_workload(w)
+    got = E.waveform_batch(gpu_params(P), cfg).cpu().numpy().astype(np.float64).transpose(0, 2, 1)
+    ref = O.waveform(P, ocfg(w))
+    werr = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    d, S = oracle_dataset(w, True)
+    dd, ss = to_device_data(d, S)
+    lnl = E.loglike_batch(gpu_params(P), dd, ss, cfg).cpu().numpy()
+    lref = O.loglike(P, d, S, ocfg(w))
+    lerr = np.max(np.abs(lnl - lref) / np.abs(lref))
+    return werr, lerr
+
+
+# the edges of the accepted configurations: every samples-per-lane variant of
+# the synthesis (coarse step 2^cl samples), the largest harmonic count, the
+# smallest transform (rows of 128 points, columns of 32)
+EDGE_CASES = [("cl9", dict(coarse_log2=9), {}), ("cl11", dict(coarse_log2=11), {}),
+              ("cl12", dict(coarse_log2=12), {}), ("nh64", {}, dict(n_harm=64)),
+              ("N4096", {}, dict(days=0.4, N=1 << 12))]
+
+
+@pytest.mark.parametrize("case", EDGE_CASES, ids=[c[0] for c in EDGE_CASES])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_configuration_edges(E, prec, case):
+    name, over, kw = case
+    w = W.small(prec, **{"n_harm": 8, **kw}).with_(**over)
+    P = W.walkers(w, B=6)
+    say("edge case", name, prec, w.coarse_log2, w.n_harm, w.N)
+    werr, lerr = _waveform_and_lnl(E, w, P)
+    say("waveform rel err", werr, "lnL rel err", lerr)
+    if prec == "fp64":
+        assert werr <= 64 * w.n_harm * max_phase(w, P) * EPS64
+        assert lerr <= 1e-10
+    else:
+        assert werr <= 2e-5
+        assert lerr <= 1e-4
+
+
 @pytest.mark.parametrize("logN", [12, 13, 15, 18, 20])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_fft_parity(E, logN, prec):

@@ -127,7 +127,7 @@ k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
     const bool smooth = stepPhi < 0.25 && stepG < 0.25 && stepA < 0.25;
 
     // ---- per sample: phases ------------------------------------------------
-    R u[SPT], cpb[SPT], spb[SPT];          // u, cos/sin of phibar
+    R u[SPT];                               // interval coordinate
     R c1[SPT], s1[SPT];                     // e^{i Phi'}
     double ph[SPT];
 #pragma unroll
@@ -141,8 +141,6 @@ k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
         small_sincos((R)(dphi * (double)off), &sd, &cd);
         const R cb = (R)cb0 * cd - (R)sb0 * sd;
         const R sb = (R)sb0 * cd + (R)cb0 * sd;
-        cpb[s] = cb;
-        spb[s] = sb;
         const double cdel = (double)cb * cps + (double)sb * sps;   // cos(phibar - phi_S)
         ph[s] = Phi + dop * nu * cdel;                              // Doppler-shifted phase
     }
@@ -195,17 +193,9 @@ k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
     }
 
     // ---- geometry, response, store -----------------------------------------
-    double gam2[SPT], alp[SPT];
-#pragma unroll
-    for (int s = 0; s < SPT; ++s) {
-        const double ud = (double)u[s];
-        gam2[s] = 2.0 * (((q[11] * ud + q[10]) * ud + q[9]) * ud + q[8]);
-        alp[s] = ((q[15] * ud + q[14]) * ud + q[13]) * ud + q[12];
-    }
-    R c2gv[SPT], s2gv[SPT], cav[SPT], sav[SPT];
-    angle_run<R, SPT>(gam2, smooth, c2gv, s2gv);
-    angle_run<R, SPT>(alp, smooth, cav, sav);
-
+    // one sample at a time, with the angles carried from sample to sample
+    // (the same rotations as for Phi'), so that only the three harmonic sums
+    // stay live from the loop above
     const R Nx = (R)c[WC_NX], Ny = (R)c[WC_NY], Nz = (R)c[WC_NZ];
     const R Sx = (R)c[WC_SX], Sy = (R)c[WC_SY], Sz = (R)c[WC_SZ];
     const R E1x = (R)c[WC_E1X], E1y = (R)c[WC_E1Y], E1z = (R)c[WC_E1Z];
@@ -217,14 +207,48 @@ k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
     const R NSx = Ny * Sz - Nz * Sy, NSy = Nz * Sx - Nx * Sz, NSz = Nx * Sy - Ny * Sx;
     const R h3 = (R)0.8660254037844386467637231707529362;  // sqrt(3)/2
     const R thr = Degenerate<R>::v;
+    R sdp, cdp;                                   // azimuth step per sample
+    small_sincos((R)dphi, &sdp, &cdp);
+    R cb = R(0), sb = R(0), c2g = R(0), s2g = R(0), ca = R(0), sa = R(0);
+    double gprev = 0.0, aprev = 0.0;
 #pragma unroll
     for (int s = 0; s < SPT; ++s) {
         const int64_t j = jl + s;
+        const double ud = (double)(lane * SPT + s) * invL;
+        const double gam2 = 2.0 * (((q[11] * ud + q[10]) * ud + q[9]) * ud + q[8]);
+        const double alp = ((q[15] * ud + q[14]) * ud + q[13]) * ud + q[12];
+        if (s == 0) {
+            R sd, cd;
+            small_sincos((R)(dphi * (double)(lane * SPT)), &sd, &cd);
+            cb = (R)cb0 * cd - (R)sb0 * sd;
+            sb = (R)sb0 * cd + (R)cb0 * sd;
+            angle_sincos(gam2, &s2g, &c2g);
+            angle_sincos(alp, &sa, &ca);
+        } else {
+            const R t = cb * cdp - sb * sdp;
+            sb = sb * cdp + cb * sdp;
+            cb = t;
+            if (smooth) {
+                R sd, cd;
+                small_sincos((R)(gam2 - gprev), &sd, &cd);
+                const R tg = c2g * cd - s2g * sd;
+                s2g = s2g * cd + c2g * sd;
+                c2g = tg;
+                small_sincos((R)(alp - aprev), &sd, &cd);
+                const R ta = ca * cd - sa * sd;
+                sa = sa * cd + ca * sd;
+                ca = ta;
+            } else {
+                angle_sincos(gam2, &s2g, &c2g);
+                angle_sincos(alp, &sa, &ca);
+            }
+        }
+        gprev = gam2;
+        aprev = alp;
         if (j >= Nv) {
             zw[j] = R2{R(0), R(0)};
             continue;
         }
-        const R ca = cav[s], sa = sav[s];
         const R Lx = cl * Sx + sl * (ca * E1x + sa * E2x);
         const R Ly = cl * Sy + sl * (ca * E1y + sa * E2y);
         const R Lz = cl * Sz + sl * (ca * E1z);
@@ -232,7 +256,6 @@ k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
         // the three angles beta, phi_d - phibar and psi as tangent pairs
         // (x, y) = (|.| cos, |.| sin); beta is undefined (0) when sin(lambda) = 0
         const R bx = NS - ci * cl, by = Lx * NSx + Ly * NSy + Lz * NSz;
-        const R cb = cpb[s], sb = spb[s];
         const R cdel = cb * Rcps + sb * Rsps;         // cos(phibar - phi_S)
         const R sdel = sb * Rcps - cb * Rsps;         // sin(phibar - phi_S)
         const R cthd = R(0.5) * cts - h3 * sts * cdel;
@@ -257,7 +280,6 @@ k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
         const R c2s = okp ? (px_ * px_ - py_ * py_) * ip : R(1);
         const R s2s = okp ? R(2) * px_ * py_ * ip : R(0);
 
-        const R c2g = c2gv[s], s2g = s2gv[s];
         const R c2 = c2g * c2b - s2g * s2b;     // cos 2 gamma, gamma = gamma~ + beta
         const R s2 = s2g * c2b + c2g * s2b;     // sin 2 gamma
         const R ci2 = ci * ci;

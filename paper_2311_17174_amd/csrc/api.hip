@@ -255,7 +255,13 @@ static emri_status run_waveforms(const Plan& p, const double* params, int64_t B,
 {
     const int S = orbit_segments(p);
     const int64_t KT = p.N / p.L;            // synthesis intervals, zero tail included
-    auto kb = [&](int i) { return p.K * i / S; };
+    // segment bounds: the first segment (integrated before anything else can
+    // start) is a quarter of the others
+    auto kb = [&](int i) -> int64_t {
+        if (i <= 0) return 0;
+        if (i >= S) return p.K;
+        return p.K * (int64_t)(1 + 4 * (i - 1)) / (int64_t)(1 + 4 * (S - 1));
+    };
     emri_status st;
     if (S == 1) {
         if ((st = check_launch(launch_walker_setup(p, params, B, ws, p.K, s), "walker setup")))

@@ -500,8 +500,9 @@ hipError_t launch_tables(const Plan& p, int64_t B, void* ws, int64_t k0, int64_t
     // nodes k0 .. k1; node k0 of a later segment was the previous one's last
     const int64_t n0 = (seg == 0) ? 0 : k0 + 1, n1 = k1 + 1;
     const int64_t nn = (n1 - n0) * p.nh;
-    hipLaunchKernelGGL(k_nodes, dim3((unsigned)((nn + 255) / 256), (unsigned)B), dim3(256), 0, s,
-                       p.K, p.nh, n0, n1, seg, wc, orb, nv);
+    if (nn > 0)   // an empty segment has no nodes of its own
+        hipLaunchKernelGGL(k_nodes, dim3((unsigned)((nn + 255) / 256), (unsigned)B), dim3(256),
+                           0, s, p.K, p.nh, n0, n1, seg, wc, orb, nv);
     const int64_t n = (k1 - k0) * p.nh;
     dim3 grid((unsigned)((n + 255) / 256), (unsigned)B);
     if (n > 0) {

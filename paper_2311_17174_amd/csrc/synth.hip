@@ -147,10 +147,11 @@ k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
     angle_run<R, SPT>(ph, smooth, c1, s1);
 
     // ---- harmonic sum ------------------------------------------------------
-    // cos/sin(n Phi') for n = 1..nh: FP64 by the three-term recurrence
-    // x_{n+1} = 2 cos(Phi') x_n - x_{n-1} (one FMA per value; the error
-    // injected at step m is carried forward at most (n - m + 1)-fold, so
-    // below nh^2 ulp in all), FP32 by complex rotation (error ~ n ulp)
+    // cos/sin(n Phi') for n = 1..nh by the three-term recurrence
+    // x_{n+1} = 2 cos(Phi') x_n - x_{n-1}: one FMA per value.  An error made
+    // at step m is carried forward at most (n - m + 1)-fold (|U_k| <= k + 1),
+    // so harmonic n carries at most n^2/2 rounding units relative to its own
+    // amplitude; the sum's error is set by the strong low harmonics
     R Sa[SPT], Sb[SPT], Sc[SPT], cn[SPT], sn[SPT], cq[SPT], sq[SPT], tc[SPT];
 #pragma unroll
     for (int s = 0; s < SPT; ++s) {
@@ -177,18 +178,12 @@ k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
             Sa[s] += ua * cn[s];
             Sb[s] += ub * sn[s];
             Sc[s] += uc * cn[s];
-            if constexpr (sizeof(R) == 8) {
-                const R cc = tc[s] * cn[s] - cq[s];
-                const R ss = tc[s] * sn[s] - sq[s];
-                cq[s] = cn[s];
-                sq[s] = sn[s];
-                cn[s] = cc;
-                sn[s] = ss;
-            } else {
-                const R cc = cn[s] * c1[s] - sn[s] * s1[s];
-                sn[s] = sn[s] * c1[s] + cn[s] * s1[s];
-                cn[s] = cc;
-            }
+            const R cc = tc[s] * cn[s] - cq[s];
+            const R ss = tc[s] * sn[s] - sq[s];
+            cq[s] = cn[s];
+            sq[s] = sn[s];
+            cn[s] = cc;
+            sn[s] = ss;
         }
     }
 

@@ -194,11 +194,11 @@ static emri_status check_launch(hipError_t e, const char* where)
 // ---- orbit-segment pipeline -------------------------------------------------
 // The orbit integration is sequential in time and runs one lane per walker:
 // alone it would leave the GPU nearly idle.  It is cut into S segments of
-// coarse steps; the caller's stream integrates them in turn while an
-// auxiliary stream builds the tables and synthesises the samples of each
-// finished segment.  One auxiliary stream (non-blocking, default priority)
-// and its events per (device, caller stream), created on first use and kept
-// until the process ends.  Every wait refers to an event recorded earlier in
+// coarse steps; the caller's stream integrates them in turn and builds each
+// finished segment's tables while an auxiliary stream synthesises the
+// samples of the segments already tabulated.  One auxiliary stream
+// (non-blocking, default priority) and its events per (device, caller
+// stream), created on first use and kept until the process ends.  Every wait refers to an event recorded earlier in
 // host order, and the caller's stream waits for the auxiliary stream before
 // returning, so the pair behaves as one stream to the caller (also under
 // stream capture, where the auxiliary stream joins and leaves the capture).
@@ -274,17 +274,19 @@ static emri_status run_waveforms(const Plan& p, const double* params, int64_t B,
     if ((st = get_pipe(s, &pp))) return st;
     st = check_launch(launch_walker_setup(p, params, B, ws, kb(1), s), "walker setup");
     bool forked = false;
+    // the caller's stream integrates segment i and builds its tables (small
+    // kernels that fill the issue slots the synthesis leaves); the auxiliary
+    // stream synthesises segment i meanwhile
     for (int i = 0; i < S && st == EMRI_OK; ++i) {
         if (i > 0 &&
             (st = check_launch(launch_walker_resume(p, B, ws, kb(i), kb(i + 1), i, s), "orbit")))
+            break;
+        if ((st = check_launch(launch_tables(p, B, ws, kb(i), kb(i + 1), i, s), "amplitude tables")))
             break;
         if ((st = check_launch(hipEventRecord(pp->seg[i], s), "pipeline: event record"))) break;
         if ((st = check_launch(hipStreamWaitEvent(pp->aux, pp->seg[i], 0), "pipeline: wait")))
             break;
         forked = true;
-        if ((st = check_launch(launch_tables(p, B, ws, kb(i), kb(i + 1), i, pp->aux),
-                               "amplitude tables")))
-            break;
         if ((st = check_launch(launch_synth(p, B, ws, out, kb(i), i == S - 1 ? KT : kb(i + 1), i,
                                             pp->aux),
                                "synthesis")))

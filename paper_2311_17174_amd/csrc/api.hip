@@ -141,26 +141,17 @@ emri_status make_plan(const emri_cfg* cfg, int64_t B, Plan* p, const char** err)
     q.R2 = (int64_t)1 << q.m2;
     q.esz = (q.prec == EMRI_FP64) ? 16 : 8;
     q.hsz = (q.prec == EMRI_FP64) ? 8 : 4;
-    // pass A: 16 values per lane (8 with EMRI_FFT_COLS_E=8, for comparison);
-    // columns per workgroup: rows of ta * esz = 128 bytes (FP64) or 64 bytes
-    // (FP32) by default (EMRI_FFT_TA_BYTES overrides, for tuning), within
-    // 1024 lanes and the 160 KiB of LDS a workgroup may hold.
-    // EMRI_FFT_SPLIT=1 passes re and im through one LDS array in turn (half
-    // the LDS, more barriers; slower on MI355X for both precisions).
-    q.colsE = 16;
-    if (const char* env = getenv("EMRI_FFT_COLS_E")) q.colsE = (atoi(env) == 8) ? 8 : 16;
-    q.split = 0;
-    if (const char* env = getenv("EMRI_FFT_SPLIT")) q.split = atoi(env) ? 1 : 0;
-    if (q.colsE == 8) q.split = 0;
+    // pass-A workgroup: TA columns in rows of TA * esz = 128 bytes (FP64) or
+    // 64 bytes (FP32) (EMRI_FFT_TA_BYTES overrides, for tuning), within 1024
+    // lanes (16 values each) and the 160 KiB of LDS a workgroup may hold
     size_t run_bytes = (q.prec == EMRI_FP64) ? 128 : 64;
     if (const char* env = getenv("EMRI_FFT_TA_BYTES")) run_bytes = (size_t)atoi(env);
     int ta = (int)(run_bytes / q.esz);
     if (ta < 1) ta = 1;
     while (ta > 16) ta /= 2;
-    auto lds_a = [&](int t) { return cols_lds_bytes(q.prec, q.R2, t, q.split); };
-    while (ta > 1 && (ta * q.R2 / q.colsE > 1024 || lds_a(ta) > 160 * 1024)) ta /= 2;
+    while (ta > 1 && (ta * q.R2 / 16 > 1024 || cols_lds_bytes(q.prec, q.R2, ta) > 160 * 1024))
+        ta /= 2;
     q.TA = ta;
-    q.s_lo = (m + 1) / 2;
 
     q.B = B;
     size_t o = 0;

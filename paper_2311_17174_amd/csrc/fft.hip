@@ -8,7 +8,7 @@
 //   pass A  for each column j1: R2-point FFT over j2 (stride R1), times the
 //           twiddle W_N^{j1 k2}, stored back in place at k2 R1 + j1; a
 //           workgroup owns TA adjacent columns (coalesced runs of TA
-//           elements) and holds them in LDS
+//           elements), 16 values per lane, exchanges through LDS
 //   pass B  for each row k2: R1-point FFT over j1 (contiguous), in place
 // The spectrum is left in "transposed" order: z[k2 R1 + k1] = Z[k2 + R2 k1].
 // The likelihood reads it in that order (its data and weights are stored in
@@ -27,8 +27,6 @@ TwLayout tw_layout(const Plan& p)
     TwLayout t;
     t.nA = p.R2;
     t.nB = p.R1;
-    t.nlo = (int64_t)1 << p.s_lo;
-    t.nhi = p.N >> p.s_lo;
     // pass-A output twiddle W_N^{c k2}, k2 = t + i R2/16, as the product
     // Tb[t][c] Ts[i][c] with Tb[t][c] = W_N^{c t}, Ts[i][c] = W_N^{c i R2/16}
     t.nTb = (p.R2 / 16) * p.R1;
@@ -36,14 +34,10 @@ TwLayout tw_layout(const Plan& p)
     size_t o = 0;
     t.oA = o; o += align256(t.nA * 16);
     t.oB = o; o += align256(t.nB * 16);
-    t.olo = o; o += align256(t.nlo * 16);
-    t.ohi = o; o += align256(t.nhi * 16);
     t.oTb = o; o += align256(t.nTb * 16);
     t.oTs = o; o += align256(t.nTs * 16);
     t.fA = o; o += align256(t.nA * 8);
     t.fB = o; o += align256(t.nB * 8);
-    t.flo = o; o += align256(t.nlo * 8);
-    t.fhi = o; o += align256(t.nhi * 8);
     t.fTb = o; o += align256(t.nTb * 8);
     t.fTs = o; o += align256(t.nTs * 8);
     t.bytes = o;
@@ -51,11 +45,9 @@ TwLayout tw_layout(const Plan& p)
 }
 
 // entry i of the concatenated tables: W^{num} = exp(-2 pi i num / den)
-__global__ void k_twiddles(int64_t nA, int64_t nB, int64_t nlo, int64_t nhi, int64_t nTb,
-                           int64_t nTs, int64_t N, int64_t R1, int64_t R2, int s_lo,
-                           double2* tA, double2* tB, double2* tlo, double2* thi, double2* tTb,
-                           double2* tTs, float2* fA, float2* fB, float2* flo, float2* fhi,
-                           float2* fTb, float2* fTs)
+__global__ void k_twiddles(int64_t nA, int64_t nB, int64_t nTb, int64_t nTs, int64_t N,
+                           int64_t R1, int64_t R2, double2* tA, double2* tB, double2* tTb,
+                           double2* tTs, float2* fA, float2* fB, float2* fTb, float2* fTs)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double2* d;
@@ -63,12 +55,7 @@ __global__ void k_twiddles(int64_t nA, int64_t nB, int64_t nlo, int64_t nhi, int
     double num, den;
     if (i < nA) { d = tA; f = fA; num = (double)i; den = (double)nA; }
     else if ((i -= nA) < nB) { d = tB; f = fB; num = (double)i; den = (double)nB; }
-    else if ((i -= nB) < nlo) { d = tlo; f = flo; num = (double)i; den = (double)N; }
-    else if ((i -= nlo) < nhi) {
-        d = thi; f = fhi;
-        // exponent i 2^s_lo of W_N, reduced: (i 2^s_lo) / N = i / (N >> s_lo)
-        num = (double)i; den = (double)(N >> s_lo);
-    } else if ((i -= nhi) < nTb) {
+    else if ((i -= nB) < nTb) {
         d = tTb; f = fTb;
         num = (double)((i / R1) * (i % R1)); den = (double)N;        // c t < N
     } else if ((i -= nTb) < nTs) {
@@ -85,38 +72,33 @@ hipError_t launch_twiddles(const Plan& p, void* ws, hipStream_t s)
 {
     const TwLayout t = tw_layout(p);
     char* b = (char*)ws + p.off_tw;
-    const int64_t n = t.nA + t.nB + t.nlo + t.nhi + t.nTb + t.nTs;
+    const int64_t n = t.nA + t.nB + t.nTb + t.nTs;
     trace_mark(ST_TWIDDLE, s, true);
     hipLaunchKernelGGL(k_twiddles, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, t.nA,
-                       t.nB, t.nlo, t.nhi, t.nTb, t.nTs, p.N, p.R1, p.R2, p.s_lo,
-                       (double2*)(b + t.oA), (double2*)(b + t.oB), (double2*)(b + t.olo),
-                       (double2*)(b + t.ohi), (double2*)(b + t.oTb), (double2*)(b + t.oTs),
-                       (float2*)(b + t.fA), (float2*)(b + t.fB), (float2*)(b + t.flo),
-                       (float2*)(b + t.fhi), (float2*)(b + t.fTb), (float2*)(b + t.fTs));
+                       t.nB, t.nTb, t.nTs, p.N, p.R1, p.R2, (double2*)(b + t.oA),
+                       (double2*)(b + t.oB), (double2*)(b + t.oTb), (double2*)(b + t.oTs),
+                       (float2*)(b + t.fA), (float2*)(b + t.fB), (float2*)(b + t.fTb),
+                       (float2*)(b + t.fTs));
     trace_mark(ST_TWIDDLE, s, false);
     return hipGetLastError();
 }
 
 // column stride (per re/im array) of a pass-A tile: a padded column plus a
-// skew.  Lanes run column-fastest (TA columns, then L/8 positions), so the
+// skew.  Lanes run column-fastest (TA columns, then L/16 positions), so the
 // 16 lanes that share one 128-byte LDS access cycle (FP64; 32 for FP32) cover
 // TA columns times 16/TA (32/TA) consecutive positions: a skew of that many
 // slots puts the columns in disjoint banks.
 template <typename R>
 __host__ __device__ inline int col_stride(int L, int TA)
 {
-#ifndef EMRI_LDS_CYCLE_BYTES
-#define EMRI_LDS_CYCLE_BYTES 128
-#endif
-    return padded_len<R>(L) + (TA > 1 ? (int)(EMRI_LDS_CYCLE_BYTES / sizeof(R)) / TA : 0);
+    return padded_len<R>(L) + (TA > 1 ? (int)(128 / sizeof(R)) / TA : 0);
 }
 
-// LDS bytes of a pass-A tile of TA columns of R2 points
-size_t cols_lds_bytes(int prec, int64_t R2, int TA, int split)
+// LDS bytes of a pass-A tile of TA columns of R2 points (re and im arrays)
+size_t cols_lds_bytes(int prec, int64_t R2, int TA)
 {
-    const size_t arrays = split ? 1 : 2;
-    if (prec == EMRI_FP64) return (size_t)TA * col_stride<double>((int)R2, TA) * arrays * 8;
-    return (size_t)TA * col_stride<float>((int)R2, TA) * arrays * 4;
+    if (prec == EMRI_FP64) return (size_t)TA * col_stride<double>((int)R2, TA) * 2 * 8;
+    return (size_t)TA * col_stride<float>((int)R2, TA) * 2 * 4;
 }
 
 // XCD-aware tile order: the hardware hands consecutive workgroups to the 8
@@ -128,63 +110,18 @@ __device__ inline int64_t xcd_tile(int64_t bid, int64_t nb)
     return (bid & 7) * (nb >> 3) + (bid >> 3);
 }
 
-// pass A: TA columns of length L (= R2) per workgroup, TA * L / 8 lanes;
-// lane (col, t) = (tid mod TA, tid / TA) loads the positions t + i L/8 of
-// its column straight into registers (runs of TA adjacent columns per row:
-// coalesced), runs the first radix-8 stage there, the middle stages in LDS,
-// and the last one back into registers, from which it applies the four-step
-// twiddle and stores.  in and out may alias (the tile's read and write sets
-// coincide, and every read precedes the first barrier).
+// pass A: TA columns per workgroup, TA * L / 16 lanes, lane (col, t) =
+// (tid mod TA, tid / TA) loads the positions t + i L/16 of its column
+// straight into registers (runs of TA adjacent columns per row: coalesced),
+// runs the first radix-16 stage there, exchanges through LDS, and keeps the
+// last stage's outputs in registers, from which it applies the four-step
+// twiddle (two table factors, one cache line per wave per load) and
+// stores.  in and out may alias (the tile's read and write sets coincide,
+// and every read precedes the first barrier).
 template <typename R, int MAXT>
-__global__ void __launch_bounds__(MAXT) k_fft_cols(const typename C2<R>::T* in,
-                                                   typename C2<R>::T* out, int64_t N, int64_t R1,
-                                                   int L, int lgL, int TA, int s_lo,
-                                                   const typename C2<R>::T* __restrict__ twL,
-                                                   const typename C2<R>::T* __restrict__ tlo,
-                                                   const typename C2<R>::T* __restrict__ thi)
-{
-    using T2 = typename C2<R>::T;
-    extern __shared__ unsigned char smem_raw[];
-    R* sre = (R*)smem_raw;
-    const int LP = col_stride<R>(L, TA);
-    R* sim = sre + TA * LP;
-    const int64_t w = blockIdx.y;
-    const int64_t c0 = xcd_tile(blockIdx.x, gridDim.x) * TA;
-    const T2* src = in + w * N;
-    T2* dst = out + w * N;
-    int tsh = 0;
-    while ((1 << tsh) < TA) ++tsh;
-    const int col = threadIdx.x & (TA - 1), t = threadIdx.x >> tsh;
-    const int L8 = L / 8;
-    const int64_t cg = c0 + col;
-    R xr[8], xi[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const T2 v = src[cg + R1 * (int64_t)(t + i * L8)];
-        xr[i] = v.x;
-        xi[i] = v.y;
-    }
-    fft_regs<R, true>(sre + col * LP, sim + col * LP, L, lgL, t, twL, xr, xi);
-    const int64_t lomask = ((int64_t)1 << s_lo) - 1;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int k2 = t + i * L8;
-        const int64_t e = cg * (int64_t)k2;      // < N
-        const T2 a = thi[e >> s_lo], b = tlo[e & lomask];
-        const R wr = a.x * b.x - a.y * b.y, wi = a.x * b.y + a.y * b.x;
-        R yr = xr[i], yi = xi[i];
-        cmul(yr, yi, wr, wi);
-        dst[cg + R1 * (int64_t)k2] = T2{yr, yi};
-    }
-}
-
-// pass A with 16 values per lane: TA columns per workgroup, TA * L / 16
-// lanes, lane (col, t) = (tid mod TA, tid / TA) holding the positions
-// t + i L/16 of its column.  SPLIT: re and im share one LDS array in turn.
-template <typename R, int MAXT, bool SPLIT>
 __global__ void __launch_bounds__(MAXT) k_fft_cols16(const typename C2<R>::T* in,
                                                      typename C2<R>::T* out, int64_t N,
-                                                     int64_t R1, int L, int lgL, int TA, int s_lo,
+                                                     int64_t R1, int L, int lgL, int TA,
                                                      const typename C2<R>::T* __restrict__ twL,
                                                      const typename C2<R>::T* __restrict__ tTb,
                                                      const typename C2<R>::T* __restrict__ tTs)
@@ -193,8 +130,7 @@ __global__ void __launch_bounds__(MAXT) k_fft_cols16(const typename C2<R>::T* in
     extern __shared__ unsigned char smem_raw[];
     R* sre = (R*)smem_raw;
     const int LP = col_stride<R>(L, TA);
-    R* sim = SPLIT ? sre : sre + TA * LP;
-    (void)s_lo;
+    R* sim = sre + TA * LP;
     const int64_t w = blockIdx.y;
     const int64_t c0 = xcd_tile(blockIdx.x, gridDim.x) * TA;
     const T2* src = in + w * N;
@@ -212,7 +148,7 @@ __global__ void __launch_bounds__(MAXT) k_fft_cols16(const typename C2<R>::T* in
         xi[i] = v.y;
     }
     const T2 bt = tTb[(int64_t)t * R1 + cg];        // W_N^{cg t}
-    fft16_regs<R, SPLIT>(sre + col * LP, sim + col * LP, L, lgL, t, twL, xr, xi);
+    fft16_regs<R>(sre + col * LP, sim + col * LP, L, lgL, t, twL, xr, xi);
     const int RL = last_radix16(lgL);
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
@@ -263,46 +199,29 @@ static hipError_t fft_typed(const Plan& p, int64_t B, const void* in, void* ws, 
     const bool f64 = sizeof(R) == 8;
     const T2* tA = (const T2*)(twb + (f64 ? t.oA : t.fA));
     const T2* tB = (const T2*)(twb + (f64 ? t.oB : t.fB));
-    const T2* tlo = (const T2*)(twb + (f64 ? t.olo : t.flo));
-    const T2* thi = (const T2*)(twb + (f64 ? t.ohi : t.fhi));
     const T2* tTb = (const T2*)(twb + (f64 ? t.oTb : t.fTb));
     const T2* tTs = (const T2*)(twb + (f64 ? t.oTs : t.fTs));
     T2* z = (T2*)(base + p.off_z);
     const int LA = (int)p.R2, LB = (int)p.R1;
-    const size_t ldsA =
-        (size_t)p.TA * col_stride<R>(LA, p.TA) * (p.split ? 1 : 2) * sizeof(R);
+    const size_t ldsA = cols_lds_bytes(p.prec, p.R2, p.TA);
     const size_t ldsB = (size_t)padded_len<R>(LB) * 2 * sizeof(R);
-    const void* kA;
-    const int ntA = p.TA * LA / p.colsE, ntB = LB / 8;
-    if (ntA > 1024 || ntB > 512 || LA < p.colsE) return hipErrorInvalidValue;
-    if (p.colsE == 16) {
-        if (p.split) kA = ntA <= 512 ? (const void*)k_fft_cols16<R, 512, true>
-                                     : (const void*)k_fft_cols16<R, 1024, true>;
-        else kA = ntA <= 512 ? (const void*)k_fft_cols16<R, 512, false>
-                             : (const void*)k_fft_cols16<R, 1024, false>;
-    } else {
-        kA = ntA <= 512 ? (const void*)k_fft_cols<R, 512> : (const void*)k_fft_cols<R, 1024>;
-    }
-    hipError_t ae = allow_lds(kA, ldsA);
+    const int ntA = p.TA * LA / 16, ntB = LB / 8;
+    if (ntA > 1024 || ntB > 512 || LA < 16) return hipErrorInvalidValue;
+    const bool big = ntA > 512;
+    hipError_t ae = big ? allow_lds((const void*)k_fft_cols16<R, 1024>, ldsA)
+                        : allow_lds((const void*)k_fft_cols16<R, 512>, ldsA);
     if (ae == hipSuccess && rows) ae = allow_lds((const void*)k_fft_rows<R, 512>, ldsB);
     if (ae != hipSuccess) return ae;
     const T2* src = (const T2*)(in ? in : z);
+    const dim3 gA((unsigned)(p.R1 / p.TA), (unsigned)B), bA((unsigned)ntA);
     trace_mark(ST_FFT_COLS, s, true);
-    {
-        // the pass-A kernels share one signature; arguments by address
-        const T2* a_in = src;
-        T2* a_out = z;
-        int64_t a_N = p.N, a_R1 = p.R1;
-        int a_L = LA, a_lgL = p.m2, a_TA = p.TA, a_slo = p.s_lo;
-        const T2* a_tw = tA;
-        const T2* a_tlo = (p.colsE == 16) ? tTb : tlo;   // the 16-per-lane kernel takes
-        const T2* a_thi = (p.colsE == 16) ? tTs : thi;   // the two factor tables
-        void* args[] = {&a_in, &a_out, &a_N, &a_R1, &a_L, &a_lgL, &a_TA, &a_slo, &a_tw, &a_tlo, &a_thi};
-        ae = hipLaunchKernel(kA, dim3((unsigned)(p.R1 / p.TA), (unsigned)B), dim3((unsigned)ntA),
-                             args, ldsA, s);
-    }
+    if (big)
+        hipLaunchKernelGGL((k_fft_cols16<R, 1024>), gA, bA, ldsA, s, src, z, p.N, p.R1, LA, p.m2,
+                           p.TA, tA, tTb, tTs);
+    else
+        hipLaunchKernelGGL((k_fft_cols16<R, 512>), gA, bA, ldsA, s, src, z, p.N, p.R1, LA, p.m2,
+                           p.TA, tA, tTb, tTs);
     trace_mark(ST_FFT_COLS, s, false);
-    if (ae != hipSuccess) return ae;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !rows) return e;
     trace_mark(ST_FFT_ROWS, s, true);

@@ -20,16 +20,9 @@ template <typename R> struct C2;
 template <> struct C2<double> { using T = double2; };
 template <> struct C2<float> { using T = float2; };
 
-// pad one slot per 2^PadShift<R> elements
-#ifndef EMRI_PAD_F64
-#define EMRI_PAD_F64 4
-#endif
-#ifndef EMRI_PAD_F32
-#define EMRI_PAD_F32 4
-#endif
-template <typename R> struct PadShift;
-template <> struct PadShift<double> { static constexpr int v = EMRI_PAD_F64; };
-template <> struct PadShift<float> { static constexpr int v = EMRI_PAD_F32; };
+// pad one slot per 2^PadShift<R> elements (one per 16: other paddings lowered
+// the bank-conflict counters of some stages on MI355X but not the time)
+template <typename R> struct PadShift { static constexpr int v = 4; };
 template <typename R>
 __device__ __host__ inline int px(int i) { return i + (i >> PadShift<R>::v); }
 // LDS elements (per re or im array) of a padded column of length L
@@ -423,30 +416,18 @@ __device__ __forceinline__ void get_slots16(const R* buf, R (&x)[16], int L, int
 }
 
 // exchange between a stage of radix RA (outputs) and one of radix RB
-// (inputs).  SPLIT passes the real parts first and then the imaginary
-// parts through one array (half the LDS, two more barriers); otherwise re
-// and im go through two arrays at once.  Starts with a barrier, so the
+// (inputs) through the two LDS arrays.  Starts with a barrier, so the
 // caller's previous reads of the arrays are complete before they are reused.
-template <typename R, int RA, int RB, bool SPLIT>
+template <typename R, int RA, int RB>
 __device__ __forceinline__ void exchange16(R* re, R* im, R (&xr)[16], R (&xi)[16], int L, int Ns,
                                            int t)
 {
     __syncthreads();
-    if constexpr (SPLIT) {
-        put_slots16<R, RA>(re, xr, L, Ns, t);
-        __syncthreads();
-        get_slots16<R, RB>(re, xr, L, t);
-        __syncthreads();
-        put_slots16<R, RA>(re, xi, L, Ns, t);
-        __syncthreads();
-        get_slots16<R, RB>(re, xi, L, t);
-    } else {
-        put_slots16<R, RA>(re, xr, L, Ns, t);
-        put_slots16<R, RA>(im, xi, L, Ns, t);
-        __syncthreads();
-        get_slots16<R, RB>(re, xr, L, t);
-        get_slots16<R, RB>(im, xi, L, t);
-    }
+    put_slots16<R, RA>(re, xr, L, Ns, t);
+    put_slots16<R, RA>(im, xi, L, Ns, t);
+    __syncthreads();
+    get_slots16<R, RB>(re, xr, L, t);
+    get_slots16<R, RB>(im, xi, L, t);
 }
 
 // radix of the last stage of an L = 2^lgL point transform (16 if lgL is a
@@ -460,7 +441,7 @@ __device__ __forceinline__ int slot_pos16(int s, int RL) { return (s % RL) * (16
 // holds the transform at position t + slot_pos16(s, last_radix16(lgL)) L/16.
 // Stage radices: 16 as often as fits, then the remainder (2, 4 or 8).
 // Every lane of the workgroup must call it with the same L (barriers).
-template <typename R, bool SPLIT>
+template <typename R>
 __device__ __forceinline__ void fft16_regs(R* re, R* im, int L, int lgL, int t,
                                            const typename C2<R>::T* __restrict__ tw,
                                            R (&xr)[16], R (&xi)[16])
@@ -469,21 +450,21 @@ __device__ __forceinline__ void fft16_regs(R* re, R* im, int L, int lgL, int t,
     dft_slots16<R, 16>(xr, xi);              // stage 1: Ns = 1, no twiddles
     int Ns = 16;                             // product of the radices so far
     for (int st = 1; st < n16; ++st) {
-        exchange16<R, 16, 16, SPLIT>(re, im, xr, xi, L, Ns / 16, t);
+        exchange16<R, 16, 16>(re, im, xr, xi, L, Ns / 16, t);
         twiddle_slots16<R, 16>(xr, xi, L, Ns, t, tw);
         dft_slots16<R, 16>(xr, xi);
         Ns *= 16;
     }
     if (rem == 1) {
-        exchange16<R, 16, 2, SPLIT>(re, im, xr, xi, L, Ns / 16, t);
+        exchange16<R, 16, 2>(re, im, xr, xi, L, Ns / 16, t);
         twiddle_slots16<R, 2>(xr, xi, L, Ns, t, tw);
         dft_slots16<R, 2>(xr, xi);
     } else if (rem == 2) {
-        exchange16<R, 16, 4, SPLIT>(re, im, xr, xi, L, Ns / 16, t);
+        exchange16<R, 16, 4>(re, im, xr, xi, L, Ns / 16, t);
         twiddle_slots16<R, 4>(xr, xi, L, Ns, t, tw);
         dft_slots16<R, 4>(xr, xi);
     } else if (rem == 3) {
-        exchange16<R, 16, 8, SPLIT>(re, im, xr, xi, L, Ns / 16, t);
+        exchange16<R, 16, 8>(re, im, xr, xi, L, Ns / 16, t);
         twiddle_slots16<R, 8>(xr, xi, L, Ns, t, tw);
         dft_slots16<R, 8>(xr, xi);
     }

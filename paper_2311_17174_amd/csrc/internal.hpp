@@ -80,10 +80,6 @@ struct Plan {
     int m1, m2;
     int64_t R1, R2;
     int TA;                // columns per pass-A workgroup
-    int colsE;             // values per lane in pass A (8 or 16)
-    int split;             // pass A (16 per lane) exchanges re, then im
-                           // through one LDS array
-    int s_lo;              // split of the four-step twiddle exponent
     size_t esz;            // bytes per complex element (16 or 8)
     size_t hsz;            // bytes per harmonic coefficient (8 or 4)
     // workspace (bytes, for B walkers)
@@ -98,15 +94,15 @@ emri_status make_plan(const emri_cfg* cfg, int64_t B, Plan* p, const char** err)
 
 // twiddle table layout inside the tw region (complex fp64 then fp32 copies)
 struct TwLayout {
-    int64_t nA, nB, nlo, nhi;     // entries of each table
-    int64_t nTb, nTs;             // pass-A four-step factors (16 per lane)
-    size_t oA, oB, olo, ohi, oTb, oTs;   // fp64 tables (double2)
-    size_t fA, fB, flo, fhi, fTb, fTs;   // fp32 tables (float2)
+    int64_t nA, nB;               // W_R2^e, W_R1^e
+    int64_t nTb, nTs;             // pass-A four-step factors
+    size_t oA, oB, oTb, oTs;      // fp64 tables (double2)
+    size_t fA, fB, fTb, fTs;      // fp32 tables (float2)
     size_t bytes;
 };
 TwLayout tw_layout(const Plan& p);
 // LDS bytes of a pass-A tile of TA columns of R2 points
-size_t cols_lds_bytes(int prec, int64_t R2, int TA, int split);
+size_t cols_lds_bytes(int prec, int64_t R2, int TA);
 
 // ---- launchers (return hipSuccess or the launch error) -------------------
 // the orbit is integrated in segments [k_i, k_{i+1}) of coarse steps so that

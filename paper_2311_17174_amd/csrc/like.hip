@@ -23,8 +23,6 @@
 // fixed order (results do not depend on how walkers are batched).
 #include "fft_lds.hpp"
 
-#include <stdlib.h>
-
 namespace emri {
 
 // ---------------------------------------------------------------------------
@@ -402,7 +400,7 @@ k_rows_like16(const typename C2<R>::T* __restrict__ z, int64_t N, int L, int lgL
             ar[i] = v.x;
             ai[i] = v.y;
         }
-        fft16_regs<R, false>(sre, sim, L, lgL, t, twL, ar, ai);
+        fft16_regs<R>(sre, sim, L, lgL, t, twL, ar, ai);
         if (!self) {
             R br[16], bi[16];
 #pragma unroll
@@ -411,7 +409,7 @@ k_rows_like16(const typename C2<R>::T* __restrict__ z, int64_t N, int L, int lgL
                 br[i] = v.x;
                 bi[i] = v.y;
             }
-            fft16_regs<R, false>(sre, sim, L, lgL, t, twL, br, bi);
+            fft16_regs<R>(sre, sim, L, lgL, t, twL, br, bi);
             __syncthreads();
 #pragma unroll
             for (int s = 0; s < 16; ++s) {
@@ -478,8 +476,7 @@ hipError_t launch_likelihood(const Plan& p, int64_t B, const void* ds, void* ws,
     const double* wc = (const double*)(base + p.off_wc);
     double* part = (double*)(base + p.off_part);
     const int L = (int)p.R1;
-    int WT = (B >= 128) ? 8 : (B >= 16 ? 4 : 1);
-    if (const char* env = getenv("EMRI_LIKE_WT")) WT = atoi(env) > 0 ? atoi(env) : WT;
+    const int WT = (B >= 128) ? 8 : (B >= 16 ? 4 : 1);
     const size_t lds = (p.prec == EMRI_FP64) ? (size_t)padded_len<double>(L) * 2 * 8
                                              : (size_t)padded_len<float>(L) * 2 * 4;
     const int64_t nparts = p.R2 / 2 + 1;
@@ -487,17 +484,14 @@ hipError_t launch_likelihood(const Plan& p, int64_t B, const void* ds, void* ws,
     dim3 grid((unsigned)(((nparts + 7) / 8) * 8 * ntiles));
     const TwLayout tl = tw_layout(p);
     const char* twb = base + p.off_tw;
-    // FP32 rows take 16 values per lane (EMRI_LIKE_E=8 selects the 8-per-lane
-    // kernel); FP64 keeps 8: two rows of 16 FP64 values do not fit 128 VGPRs
-    int E = (p.prec == EMRI_FP64) ? 8 : 16;
-    if (const char* env = getenv("EMRI_LIKE_E")) E = (atoi(env) == 8) ? 8 : E;
-    const void* kern;
-    if (p.prec == EMRI_FP64) kern = (const void*)k_rows_like<double, false, 512>;
-    else if (E == 16) kern = (const void*)k_rows_like16<float, true, 256>;
-    else kern = (const void*)k_rows_like<float, true, 512>;
+    // FP32 rows take 16 values per lane; FP64 keeps 8: two rows of 16 FP64
+    // values do not fit 128 registers
+    const int E = (p.prec == EMRI_FP64) ? 8 : 16;
+    const void* kern = (p.prec == EMRI_FP64) ? (const void*)k_rows_like<double, false, 512>
+                                             : (const void*)k_rows_like16<float, true, 256>;
     hipError_t ae = allow_lds(kern, lds);
     if (ae != hipSuccess) return ae;
-    if (L / E > 512 || L < 16) return hipErrorInvalidValue;   // rows of 2^7 .. 2^12 points
+    if (L / E > 512 || L < 16 * (E / 8)) return hipErrorInvalidValue;   // rows of 2^7 .. 2^12 points
     const dim3 blk((unsigned)(L / E));
     const void* dsd = (const void*)(db + p.ds_off_d);
     const void* dsw = (const void*)(db + p.ds_off_w);

@@ -17,6 +17,11 @@
  *  - Every call is asynchronous on `stream` (0 = the null stream).  Inputs
  *    must stay valid, and outputs must not be read, until the stream has
  *    reached the call's end.  Calls that share a workspace must be ordered.
+ *    Waveform generation may also run on an auxiliary stream the library
+ *    keeps per (device, caller stream), created on the first call; it is
+ *    forked from and joined back into `stream` by events within the call
+ *    (also under stream capture), so `stream` alone orders the call.  The
+ *    auxiliary streams are the only resources the library keeps.
  *  - Call-level errors (null pointer, bad configuration, workspace too
  *    small, launch failure) return a negative status and launch nothing new;
  *    emri_last_error() then describes the error (per host thread).
@@ -166,7 +171,9 @@ emri_status emri_model_batch(const double* params, int64_t B, const emri_cfg* cf
 emri_status emri_noise_psd(int model, int64_t N, double dt, double* psd, hipStream_t stream);
 
 /* Per-stage device timing (profiling).  While enabled, every kernel launch
- * of the library is bracketed by HIP events on its stream.
+ * of the library is bracketed by HIP events on the stream it runs on; with
+ * the auxiliary stream, stages overlap and their sum exceeds the call's
+ * duration.
  * emri_trace_read synchronises the recorded events, writes for each stage i
  * (0 <= i < n) the summed duration in ms and the number of launches since the
  * previous read, and returns the number of stages.  Stage names come from

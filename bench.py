@@ -110,11 +110,81 @@ def run_path(E, W, w, P, data, psd, steps, warmup):
     return (t1 - t0), stages, np.array(lat), out.cpu().numpy()
 
 
+def noise_weighted_mismatch(a, b, psd, df):
+    """1 - <a|b> / sqrt(<a|a><b|b>) per walker, <a|b> = 4 df sum_{I,II}
+    sum_{k=1}^{N/2-1} Re(conj(a) b) / S_k (no maximisation over time or
+    phase).  a, b: [W][2][N/2+1] complex (device), psd [N/2+1]."""
+    import torch
+    a = a.to(torch.complex128)[..., 1:-1]
+    b = b.to(torch.complex128)[..., 1:-1]
+    w = (4.0 * df / psd[1:-1]).to(torch.float64)
+
+    def ip(x, y):
+        return ((x.conj() * y).real * w).sum(dim=(1, 2))
+
+    m = 1.0 - ip(a, b) / torch.sqrt(ip(a, a) * ip(b, b))
+    return m.cpu().numpy()
+
+
+def run_config5(E, W, steps: int, warmup: int, ws_gib: float):
+    """Stress configuration: 1024 walkers, 2 yr at dt = 5 s (2^24 samples),
+    40 harmonics; the workspace holds a fraction of the batch, so the call
+    runs in HBM-admitted chunks.  FP64 and mixed on the same inputs."""
+    import torch
+    out = {}
+    w5 = W.config5("fp64")
+    P = torch.from_numpy(W.walkers(w5)).cuda()
+    cfg = E.Config.from_workload(w5)
+    psd = E.noise_psd(w5.N, w5.dt)
+    minj = E.model_batch(torch.from_numpy(w5.inj[None]).cuda(), cfg)[0]
+    g = torch.from_numpy(W.gaussian_draws(w5.N, w5.noise_seed)).cuda()
+    sig = torch.sqrt(psd * (w5.N * w5.dt / 4.0))
+    sig[0] = 0.0
+    sig[-1] = 0.0
+    data = (torch.view_as_real(minj).clone() + sig[None, :, None] * g).contiguous()
+    del minj, g, sig
+    # share of the window after the injection's plunge (zero samples)
+    h = E.waveform_batch(torch.from_numpy(w5.inj[None]).cuda(), cfg)[0]
+    nz = torch.nonzero(h.abs().sum(dim=1)).max().item() + 1
+    del h
+    ws = torch.empty(int(ws_gib * (1 << 30)), dtype=torch.uint8, device="cuda")
+    lnl = {}
+    for prec in ("fp64", "mixed"):
+        w = W.config5(prec)
+        c = E.Config.from_workload(w)
+        per = E.workspace_bytes(c, 1)
+        chunk = 1
+        while chunk < w.B and E.workspace_bytes(c, 2 * chunk) + E.dataset_bytes(c) + 256 <= ws.numel():
+            chunk *= 2
+        res = torch.empty(w.B, dtype=torch.float64, device="cuda")
+        for _ in range(warmup):
+            E.loglike_batch(P, data, psd, c, out=res, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            E.loglike_batch(P, data, psd, c, out=res, ws=ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        lnl[prec] = res.cpu().numpy()
+        out[prec] = {"value": w.B / dt, "unit": "lnL evals/s", "ms_per_step": 1e3 * dt,
+                     "walkers_per_chunk_at_least": chunk,
+                     "workspace_gib": ws.numel() / 2 ** 30,
+                     "workspace_per_walker_mib": per / 2 ** 20}
+    rel = np.abs(lnl["mixed"] - lnl["fp64"]) / np.abs(lnl["fp64"])
+    out.update({"workload": w5.name, "walkers": w5.B, "samples": w5.N, "n_harm": w5.n_harm,
+                "dt": w5.dt, "injection_zero_tail_fraction": 1.0 - nz / w5.N,
+                "mixed_vs_fp64_max_rel_dlnL": float(rel.max()), "steps": steps})
+    del ws, data
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_serving(E, W, n_burst: int, n_requests: int, arena_gib: float, n_streams: int,
-                max_batch: int):
+                max_batch: int, n_sweep: int = 0):
     """Serving loop (mixed precision): 8 chains x 3 observation times of
     resident data, Poisson request arrivals at 0.8x the saturated rate
-    measured first with a burst; returns the report dict."""
+    measured first with a burst, then n_sweep requests each at 0.5x and
+    1.0x; returns the report dict."""
     import threading
     import queue
     import torch
@@ -141,40 +211,55 @@ def run_serving(E, W, n_burst: int, n_requests: int, arena_gib: float, n_streams
         gap, c, t, Wn, seed = req
         return W.walkers(ids[(c, t)][1], B=Wn, seed=seed)
 
-    reqs = W.serving_requests(n_burst + n_requests)
-    burst, timed = reqs[:n_burst], reqs[n_burst:]
+    reqs = W.serving_requests(n_burst + n_requests + 2 * n_sweep)
+    burst, timed = reqs[:n_burst], reqs[n_burst:n_burst + n_requests]
+    sweep_reqs = reqs[n_burst + n_requests:]
     # saturated throughput: everything submitted at once
     t0 = time.perf_counter()
     tk = [srv.submit(ids[(r[1], r[2])][0], params_of(r)) for r in burst]
     for t in tk:
         srv.wait(t)
     mu = n_burst / (time.perf_counter() - t0)
+
+    def open_loop(rs, rate, keep=()):
+        """Poisson arrivals at `rate` per s; returns latencies, span, outputs kept"""
+        arrivals = np.cumsum([r[0] for r in rs]) / rate
+        pre = [params_of(r) for r in rs]
+        q = queue.Queue()
+        lat = np.zeros(len(rs))
+        kept = {}
+
+        def collect():
+            for _ in range(len(rs)):
+                i, t = q.get()
+                out, lat[i] = srv.wait(t)
+                if i in keep:
+                    kept[i] = out.copy()
+
+        th = threading.Thread(target=collect)
+        th.start()
+        start = time.perf_counter()
+        for i, r in enumerate(rs):
+            dtw = arrivals[i] - (time.perf_counter() - start)
+            if dtw > 0:
+                time.sleep(dtw)
+            q.put((i, srv.submit(ids[(r[1], r[2])][0], pre[i])))
+        th.join()
+        return lat, time.perf_counter() - start, kept, pre
+
     lam = 0.8 * mu
-    # open-loop Poisson arrivals at lam
-    arrivals = np.cumsum([r[0] for r in timed]) / lam
-    pre = [params_of(r) for r in timed]
-    q = queue.Queue()
-    lat = np.zeros(len(timed))
-    served = {}
     sample = set(range(0, len(timed), max(1, len(timed) // 8)))
-
-    def collect():
-        for k in range(len(timed)):
-            i, t = q.get()
-            out, lat[i] = srv.wait(t)
-            if i in sample:
-                served[i] = out.copy()
-
-    th = threading.Thread(target=collect)
-    th.start()
-    start = time.perf_counter()
-    for i, r in enumerate(timed):
-        dtw = arrivals[i] - (time.perf_counter() - start)
-        if dtw > 0:
-            time.sleep(dtw)
-        q.put((i, srv.submit(ids[(r[1], r[2])][0], pre[i])))
-    th.join()
-    span = time.perf_counter() - start
+    lat, span, served, pre = open_loop(timed, lam, sample)
+    sweep = []
+    half = len(sweep_reqs) // 2
+    for frac, rs in ((0.5, sweep_reqs[:half]), (1.0, sweep_reqs[half:])):
+        if not rs:
+            continue
+        l2, sp2, _, _ = open_loop(rs, frac * mu)
+        sweep.append({"lambda_over_mu": frac, "arrival_rate_per_s": frac * mu,
+                      "requests": len(rs), "p50_ms": float(np.percentile(l2, 50) * 1e3),
+                      "p99_ms": float(np.percentile(l2, 99) * 1e3),
+                      "evals_per_s": sum(r[3] for r in rs) / sp2})
     st = srv.stats()
     srv.close()
     # the same walkers alone (eager emri_loglike_dataset) must give the same bits
@@ -200,7 +285,7 @@ def run_serving(E, W, n_burst: int, n_requests: int, arena_gib: float, n_streams
         "batches": st["batches"], "graph_launches": st["graph_launches"],
         "graph_captures": st["graph_captures"], "padded_walkers": st["padded_walkers"],
         "arena_gib": arena_gib, "arena_peak_gib": st["arena_peak"] / 2 ** 30,
-        "n_streams": n_streams, "max_batch": max_batch,
+        "n_streams": n_streams, "max_batch": max_batch, "rate_sweep": sweep,
     }
 
 
@@ -218,6 +303,12 @@ def main():
                     help="timed serving requests (the full serving workload is 10000)")
     ap.add_argument("--serve-burst", type=int, default=60)
     ap.add_argument("--serve-arena-gib", type=float, default=160.0)
+    ap.add_argument("--serve-sweep", type=int, default=100,
+                    help="requests at each of 0.5x and 1.0x the saturated rate")
+    ap.add_argument("--no-config5", action="store_true")
+    ap.add_argument("--config5-steps", type=int, default=2)
+    ap.add_argument("--config5-ws-gib", type=float, default=100.0,
+                    help="workspace for the 1024-walker stress case (it runs in chunks)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (scale reference for "
                          "HBM byte counters)")
@@ -278,6 +369,16 @@ def main():
                              "max_abs_dlnL": float(np.abs(lnlm - lnl64).max())},
             "stages_ms_per_step": {k: v[0] / args.steps for k, v in stm.items()},
         }
+        # waveform mismatch of the mixed path against the FP64 path (whose
+        # parity with the oracle is tested) on the first 16 walkers
+        cmx = E.Config.from_workload(wmx)
+        Pd = torch.from_numpy(P[:16]).cuda()
+        mm = noise_weighted_mismatch(E.model_batch(Pd, cmx), E.model_batch(Pd, cfg64), psd,
+                                     1.0 / (w64.N * w64.dt))
+        mixed["vs_fp64_path"]["mismatch_max"] = float(np.max(np.abs(mm)))
+        mixed["vs_fp64_path"]["mismatch_walkers"] = 16
+        # <d|d> is common to both paths, so max_abs_dlnL is also the error of
+        # the signal part lnL + <d|d>/2
         print(f"[bench] mixed: {mixed['value']:.1f} evals/s", file=sys.stderr, flush=True)
 
     serving = None
@@ -285,10 +386,19 @@ def main():
         torch.cuda.empty_cache()
         print("[bench] serving loop", file=sys.stderr, flush=True)
         serving = run_serving(E, W, args.serve_burst, args.serve_requests,
-                              args.serve_arena_gib, 4, 512)
+                              args.serve_arena_gib, 4, 512, args.serve_sweep)
         print(f"[bench] serving: {serving['evals_per_s']:.1f} evals/s, p50 "
               f"{serving['latency_ms']['p50']:.1f} ms, p99 {serving['latency_ms']['p99']:.1f} ms",
               file=sys.stderr, flush=True)
+
+    config5 = None
+    if not args.no_config5:
+        torch.cuda.empty_cache()
+        print("[bench] stress configuration (1024 walkers, 2^24 samples)", file=sys.stderr,
+              flush=True)
+        config5 = run_config5(E, W, args.config5_steps, 1, args.config5_ws_gib)
+        print(f"[bench] config 5: fp64 {config5['fp64']['value']:.1f} evals/s, mixed "
+              f"{config5['mixed']['value']:.1f} evals/s", file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel of the value path
     valid = w64.B * w64.n_valid
@@ -356,6 +466,7 @@ def main():
         "cpu_baseline": cpu,
         "mixed": mixed,
         "serving": serving,
+        "stress": config5,
         "stages": stages_out,
     }
     print(json.dumps(rec), flush=True)

@@ -104,6 +104,14 @@ def lib():
             "oracle_dl_of_z": ([ctypes.c_double], ctypes.c_double),
             "oracle_z_of_dl": ([ctypes.c_double], ctypes.c_double),
             "oracle_num_threads": ([], ctypes.c_int),
+            "oracle_stretch_propose": ([dp, i64, ctypes.c_int32, ip, ctypes.c_int32, dp, dp,
+                                        ctypes.c_double, dp, dp, dp, dp], ctypes.c_int),
+            "oracle_stretch_accept": ([dp, dp, i64, ctypes.c_int32, dp, dp, dp, dp, ip],
+                                      ctypes.c_int),
+            "oracle_ensemble_lnprob": ([dp, i64, ip, ctypes.c_int32, dp, dp, dp, dp, cp, dp],
+                                       ctypes.c_int),
+            "oracle_stretch_step": ([dp, dp, i64, ip, ctypes.c_int32, dp, dp, ctypes.c_double,
+                                     dp, dp, dp, cp, ip], ctypes.c_int),
         }
         for name, (argt, rest) in sig.items():
             f = getattr(L, name)
@@ -269,3 +277,69 @@ def z_of_dl(D_seconds: float) -> float:
 
 def num_threads() -> int:
     return lib().oracle_num_threads()
+
+
+# --------------------------------------------------------------------------
+# ensemble sampler (stretch move of Goodman & Weare 2010, two-half form)
+def _ip(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _prior(free_idx, lo, hi):
+    fi = np.ascontiguousarray(free_idx, dtype=np.int32)
+    return fi, _f64(lo), _f64(hi)
+
+
+def stretch_propose(X, h, free_idx, lo, hi, a, u):
+    """Proposals for half h of the ensemble X [2W][17]: (Y [W][17],
+    (D-1) ln z [W], log-prior [W]); u is [W][3]."""
+    X = _f64(X).reshape(-1, NPAR)
+    W = X.shape[0] // 2
+    fi, lo, hi = _prior(free_idx, lo, hi)
+    u = _f64(u).reshape(W, 3)
+    Y = np.zeros((W, NPAR))
+    lnz = np.zeros(W)
+    lpr = np.zeros(W)
+    _check(lib().oracle_stretch_propose(_p(X), W, int(h), _ip(fi), len(fi), _p(lo), _p(hi),
+                                        float(a), _p(u), _p(Y), _p(lnz), _p(lpr)), "propose")
+    return Y, lnz, lpr
+
+
+def stretch_accept(X, lnp, h, Y, lnpY, lnz, u):
+    """Acceptance for half h; updates X [2W][17] and lnp [2W] in place and
+    returns the accepted flags [2W] (entries of the other half are 0)."""
+    W = X.shape[0] // 2
+    acc = np.zeros(2 * W, dtype=np.int32)
+    _check(lib().oracle_stretch_accept(_p(X), _p(lnp), W, int(h), _p(_f64(Y)), _p(_f64(lnpY)),
+                                       _p(_f64(lnz)), _p(_f64(u).reshape(W, 3)), _ip(acc)),
+           "accept")
+    return acc
+
+
+def ensemble_lnprob(X, free_idx, lo, hi, data, psd, cfg: OracleConfig) -> np.ndarray:
+    X = _f64(X).reshape(-1, NPAR)
+    fi, lo, hi = _prior(free_idx, lo, hi)
+    d = _cplx_pairs(data)
+    s = _f64(psd)
+    out = np.zeros(X.shape[0])
+    c = cfg.c()
+    _check(lib().oracle_ensemble_lnprob(_p(X), X.shape[0], _ip(fi), len(fi), _p(lo), _p(hi),
+                                        _p(d), _p(s), ctypes.byref(c), _p(out)), "lnprob")
+    return out
+
+
+def stretch_step(X, lnp, free_idx, lo, hi, a, u, data, psd, cfg: OracleConfig):
+    """One step of the ensemble X [2W][17] with log-posteriors lnp [2W];
+    u [2][W][3].  Returns (X, lnp, accepted) as new arrays."""
+    X = _f64(X).reshape(-1, NPAR).copy()
+    lnp = _f64(lnp).copy()
+    W = X.shape[0] // 2
+    fi, lo, hi = _prior(free_idx, lo, hi)
+    d = _cplx_pairs(data)
+    s = _f64(psd)
+    acc = np.zeros(2 * W, dtype=np.int32)
+    c = cfg.c()
+    _check(lib().oracle_stretch_step(_p(X), _p(lnp), W, _ip(fi), len(fi), _p(lo), _p(hi),
+                                     float(a), _p(_f64(u).reshape(2, W, 3)), _p(d), _p(s),
+                                     ctypes.byref(c), _ip(acc)), "stretch step")
+    return X, lnp, acc

@@ -773,3 +773,125 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* ======================================================================== */
+/* Ensemble sampler step: the affine-invariant stretch move of Goodman &    */
+/* Weare (2010) that the paper's sampler (emcee, Sec. 1 iii and Sec. 3      */
+/* "Posterior sampling") applies to the walker matrix, in its parallel form */
+/* where the ensemble of 2W walkers is split into two halves updated in     */
+/* turn, each against the other.                                             */
+/*                                                                           */
+/* For walker k of half h: a partner j is drawn uniformly from the other     */
+/* half; the stretch z has density proportional to 1/sqrt(z) on [1/a, a],    */
+/* drawn by inverting its distribution function, F(z) = (sqrt(a z) - 1) /   */
+/* (a - 1); the proposal moves the free coordinates to X_j + z (X_k - X_j)   */
+/* and keeps the others; it is accepted with probability                     */
+/* min(1, z^(D-1) p(Y) / p(X_k)), D the number of free coordinates.          */
+/* Readings: the log-prior is flat inside a box on the free coordinates and  */
+/* -inf outside (the paper's priors are not printed); a proposal with log-   */
+/* posterior -inf is rejected, a walker at -inf accepts any finite proposal. */
+/* The random numbers are inputs, three per walker and half: u0 picks the    */
+/* partner, u1 the stretch, u2 decides acceptance (all in [0, 1)).           */
+/* ======================================================================== */
+
+/* proposals, their (D-1) ln z and log-prior, for half h of 2W walkers */
+int oracle_stretch_propose(const double *X, int64_t W, int32_t h, const int32_t *free_idx,
+                           int32_t D, const double *lo, const double *hi, double a,
+                           const double *u /* [W][3] */, double *Y /* [W][NPAR] */,
+                           double *lnz /* [W] */, double *lnprior /* [W] */)
+{
+    if (W < 1 || h < 0 || h > 1 || D < 1 || D > NPAR || !(a > 1.0)) return -1;
+    for (int64_t k = 0; k < W; ++k) {
+        const double *xk = X + (h * W + k) * NPAR;
+        int64_t j = (int64_t)floor(u[3 * k] * (double)W);
+        if (j < 0) j = 0;
+        if (j > W - 1) j = W - 1;
+        const double *xj = X + ((1 - h) * W + j) * NPAR;
+        const double s = (a - 1.0) * u[3 * k + 1] + 1.0;   /* s = sqrt(a z) */
+        const double z = s * s / a;
+        double *y = Y + k * NPAR;
+        for (int i = 0; i < NPAR; ++i) y[i] = xk[i];
+        int inside = 1;
+        for (int d = 0; d < D; ++d) {
+            const int i = free_idx[d];
+            y[i] = xj[i] + z * (xk[i] - xj[i]);
+            if (!(y[i] >= lo[d] && y[i] <= hi[d])) inside = 0;
+        }
+        lnz[k] = (double)(D - 1) * log(z);
+        lnprior[k] = inside ? 0.0 : -INFINITY;
+    }
+    return 0;
+}
+
+/* acceptance for half h, given the proposals' log-posteriors lnpY */
+int oracle_stretch_accept(double *X, double *lnp, int64_t W, int32_t h, const double *Y,
+                          const double *lnpY, const double *lnz, const double *u /* [W][3] */,
+                          int32_t *accepted /* [2W] */)
+{
+    if (W < 1 || h < 0 || h > 1) return -1;
+    for (int64_t k = 0; k < W; ++k) {
+        const int64_t g = h * W + k;
+        const double lold = lnp[g], lnew = lnpY[k];
+        int take;
+        if (!(lnew > -INFINITY)) take = 0;            /* -inf or NaN */
+        else if (!(lold > -INFINITY)) take = 1;
+        else take = log(u[3 * k + 2]) < lnz[k] + lnew - lold;
+        if (take) {
+            for (int i = 0; i < NPAR; ++i) X[g * NPAR + i] = Y[k * NPAR + i];
+            lnp[g] = lnew;
+        }
+        accepted[g] = take;
+    }
+    return 0;
+}
+
+static double box_lnprior(const double *p, const int32_t *free_idx, int32_t D, const double *lo,
+                          const double *hi)
+{
+    for (int d = 0; d < D; ++d) {
+        const double v = p[free_idx[d]];
+        if (!(v >= lo[d] && v <= hi[d])) return -INFINITY;
+    }
+    return 0.0;
+}
+
+/* log-posterior of n walkers: box prior plus log-likelihood */
+int oracle_ensemble_lnprob(const double *X, int64_t n, const int32_t *free_idx, int32_t D,
+                           const double *lo, const double *hi, const double *data,
+                           const double *psd, const oracle_cfg *c, double *lnp)
+{
+    if (n < 1 || D < 1 || D > NPAR) return -1;
+    int rc = oracle_loglike(X, n, data, psd, c, lnp);
+    if (rc) return rc;
+    for (int64_t k = 0; k < n; ++k) lnp[k] += box_lnprior(X + k * NPAR, free_idx, D, lo, hi);
+    return 0;
+}
+
+/* one step of the ensemble of 2W walkers: half 0 against half 1, then half
+ * 1 against the updated half 0; u is [2][W][3] */
+int oracle_stretch_step(double *X, double *lnp, int64_t W, const int32_t *free_idx, int32_t D,
+                        const double *lo, const double *hi, double a, const double *u,
+                        const double *data, const double *psd, const oracle_cfg *c,
+                        int32_t *accepted)
+{
+    if (W < 1 || D < 1 || D > NPAR || !(a > 1.0)) return -1;
+    double *Y = (double *)malloc((size_t)W * NPAR * sizeof(double));
+    double *lnz = (double *)malloc((size_t)W * sizeof(double));
+    double *lpr = (double *)malloc((size_t)W * sizeof(double));
+    double *lnL = (double *)malloc((size_t)W * sizeof(double));
+    int rc = (Y && lnz && lpr && lnL) ? 0 : -2;
+    for (int h = 0; h < 2 && rc == 0; ++h) {
+        const double *uh = u + (int64_t)h * W * 3;
+        rc = oracle_stretch_propose(X, W, h, free_idx, D, lo, hi, a, uh, Y, lnz, lpr);
+        if (rc == 0) rc = oracle_loglike(Y, W, data, psd, c, lnL);
+        if (rc == 0) {
+            for (int64_t k = 0; k < W; ++k) lnL[k] += lpr[k];
+            rc = oracle_stretch_accept(X, lnp, W, h, Y, lnL, lnz, uh, accepted);
+        }
+    }
+    free(Y);
+    free(lnz);
+    free(lpr);
+    free(lnL);
+    return rc;
+}

@@ -179,6 +179,45 @@ def run_config5(E, W, steps: int, warmup: int, ws_gib: float):
     return out
 
 
+def run_sampler(E, W, w, data, psd, steps: int, warmup: int):
+    """Ensemble sampler on the likelihood's workload: 2W walkers with W the
+    workload's batch, so each half is one batch; stretch scale 2, box prior on
+    the free parameters of the sampler workloads.  The uniforms of every step
+    are resident before the timed steps."""
+    import torch
+    Wh = w.B
+    fi = W.SAMPLER_FREE
+    lo, hi = W.sampler_prior(w, fi)
+    cfg = E.Config.from_workload(w)
+    prior = E.make_prior(fi, lo, hi)
+    ds = E.dataset_init(data, psd, cfg)
+    X = torch.from_numpy(W.sampler_ensemble(w, Wh, fi)).cuda()
+    U = torch.from_numpy(W.sampler_uniforms(Wh, warmup + steps)).cuda()
+    ws = torch.empty(E.sampler_workspace_bytes(cfg, Wh), dtype=torch.uint8, device="cuda")
+    lnp = E.ensemble_lnprob(X, prior, ds, cfg, ws=ws)
+    acc = torch.empty(2 * Wh, dtype=torch.int32, device="cuda")
+    for i in range(warmup):
+        E.stretch_step(X, lnp, prior, 2.0, U[i], ds, cfg, accepted=acc, ws=ws)
+    n_acc = torch.zeros((), dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    with E.Tracer() as tr:
+        t0 = time.perf_counter()
+        for i in range(steps):
+            E.stretch_step(X, lnp, prior, 2.0, U[warmup + i], ds, cfg, accepted=acc, ws=ws)
+            n_acc += acc.sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        stages = tr.read()
+    dt = (t1 - t0) / steps
+    own = stages.get("sampler", (0.0, 0))[0] / steps
+    return {"workload": w.name, "walkers": 2 * Wh, "free_parameters": len(fi),
+            "stretch_scale": 2.0, "steps": steps, "ms_per_step": 1e3 * dt,
+            "steps_per_s": 1.0 / dt, "lnL_evals_per_s": 2 * Wh / dt,
+            "sampler_kernels_ms_per_step": own, "sampler_kernels_share": own / (1e3 * dt),
+            "acceptance_fraction": float(n_acc.item()) / (2 * Wh * steps),
+            "finite_lnp_walkers": int(torch.isfinite(lnp).sum().item())}
+
+
 def run_serving(E, W, n_burst: int, n_requests: int, arena_gib: float, n_streams: int,
                 max_batch: int, n_sweep: int = 0):
     """Serving loop (mixed precision): 8 chains x 3 observation times of
@@ -305,6 +344,8 @@ def main():
     ap.add_argument("--serve-arena-gib", type=float, default=160.0)
     ap.add_argument("--serve-sweep", type=int, default=100,
                     help="requests at each of 0.5x and 1.0x the saturated rate")
+    ap.add_argument("--no-sampler", action="store_true")
+    ap.add_argument("--sampler-steps", type=int, default=4)
     ap.add_argument("--no-config5", action="store_true")
     ap.add_argument("--config5-steps", type=int, default=2)
     ap.add_argument("--config5-ws-gib", type=float, default=100.0,
@@ -380,6 +421,16 @@ def main():
         # <d|d> is common to both paths, so max_abs_dlnL is also the error of
         # the signal part lnL + <d|d>/2
         print(f"[bench] mixed: {mixed['value']:.1f} evals/s", file=sys.stderr, flush=True)
+
+    sampler = None
+    if not args.no_sampler:
+        sampler = {}
+        for wk in (w64, wmx):
+            sampler["fp64" if wk is w64 else "mixed"] = run_sampler(
+                E, W, wk, data, psd, args.sampler_steps, 1)
+        print(f"[bench] sampler: fp64 {sampler['fp64']['steps_per_s']:.2f} steps/s, mixed "
+              f"{sampler['mixed']['steps_per_s']:.2f} steps/s ({2 * w64.B} walkers)",
+              file=sys.stderr, flush=True)
 
     serving = None
     if not args.no_serving:
@@ -467,6 +518,7 @@ def main():
         "mixed": mixed,
         "serving": serving,
         "stress": config5,
+        "sampler": sampler,
         "stages": stages_out,
     }
     print(json.dumps(rec), flush=True)

@@ -53,7 +53,7 @@ extern "C" {
 #endif
 
 #define EMRI_NPAR 17
-#define EMRI_ABI_VERSION 1
+#define EMRI_ABI_VERSION 2
 
 typedef enum {
     EMRI_OK = 0,
@@ -232,6 +232,52 @@ emri_status emri_server_submit(emri_server* s, int32_t dataset_id, const double*
 emri_status emri_server_wait(emri_server* s, uint64_t ticket, double timeout_s,
                              double* latency_s);
 emri_status emri_server_stats_get(emri_server* s, emri_server_stats* out);
+
+/* ---- ensemble sampler step -------------------------------------------------
+ * The affine-invariant stretch move of Goodman & Weare (2010), which the
+ * paper's sampler applies to the walker matrix (Sec. 1 iii; Sec. 3
+ * "Posterior sampling"), in its parallel form: the ensemble of 2W walkers
+ * (rows of X, EMRI_NPAR doubles each) is split into halves [0, W) and
+ * [W, 2W), updated in turn, each against the other.  For walker k of half h
+ * a partner j of the other half is drawn, a stretch z with density
+ * proportional to 1/sqrt(z) on [1/a, a], and the proposal
+ * Y = X_j + z (X_k - X_j) on the free coordinates (the others are kept) is
+ * accepted with probability min(1, z^(D-1) p(Y) / p(X_k)).  The log-posterior
+ * is a flat prior on a box of the free coordinates (-inf outside) plus the
+ * log-likelihood against a resident data set (emri_dataset_init).
+ * The random numbers are inputs (u, in [0, 1)), so that a step is a
+ * deterministic function of them: u[h][k][0] picks the partner
+ * (j = floor(u0 W)), u[h][k][1] the stretch (z = ((a-1) u1 + 1)^2 / a),
+ * u[h][k][2] the acceptance (accept if ln u2 < (D-1) ln z + lnp(Y) - lnp(X_k);
+ * a proposal at -inf is rejected, a walker at -inf takes any finite one). */
+typedef struct {
+    int32_t n_free;              /* D, 1..EMRI_NPAR */
+    int32_t idx[EMRI_NPAR];      /* parameter indices of the free coordinates (first D) */
+    double lo[EMRI_NPAR];        /* prior box: lo[d] <= p[idx[d]] <= hi[d] */
+    double hi[EMRI_NPAR];
+} emri_prior;                    /* a HOST struct, read during the call */
+
+/* Workspace of emri_stretch_step for 2W walkers evaluated in one chunk
+ * (smaller workspaces down to the proposals plus emri_workspace_bytes(cfg, 1)
+ * work in chunks). */
+size_t emri_sampler_workspace_bytes(const emri_cfg* cfg, int64_t W);
+
+/* lnp[n] = log-prior (box) + log-likelihood of the n walkers X[n][17]
+ * against the resident data set ds.  ws as emri_loglike_dataset. */
+emri_status emri_ensemble_lnprob(const double* X, int64_t n, const emri_prior* prior,
+                                 const void* ds, const emri_cfg* cfg, double* lnp, void* ws,
+                                 size_t ws_bytes, hipStream_t stream);
+
+/* One step of the ensemble X[2W][17] (device, updated in place) with
+ * log-posteriors lnp[2W] (device, in/out, e.g. from emri_ensemble_lnprob);
+ * a > 1 is the stretch scale (2 is the usual choice); u[2][W][3] device
+ * uniforms; accepted[2W] (device, may be NULL) receives 1 where the walker
+ * moved.  Errors: W < 1, a <= 1, a prior with D outside 1..17, an index
+ * outside 0..16 or repeated, lo > hi: EMRI_EINVAL; workspace smaller than the
+ * proposals plus emri_workspace_bytes(cfg, 1): EMRI_EWORKSPACE. */
+emri_status emri_stretch_step(double* X, double* lnp, int64_t W, const emri_prior* prior,
+                              double a, const double* u, const void* ds, const emri_cfg* cfg,
+                              int32_t* accepted, void* ws, size_t ws_bytes, hipStream_t stream);
 
 #ifdef __cplusplus
 }

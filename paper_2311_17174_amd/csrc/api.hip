@@ -22,7 +22,7 @@ static thread_local std::string g_err;
 // ---- event tracing ---------------------------------------------------------
 static const char* const kStageNames[ST_COUNT] = {
     "walker_setup", "amplitude_tables", "synthesis", "twiddles", "fft_columns",
-    "fft_rows", "unpack", "dataset", "inner_product", "walker_sum", "noise_psd"};
+    "fft_rows", "unpack", "dataset", "inner_product", "walker_sum", "noise_psd", "sampler"};
 
 struct TraceRec { int stage; hipEvent_t a, b; };
 static std::mutex g_trace_mu;
@@ -429,6 +429,38 @@ emri_status emri_loglike_dataset(const double* params, int64_t B, const void* ds
     return loglike_chunks(cfg, params, B, ds, lnL, ws, ws_bytes, stream);
 }
 
+// ---- ensemble sampler step ---------------------------------------------------
+static emri_status check_prior(const emri_prior* pr, PriorBox* out)
+{
+    if (!pr) return fail(EMRI_EINVAL, "null prior");
+    if (pr->n_free < 1 || pr->n_free > EMRI_NPAR)
+        return fail(EMRI_EINVAL, "prior: n_free must be in 1..17");
+    bool seen[EMRI_NPAR] = {};
+    out->D = pr->n_free;
+    for (int d = 0; d < EMRI_NPAR; ++d) {
+        out->idx[d] = 0;
+        out->lo[d] = out->hi[d] = 0.0;
+    }
+    for (int d = 0; d < pr->n_free; ++d) {
+        const int i = pr->idx[d];
+        if (i < 0 || i >= EMRI_NPAR || seen[i])
+            return fail(EMRI_EINVAL, "prior: free indices must be distinct, in 0..16");
+        seen[i] = true;
+        if (!(pr->lo[d] <= pr->hi[d])) return fail(EMRI_EINVAL, "prior: lo > hi (or NaN)");
+        out->idx[d] = i;
+        out->lo[d] = pr->lo[d];
+        out->hi[d] = pr->hi[d];
+    }
+    return EMRI_OK;
+}
+
+// proposals of W walkers at the head of the workspace
+static size_t sampler_head_bytes(int64_t W)
+{
+    return align256((size_t)W * EMRI_NPAR * 8) + 3 * align256((size_t)W * 8);
+}
+
+
 emri_status emri_model_batch(const double* params, int64_t B, const emri_cfg* cfg, void* mf,
                              void* ws, size_t ws_bytes, hipStream_t stream)
 {
@@ -486,6 +518,63 @@ int emri_trace_read(double* ms, int64_t* launches, int n)
 const char* emri_trace_stage_name(int i)
 {
     return (i >= 0 && i < ST_COUNT) ? kStageNames[i] : "";
+}
+
+
+size_t emri_sampler_workspace_bytes(const emri_cfg* cfg, int64_t W)
+{
+    if (W < 1) W = 1;
+    const size_t w = emri_workspace_bytes(cfg, W);
+    return w ? sampler_head_bytes(W) + w : 0;
+}
+
+emri_status emri_ensemble_lnprob(const double* X, int64_t n, const emri_prior* prior,
+                                 const void* ds, const emri_cfg* cfg, double* lnp, void* ws,
+                                 size_t ws_bytes, hipStream_t stream)
+{
+    PriorBox pb;
+    emri_status st = check_prior(prior, &pb);
+    if (st != EMRI_OK) return st;
+    if (n < 0) return fail(EMRI_EINVAL, "n must be >= 0");
+    if (n == 0) return EMRI_OK;
+    if ((st = emri_loglike_dataset(X, n, ds, cfg, lnp, ws, ws_bytes, stream))) return st;
+    return check_launch(launch_add_box_prior(X, n, pb, lnp, stream), "prior");
+}
+
+emri_status emri_stretch_step(double* X, double* lnp, int64_t W, const emri_prior* prior,
+                              double a, const double* u, const void* ds, const emri_cfg* cfg,
+                              int32_t* accepted, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    PriorBox pb;
+    emri_status st = check_prior(prior, &pb);
+    if (st != EMRI_OK) return st;
+    if (W < 1) return fail(EMRI_EINVAL, "W must be >= 1");
+    if (!(a > 1.0) || !isfinite(a)) return fail(EMRI_EINVAL, "stretch scale a must be > 1");
+    if (!X || !lnp || !u || !ds || !ws) return fail(EMRI_EINVAL, "null pointer argument");
+    Plan p1;
+    const char* err;
+    if ((st = make_plan(cfg, 1, &p1, &err)) != EMRI_OK) return fail(st, err);
+    const size_t head = sampler_head_bytes(W);
+    if (ws_bytes < head + p1.total)
+        return fail(EMRI_EWORKSPACE, "workspace smaller than the proposals plus emri_workspace_bytes(cfg, 1)");
+    char* b = (char*)ws;
+    double* Y = (double*)b;
+    double* lnz = (double*)(b + align256((size_t)W * EMRI_NPAR * 8));
+    double* lpr = (double*)((char*)lnz + align256((size_t)W * 8));
+    double* lnL = (double*)((char*)lpr + align256((size_t)W * 8));
+    for (int h = 0; h < 2; ++h) {
+        const double* uh = u + (int64_t)h * W * 3;
+        if ((st = check_launch(launch_stretch_propose(X, W, h, pb, a, uh, Y, lnz, lpr, stream),
+                               "stretch proposals")))
+            return st;
+        if ((st = loglike_chunks(cfg, Y, W, ds, lnL, b + head, ws_bytes - head, stream)))
+            return st;
+        if ((st = check_launch(launch_stretch_accept(X, lnp, W, h, Y, lpr, lnL, lnz, uh, accepted,
+                                                     stream),
+                               "stretch acceptance")))
+            return st;
+    }
+    return EMRI_OK;
 }
 
 }  // extern "C"

@@ -122,6 +122,20 @@ hipError_t launch_tables(const Plan& p, int64_t B, void* ws, int64_t k0, int64_t
 hipError_t launch_synth(const Plan& p, int64_t B, void* ws, void* out, int64_t k0, int64_t k1,
                         int seg, hipStream_t s);
 hipError_t launch_twiddles(const Plan& p, void* ws, hipStream_t s);
+// ensemble sampler step (sampler.hip); the prior box by value
+struct PriorBox {
+    int32_t D;
+    int32_t idx[EMRI_NPAR];
+    double lo[EMRI_NPAR], hi[EMRI_NPAR];
+};
+hipError_t launch_stretch_propose(const double* X, int64_t W, int h, const PriorBox& pr, double a,
+                                  const double* u, double* Y, double* lnz, double* lpr,
+                                  hipStream_t s);
+hipError_t launch_stretch_accept(double* X, double* lnp, int64_t W, int h, const double* Y,
+                                 const double* lpr, const double* lnL, const double* lnz,
+                                 const double* u, int32_t* acc, hipStream_t s);
+hipError_t launch_add_box_prior(const double* X, int64_t n, const PriorBox& pr, double* lnp,
+                                hipStream_t s);
 hipError_t launch_fft(const Plan& p, int64_t B, void* ws, hipStream_t s);  // z -> z (transposed)
 // FFT reading `in` ([B][N] complex, NULL: the workspace signal), result in z
 hipError_t launch_fft_from(const Plan& p, int64_t B, const void* in, void* ws, hipStream_t s);
@@ -141,7 +155,7 @@ hipError_t launch_noise_psd(int64_t N, double dt, double* psd, hipStream_t s);
 // ---- per-stage event tracing (see emri_trace_enable) ---------------------
 enum Stage {
     ST_SETUP = 0, ST_TABLES, ST_SYNTH, ST_TWIDDLE, ST_FFT_COLS, ST_FFT_ROWS, ST_UNPACK,
-    ST_DATASET, ST_LIKE, ST_WALKER_SUM, ST_PSD, ST_COUNT
+    ST_DATASET, ST_LIKE, ST_WALKER_SUM, ST_PSD, ST_SAMPLER, ST_COUNT
 };
 void trace_mark(int stage, hipStream_t s, bool begin);
 

@@ -25,7 +25,8 @@ EXPORTED = ("emri_abi_version", "emri_last_error", "emri_workspace_bytes",
             "emri_waveform_batch", "emri_fft_batch", "emri_loglike_batch",
             "emri_dataset_bytes", "emri_dataset_init", "emri_loglike_dataset",
             "emri_model_batch", "emri_noise_psd", "emri_trace_enable", "emri_trace_read",
-            "emri_trace_stage_name")
+            "emri_trace_stage_name", "emri_sampler_workspace_bytes", "emri_ensemble_lnprob",
+            "emri_stretch_step")
 
 
 class EmriError(RuntimeError):
@@ -38,6 +39,23 @@ class _Cfg(ctypes.Structure):
     _fields_ = [("T_obs", ctypes.c_double), ("dt", ctypes.c_double), ("N", ctypes.c_int64),
                 ("n_harm", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("coarse_log2", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _Prior(ctypes.Structure):
+    _fields_ = [("n_free", ctypes.c_int32), ("idx", ctypes.c_int32 * NPAR),
+                ("lo", ctypes.c_double * NPAR), ("hi", ctypes.c_double * NPAR)]
+
+
+def make_prior(free_idx, lo, hi) -> _Prior:
+    """Box prior on the parameters free_idx (lo <= p[i] <= hi), as emri_prior."""
+    free_idx, lo, hi = list(free_idx), list(lo), list(hi)
+    if not (len(free_idx) == len(lo) == len(hi)) or len(free_idx) > NPAR:
+        raise ValueError("free_idx, lo and hi must have the same length, at most 17")
+    pr = _Prior()
+    pr.n_free = len(free_idx)
+    for d, (i, a, b) in enumerate(zip(free_idx, lo, hi)):
+        pr.idx[d], pr.lo[d], pr.hi[d] = int(i), float(a), float(b)
+    return pr
 
 
 @dataclass(frozen=True)
@@ -86,6 +104,11 @@ def _load():
         "emri_trace_read": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                              ctypes.c_int], ctypes.c_int),
         "emri_trace_stage_name": ([ctypes.c_int], ctypes.c_char_p),
+        "emri_sampler_workspace_bytes": ([cp, i64], sz),
+        "emri_ensemble_lnprob": ([vp, i64, ctypes.POINTER(_Prior), vp, cp, vp, vp, sz, vp],
+                                 ctypes.c_int),
+        "emri_stretch_step": ([vp, vp, i64, ctypes.POINTER(_Prior), d, vp, vp, cp, vp, vp, sz,
+                               vp], ctypes.c_int),
     }
     for name, (a, r) in sig.items():
         f = getattr(L, name)
@@ -223,6 +246,56 @@ def loglike_dataset(params: torch.Tensor, ds: torch.Tensor, cfg: Config,
     _check(lib.emri_loglike_dataset(pp, B, ds.data_ptr(), ctypes.byref(c), op, ws.data_ptr(),
                                     ws.numel(), _stream(stream)), "emri_loglike_dataset")
     return out
+
+
+def sampler_workspace_bytes(cfg: Config, W: int) -> int:
+    c = cfg.c()
+    n = lib.emri_sampler_workspace_bytes(ctypes.byref(c), int(W))
+    if n == 0:
+        raise EmriError(-1, "emri_sampler_workspace_bytes", "invalid configuration")
+    return n
+
+
+def ensemble_lnprob(X: torch.Tensor, prior: _Prior, ds: torch.Tensor, cfg: Config,
+                    out: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+                    stream=None) -> torch.Tensor:
+    """Box log-prior plus log-likelihood of the walkers X[n][17]."""
+    n = X.shape[0]
+    xp = _dev(X, torch.float64, (n, NPAR), "X")
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=X.device)
+    op = _dev(out, torch.float64, (n,), "out")
+    if ws is None:
+        ws = alloc_workspace(cfg, max(n, 1), X.device)
+    c = cfg.c()
+    _check(lib.emri_ensemble_lnprob(xp, n, ctypes.byref(prior), ds.data_ptr(), ctypes.byref(c),
+                                    op, ws.data_ptr(), ws.numel(), _stream(stream)),
+           "emri_ensemble_lnprob")
+    return out
+
+
+def stretch_step(X: torch.Tensor, lnp: torch.Tensor, prior: _Prior, a: float, u: torch.Tensor,
+                 ds: torch.Tensor, cfg: Config, accepted: torch.Tensor | None = None,
+                 ws: torch.Tensor | None = None, stream=None):
+    """One stretch-move step of the ensemble X[2W][17], lnp[2W] (both in place);
+    u[2][W][3] uniforms.  Returns accepted[2W] (int32, 1 where the walker moved)."""
+    n = X.shape[0]
+    if n % 2:
+        raise ValueError("the ensemble must have an even number of walkers")
+    W = n // 2
+    xp = _dev(X, torch.float64, (n, NPAR), "X")
+    lp = _dev(lnp, torch.float64, (n,), "lnp")
+    up = _dev(u, torch.float64, (2, W, 3), "u")
+    if accepted is None:
+        accepted = torch.empty(n, dtype=torch.int32, device=X.device)
+    ap = _dev(accepted, torch.int32, (n,), "accepted")
+    if ws is None:
+        ws = torch.empty(sampler_workspace_bytes(cfg, W), dtype=torch.uint8, device=X.device)
+    c = cfg.c()
+    _check(lib.emri_stretch_step(xp, lp, W, ctypes.byref(prior), float(a), up, ds.data_ptr(),
+                                 ctypes.byref(c), ap, ws.data_ptr(), ws.numel(), _stream(stream)),
+           "emri_stretch_step")
+    return accepted
 
 
 def model_batch(params: torch.Tensor, cfg: Config, out: torch.Tensor | None = None,

@@ -166,3 +166,38 @@ def serving_requests(n: int, n_chains: int = 8, seed: int = 4, w_min: int = 16,
     tidx = r.integers(0, len(SERVING_T_OBS_YR), n)
     Ws = r.integers(w_min, w_max + 1, n)
     return [(float(gaps[i]), int(chains[i]), int(tidx[i]), int(Ws[i]), i) for i in range(n)]
+
+
+# ---------------------------------------------------------------------------
+# ensemble sampler inputs: prior box, initial ensemble, uniforms
+# ---------------------------------------------------------------------------
+# free parameters of the sampler workloads: the masses, spin, eccentricity,
+# frequency, distance and the two propagation parameters Xi0 and n
+SAMPLER_FREE = (0, 1, 2, 3, 4, 13, 14, 15)
+
+
+def sampler_prior(w: Workload, free_idx=SAMPLER_FREE, width: float = 50.0):
+    """Box of the free parameters: inj[i] (1 -/+ width SIGMA_REL[i]), or
+    -/+ width 1e-3 around an injected 0.  Returns (lo, hi) in free order."""
+    lo, hi = [], []
+    for i in free_idx:
+        v, s = w.inj[i], SIGMA_REL[i] if SIGMA_REL[i] > 0 else 1e-3
+        half = width * s * (abs(v) if v != 0 else 1.0)
+        lo.append(v - half)
+        hi.append(v + half)
+    return np.array(lo), np.array(hi)
+
+
+def sampler_ensemble(w: Workload, W: int, free_idx=SAMPLER_FREE, seed: int = 7) -> np.ndarray:
+    """Initial ensemble [2W][17]: the injection, with the free parameters of
+    each walker drawn as in walkers(w, 2W, seed)."""
+    P = walkers(w, 2 * W, seed)
+    X = np.tile(w.inj, (2 * W, 1))
+    X[:, list(free_idx)] = P[:, list(free_idx)]
+    return np.ascontiguousarray(X)
+
+
+def sampler_uniforms(W: int, steps: int, seed: int = 11) -> np.ndarray:
+    """Uniforms in [0, 1) [steps][2][W][3] from PCG64(seed): per walker the
+    partner, stretch and acceptance draws of each step's two halves."""
+    return np.random.Generator(np.random.PCG64(seed)).random((steps, 2, W, 3))

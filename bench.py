@@ -48,8 +48,11 @@ def stage_work(stage: str, B: int, w, esz: int, valid_samples: int):
     N = w.N
     if stage == "synthesis":
         return "flop", valid_samples * synth_flops_per_sample(w.n_harm)
-    if stage in ("fft_columns", "fft_rows"):
-        return "byte", 2 * B * N * esz                       # read + write the signal
+    if stage == "fft_columns":
+        # read the valid samples (the zero tail is not read), write the whole signal
+        return "byte", (valid_samples + B * N) * esz
+    if stage == "fft_rows":
+        return "byte", 2 * B * N * esz
     if stage == "inner_product":
         half = N // 2
         dsz = 2 * half * esz + half * (8 if esz == 16 else 4)  # data + weights, once

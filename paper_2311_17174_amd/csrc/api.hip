@@ -240,12 +240,15 @@ static int orbit_segments(const Plan& p)
     return S < 1 ? 1 : (int)S;
 }
 
-// walkers [0, B) of params, workspace planned for at least B walkers
+// walkers [0, B) of params, workspace planned for at least B walkers.  With
+// zero_tail false the samples from nv_w = min(K_w L, N_valid) on are left
+// unwritten (the FFT's pass A takes them as zero)
 static emri_status run_waveforms(const Plan& p, const double* params, int64_t B, void* ws,
-                                 void* out, hipStream_t s)
+                                 void* out, bool zero_tail, hipStream_t s)
 {
     const int S = orbit_segments(p);
-    const int64_t KT = p.N / p.L;            // synthesis intervals, zero tail included
+    // synthesis intervals: with the zero tail up to N / L, else those covering N_valid
+    const int64_t KT = zero_tail ? p.N / p.L : p.K;
     // segment bounds: the first segment (integrated before anything else can
     // start) is a quarter of the others
     auto kb = [&](int i) -> int64_t {
@@ -259,7 +262,7 @@ static emri_status run_waveforms(const Plan& p, const double* params, int64_t B,
             return st;
         if ((st = check_launch(launch_tables(p, B, ws, 0, p.K, 0, s), "amplitude tables")))
             return st;
-        return check_launch(launch_synth(p, B, ws, out, 0, KT, 0, s), "synthesis");
+        return check_launch(launch_synth(p, B, ws, out, 0, KT, 0, zero_tail, s), "synthesis");
     }
     Pipe* pp = nullptr;
     if ((st = get_pipe(s, &pp))) return st;
@@ -279,7 +282,7 @@ static emri_status run_waveforms(const Plan& p, const double* params, int64_t B,
             break;
         forked = true;
         if ((st = check_launch(launch_synth(p, B, ws, out, kb(i), i == S - 1 ? KT : kb(i + 1), i,
-                                            pp->aux),
+                                            zero_tail, pp->aux),
                                "synthesis")))
             break;
     }
@@ -342,7 +345,7 @@ emri_status emri_waveform_batch(const double* params, int64_t B, const emri_cfg*
     if (B == 0) return EMRI_OK;
     if (!params || !ht || !ws) return fail(EMRI_EINVAL, "null pointer argument");
     if (ws_bytes < p.total) return fail(EMRI_EWORKSPACE, "workspace smaller than emri_workspace_bytes(cfg, B)");
-    return run_waveforms(p, params, B, ws, ht, stream);
+    return run_waveforms(p, params, B, ws, ht, true, stream);
 }
 
 emri_status emri_fft_batch(const void* ht, int64_t B, const emri_cfg* cfg, void* hf, void* ws,
@@ -376,7 +379,7 @@ static emri_status loglike_chunks(const emri_cfg* cfg, const double* params, int
     for (int64_t w0 = 0; w0 < B; w0 += chunk) {
         const int64_t nb = (B - w0 < chunk) ? (B - w0) : chunk;
         if ((st = run_waveforms(p, params + w0 * EMRI_NPAR, nb, ws,
-                                (char*)ws + p.off_z, stream)))
+                                (char*)ws + p.off_z, false, stream)))
             return st;
         if ((st = check_launch(launch_fft_cols(p, nb, ws, stream), "fft columns"))) return st;
         if ((st = check_launch(launch_likelihood(p, nb, ds, ws, lnL + w0, stream), "likelihood")))
@@ -471,7 +474,7 @@ emri_status emri_model_batch(const double* params, int64_t B, const emri_cfg* cf
     if (B == 0) return EMRI_OK;
     if (!params || !mf || !ws) return fail(EMRI_EINVAL, "null pointer argument");
     if (ws_bytes < p.total) return fail(EMRI_EWORKSPACE, "workspace smaller than emri_workspace_bytes(cfg, B)");
-    if ((st = run_waveforms(p, params, B, ws, (char*)ws + p.off_z, stream))) return st;
+    if ((st = run_waveforms(p, params, B, ws, (char*)ws + p.off_z, false, stream))) return st;
     if ((st = check_launch(launch_twiddles(p, ws, stream), "twiddles"))) return st;
     if ((st = check_launch(launch_fft(p, B, ws, stream), "fft"))) return st;
     return check_launch(launch_model_unpack(p, B, ws, mf, stream), "unpack");

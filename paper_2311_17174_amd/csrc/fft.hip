@@ -118,13 +118,18 @@ __device__ inline int64_t xcd_tile(int64_t bid, int64_t nb)
 // twiddle (two table factors, one cache line per wave per load) and
 // stores.  in and out may alias (the tile's read and write sets coincide,
 // and every read precedes the first barrier).
+// With walker constants wc, the input of walker w is known to vanish from
+// sample nv_w = min(K_w 2^cl, Nv) on (0 for an invalid walker): those samples
+// are taken as zero and not read, so the synthesis need not write them.
 template <typename R, int MAXT>
 __global__ void __launch_bounds__(MAXT) k_fft_cols16(const typename C2<R>::T* in,
                                                      typename C2<R>::T* out, int64_t N,
                                                      int64_t R1, int L, int lgL, int TA,
                                                      const typename C2<R>::T* __restrict__ twL,
                                                      const typename C2<R>::T* __restrict__ tTb,
-                                                     const typename C2<R>::T* __restrict__ tTs)
+                                                     const typename C2<R>::T* __restrict__ tTs,
+                                                     const double* __restrict__ wc, int64_t Nv,
+                                                     int cl)
 {
     using T2 = typename C2<R>::T;
     extern __shared__ unsigned char smem_raw[];
@@ -140,10 +145,17 @@ __global__ void __launch_bounds__(MAXT) k_fft_cols16(const typename C2<R>::T* in
     const int col = threadIdx.x & (TA - 1), t = threadIdx.x >> tsh;
     const int L16 = L / 16;
     const int64_t cg = c0 + col;
+    int64_t nv = N;
+    if (wc) {
+        const double* c = wc + w * WC;
+        const int64_t kv = c[WC_VALID] == 0.0 ? 0 : (int64_t)c[WC_KW];
+        nv = (kv << cl) < Nv ? (kv << cl) : Nv;
+    }
     R xr[16], xi[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        const T2 v = src[cg + R1 * (int64_t)(t + i * L16)];
+        const int64_t n = cg + R1 * (int64_t)(t + i * L16);
+        const T2 v = n < nv ? src[n] : T2{R(0), R(0)};
         xr[i] = v.x;
         xi[i] = v.y;
     }
@@ -190,7 +202,7 @@ __global__ void __launch_bounds__(MAXT) k_fft_rows(typename C2<R>::T* z, int64_t
 
 template <typename R>
 static hipError_t fft_typed(const Plan& p, int64_t B, const void* in, void* ws, bool rows,
-                           hipStream_t s)
+                           bool known_tail, hipStream_t s)
 {
     using T2 = typename C2<R>::T;
     char* base = (char*)ws;
@@ -213,14 +225,15 @@ static hipError_t fft_typed(const Plan& p, int64_t B, const void* in, void* ws, 
     if (ae == hipSuccess && rows) ae = allow_lds((const void*)k_fft_rows<R, 512>, ldsB);
     if (ae != hipSuccess) return ae;
     const T2* src = (const T2*)(in ? in : z);
+    const double* wc = known_tail ? (const double*)(base + p.off_wc) : nullptr;
     const dim3 gA((unsigned)(p.R1 / p.TA), (unsigned)B), bA((unsigned)ntA);
     trace_mark(ST_FFT_COLS, s, true);
     if (big)
         hipLaunchKernelGGL((k_fft_cols16<R, 1024>), gA, bA, ldsA, s, src, z, p.N, p.R1, LA, p.m2,
-                           p.TA, tA, tTb, tTs);
+                           p.TA, tA, tTb, tTs, wc, p.Nv, p.cl);
     else
         hipLaunchKernelGGL((k_fft_cols16<R, 512>), gA, bA, ldsA, s, src, z, p.N, p.R1, LA, p.m2,
-                           p.TA, tA, tTb, tTs);
+                           p.TA, tA, tTb, tTs, wc, p.Nv, p.cl);
     trace_mark(ST_FFT_COLS, s, false);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !rows) return e;
@@ -233,19 +246,20 @@ static hipError_t fft_typed(const Plan& p, int64_t B, const void* in, void* ws, 
 
 hipError_t launch_fft_from(const Plan& p, int64_t B, const void* in, void* ws, hipStream_t s)
 {
-    if (p.prec == EMRI_FP64) return fft_typed<double>(p, B, in, ws, true, s);
-    return fft_typed<float>(p, B, in, ws, true, s);
+    if (p.prec == EMRI_FP64) return fft_typed<double>(p, B, in, ws, true, false, s);
+    return fft_typed<float>(p, B, in, ws, true, false, s);
 }
 
 hipError_t launch_fft_cols(const Plan& p, int64_t B, void* ws, hipStream_t s)
 {
-    if (p.prec == EMRI_FP64) return fft_typed<double>(p, B, nullptr, ws, false, s);
-    return fft_typed<float>(p, B, nullptr, ws, false, s);
+    if (p.prec == EMRI_FP64) return fft_typed<double>(p, B, nullptr, ws, false, true, s);
+    return fft_typed<float>(p, B, nullptr, ws, false, true, s);
 }
 
 hipError_t launch_fft(const Plan& p, int64_t B, void* ws, hipStream_t s)
 {
-    return launch_fft_from(p, B, nullptr, ws, s);
+    if (p.prec == EMRI_FP64) return fft_typed<double>(p, B, nullptr, ws, true, true, s);
+    return fft_typed<float>(p, B, nullptr, ws, true, true, s);
 }
 
 // unpack: transposed packed spectrum -> hf[B][2][N/2+1], scaled by dt and,

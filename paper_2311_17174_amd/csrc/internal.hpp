@@ -118,9 +118,12 @@ hipError_t launch_walker_resume(const Plan& p, int64_t B, void* ws, int64_t k0, 
 // node amplitudes and interval tables of segment seg (intervals [k0, k1))
 hipError_t launch_tables(const Plan& p, int64_t B, void* ws, int64_t k0, int64_t k1, int seg,
                          hipStream_t s);
-// samples of the intervals [k0, k1) (k1 may reach N / L: zero tail)
+// samples of the intervals [k0, k1) (k1 may reach N / L: zero tail); with
+// zfill false, intervals past a walker's plunge or N_valid are not written
+// (for consumers that take the samples from nv_w = min(K_w L, N_valid) on
+// as zero: launch_fft_cols, launch_fft)
 hipError_t launch_synth(const Plan& p, int64_t B, void* ws, void* out, int64_t k0, int64_t k1,
-                        int seg, hipStream_t s);
+                        int seg, bool zfill, hipStream_t s);
 hipError_t launch_twiddles(const Plan& p, void* ws, hipStream_t s);
 // ensemble sampler step (sampler.hip); the prior box by value
 struct PriorBox {
@@ -136,10 +139,13 @@ hipError_t launch_stretch_accept(double* X, double* lnp, int64_t W, int h, const
                                  const double* u, int32_t* acc, hipStream_t s);
 hipError_t launch_add_box_prior(const double* X, int64_t n, const PriorBox& pr, double* lnp,
                                 hipStream_t s);
-hipError_t launch_fft(const Plan& p, int64_t B, void* ws, hipStream_t s);  // z -> z (transposed)
-// FFT reading `in` ([B][N] complex, NULL: the workspace signal), result in z
+// z -> z (transposed); the signal in z is read below nv_w only (walker
+// constants of the same batch in the workspace)
+hipError_t launch_fft(const Plan& p, int64_t B, void* ws, hipStream_t s);
+// FFT reading `in` ([B][N] complex, all of it), result in z
 hipError_t launch_fft_from(const Plan& p, int64_t B, const void* in, void* ws, hipStream_t s);
-// pass A only (column FFTs with the four-step twiddle), in place on z
+// pass A only (column FFTs with the four-step twiddle), in place on z, read
+// below nv_w only as launch_fft
 hipError_t launch_fft_cols(const Plan& p, int64_t B, void* ws, hipStream_t s);
 hipError_t launch_unpack(const Plan& p, int64_t B, const void* ws, void* hf, hipStream_t s);
 hipError_t launch_dataset(const Plan& p, const double* data, const double* psd, void* ds,

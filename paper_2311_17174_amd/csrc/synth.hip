@@ -90,7 +90,7 @@ __device__ __forceinline__ void angle_run(const double (&a)[SPT], bool smooth, R
 template <typename R, typename HT, int SPT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPT <= 4 ? 4 : 1)))
 k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
-                                               int64_t k0, int seg,
+                                               int64_t k0, int seg, int zfill,
                                                double dt, const double* __restrict__ wc,
                                                const double* __restrict__ co,
                                                const HT* __restrict__ ch,
@@ -107,8 +107,10 @@ k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
     const double* c = wc + w * WC;
     const int64_t Kw = (int64_t)c[WC_KSEG + seg];
     if (c[WC_VALID] == 0.0 || k >= Kw || j0 >= Nv) {
+        if (zfill) {
 #pragma unroll
-        for (int s = 0; s < SPT; ++s) zw[jl + s] = R2{R(0), R(0)};
+            for (int s = 0; s < SPT; ++s) zw[jl + s] = R2{R(0), R(0)};
+        }
         return;
     }
 
@@ -294,7 +296,7 @@ k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
 
 template <typename R, typename HT>
 static hipError_t synth_dispatch(const Plan& p, int64_t B, const char* base, void* out,
-                                 int64_t k0, int64_t k1, int seg, hipStream_t s)
+                                 int64_t k0, int64_t k1, int seg, int zfill, hipStream_t s)
 {
     dim3 grid((unsigned)(k1 - k0), (unsigned)B);
     using R2 = typename V2<R>::T;
@@ -304,7 +306,7 @@ static hipError_t synth_dispatch(const Plan& p, int64_t B, const char* base, voi
     R2* o = (R2*)out;
 #define EMRI_SYNTH(SPT)                                                                        \
     hipLaunchKernelGGL((k_synth<R, HT, SPT>), grid, dim3(256), 0, s, p.K, p.Nv, p.N, p.nh, k0, \
-                       seg, p.dt, wc, co, ch, o)
+                       seg, zfill, p.dt, wc, co, ch, o)
     switch (p.cl) {
     case 8: EMRI_SYNTH(1); break;
     case 9: EMRI_SYNTH(2); break;
@@ -318,7 +320,7 @@ static hipError_t synth_dispatch(const Plan& p, int64_t B, const char* base, voi
 }
 
 hipError_t launch_synth(const Plan& p, int64_t B, void* ws, void* out, int64_t k0, int64_t k1,
-                        int seg, hipStream_t s)
+                        int seg, bool zfill, hipStream_t s)
 {
     if (seg < 0 || seg >= kMaxSeg || k0 < 0 || k1 < k0 || k1 > p.N / p.L)
         return hipErrorInvalidValue;
@@ -326,8 +328,9 @@ hipError_t launch_synth(const Plan& p, int64_t B, void* ws, void* out, int64_t k
     const char* base = (const char*)ws;
     trace_mark(ST_SYNTH, s, true);
     const hipError_t e =
-        (p.prec == EMRI_FP64) ? synth_dispatch<double, double>(p, B, base, out, k0, k1, seg, s)
-                              : synth_dispatch<float, float>(p, B, base, out, k0, k1, seg, s);
+        (p.prec == EMRI_FP64)
+            ? synth_dispatch<double, double>(p, B, base, out, k0, k1, seg, zfill ? 1 : 0, s)
+            : synth_dispatch<float, float>(p, B, base, out, k0, k1, seg, zfill ? 1 : 0, s);
     trace_mark(ST_SYNTH, s, false);
     return e;
 }

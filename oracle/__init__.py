@@ -95,6 +95,8 @@ def lib():
             "oracle_waveform_diag": ([dp, cp, dp, dp], ctypes.c_int),
             "oracle_rfft": ([dp, i64, i64, ctypes.c_double, dp], ctypes.c_int),
             "oracle_loglike": ([dp, i64, dp, dp, cp, dp], ctypes.c_int),
+            "oracle_loglike_fmg": ([dp, i64, dp, ctypes.c_int32, ctypes.c_double, dp, dp, cp,
+                                    dp], ctypes.c_int),
             "oracle_psd_bc04": ([dp, i64, dp], ctypes.c_int),
             "oracle_make_data": ([dp, dp, dp, dp, i64, ctypes.c_double, dp], ctypes.c_int),
             "oracle_besselj": ([ctypes.c_int, ctypes.c_double], ctypes.c_double),
@@ -217,6 +219,23 @@ def loglike(params, data, psd, cfg: OracleConfig) -> np.ndarray:
     c = cfg.c()
     _check(lib().oracle_loglike(_p(p), p.shape[0], _p(d), _p(s), ctypes.byref(c), _p(out)),
            "loglike")
+    return out
+
+
+def loglike_fmg(params, coef, f_star, data, psd, cfg: OracleConfig) -> np.ndarray:
+    """lnL with frequency-dependent alpha_M, alpha_T: coef [B][2][P] (alpha_M
+    series coefficients, then alpha_T's), pivot frequency f_star [Hz]."""
+    p = _f64(params).reshape(-1, NPAR)
+    B = p.shape[0]
+    cf = np.asarray(coef, dtype=np.float64)
+    P = cf.size // (2 * B)
+    cf = np.ascontiguousarray(cf.reshape(B, 2, P))
+    d = _cplx_pairs(data)
+    s = _f64(psd)
+    out = np.zeros(B)
+    c = cfg.c()
+    _check(lib().oracle_loglike_fmg(_p(p), B, _p(cf), P, float(f_star), _p(d), _p(s),
+                                    ctypes.byref(c), _p(out)), "loglike_fmg")
     return out
 
 

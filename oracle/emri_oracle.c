@@ -699,6 +699,95 @@ static double walker_loglike(const double *p, const double *data, const double *
     return -0.5 * (acc.s + acc.c);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Frequency-dependent propagation (the variant of Sec. 2 "Waveform           */
+/* propagation" where alpha_M and alpha_T depend on f, given there as power   */
+/* series in f / f*).  Reading: the series coefficients are constant in z,    */
+/*   alpha_M(f) = sum_n m_n (f/f*)^n,                                         */
+/*   alpha_T(f) = alpha_T(row) + sum_n t_n (f/f*)^n.                          */
+/* The friction integral of Eq. (5), (1/2) int_0^z alpha_M / (1 + z') dz',    */
+/* is then alpha_M(f) ln(1 + z) / 2, so the amplitude carries the extra       */
+/* factor (1 + z)^(-alpha_M(f)/2) on top of Eq. (6); the delay is the         */
+/* constant-speed reading of Eqs. (4)-(5) at each frequency,                  */
+/* Delta T(f) = (1/c_T(f) - 1) chi / c with c_T(f)^2 = 1 + alpha_T(f).        */
+/* A bin with 1 + alpha_T(f) <= 0 makes the walker invalid (lnL = -inf).      */
+/* ------------------------------------------------------------------------ */
+static double walker_loglike_fmg(const double *p, const double *coef, int P, double f_star,
+                                 const double *data, const double *psd, const oracle_cfg *c,
+                                 double *scratch_x, double *scratch_X)
+{
+    double s[8];
+    walker_scalars(p, s);
+    if (s[0] == 0.0) return -INFINITY;
+    int64_t N = c->N, K = n_intervals_of(c), H = N / 2 + 1;
+    double *orb = (double *)malloc((size_t)(K + 1) * 10 * sizeof(double));
+    int64_t Kw = walker_orbit(p, c, orb);
+    walker_waveform(p, c, orb, Kw, scratch_x, NULL);
+    free(orb);
+    for (int ch = 0; ch < 2; ++ch) {
+        double *re = scratch_X, *im = scratch_X + N;
+        memcpy(re, scratch_x + ch * N, (size_t)N * sizeof(double));
+        memset(im, 0, (size_t)N * sizeof(double));
+        fft_inplace(re, im, N);
+        double *spec = scratch_X + 2 * N + ch * 2 * H;
+        for (int64_t k = 0; k < H; ++k) { spec[2 * k] = c->dt * re[k]; spec[2 * k + 1] = c->dt * im[k]; }
+    }
+    const double z = s[1], chi = s[3], g = s[5];
+    const double *mM = coef, *mT = coef + P;
+    double df = 1.0 / ((double)N * c->dt);
+    /* the same summation order as the constant-propagation likelihood */
+    neumaier acc = {0.0, 0.0};
+    for (int ch = 0; ch < 2; ++ch) {
+        const double *spec = scratch_X + 2 * N + ch * 2 * H;
+        const double *d = data + ch * 2 * H;
+        for (int64_t k = 1; k < N / 2; ++k) {
+            double f = (double)k * df, x = f / f_star;
+            /* the two power series, by Horner's rule */
+            double aM = 0.0, aT = 0.0;
+            for (int n = P - 1; n >= 0; --n) {
+                aM = aM * x + mM[n];
+                aT = aT * x + mT[n];
+            }
+            aT += p[I_AT];
+            if (!(1.0 + aT > 0.0)) return -INFINITY;
+            double amp = g * exp(-0.5 * aM * log1p(z));
+            double ct = sqrt(1.0 + aT);
+            double dT = -aT / (ct * (1.0 + ct)) * chi;   /* (1/c_T - 1) chi as for constant alpha_T */
+            double cyc = f * dT;
+            cyc -= floor(cyc);
+            double cr = cos(2.0 * O_PI * cyc), ci = -sin(2.0 * O_PI * cyc);
+            double hr = spec[2 * k], hi = spec[2 * k + 1];
+            double mr = amp * (cr * hr - ci * hi);
+            double mi = amp * (cr * hi + ci * hr);
+            double rr = d[2 * k] - mr, ri = d[2 * k + 1] - mi;
+            nsum_add(&acc, (4.0 * df / psd[k]) * (rr * rr + ri * ri));
+        }
+    }
+    return -0.5 * (acc.s + acc.c);
+}
+
+/* lnL with the frequency-dependent propagation: coef [B][2][P] holds per
+ * walker m_0..m_{P-1} then t_0..t_{P-1}; 0 <= P <= 8, f_star > 0. */
+int oracle_loglike_fmg(const double *params, int64_t B, const double *coef, int32_t P,
+                       double f_star, const double *data, const double *psd, const oracle_cfg *c,
+                       double *lnL)
+{
+    if (!cfg_ok(c) || P < 0 || P > 8 || !(f_star > 0.0)) return -1;
+    int64_t N = c->N, H = N / 2 + 1;
+#pragma omp parallel if (B >= oracle_num_threads())
+    {
+        double *sx = (double *)malloc((size_t)(2 * N) * sizeof(double));
+        double *sX = (double *)malloc((size_t)(2 * N + 4 * H) * sizeof(double));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t w = 0; w < B; ++w)
+            lnL[w] = walker_loglike_fmg(params + w * NPAR, coef + w * 2 * P, P, f_star, data, psd,
+                                        c, sx, sX);
+        free(sx);
+        free(sX);
+    }
+    return 0;
+}
+
 int oracle_loglike(const double *params, int64_t B, const double *data /* [2][N/2+1][2] */,
                    const double *psd /* [N/2+1] */, const oracle_cfg *c, double *lnL)
 {

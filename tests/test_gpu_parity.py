@@ -96,6 +96,29 @@ def test_waveform_plunge_inside_window(E):
         assert np.any(got[b, :, (kw[b] << w.coarse_log2) - 1] != 0.0)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_loglike_plunge_inside_window(E, prec):
+    """The likelihood path leaves the samples after each walker's plunge
+    unwritten and unread (taken as zero): against the oracle on noise-less
+    data, where lnL is the signal part alone, for walkers that plunge at
+    different nodes and one that is invalid."""
+    w = plunge_workload(8).with_(precision=prec)
+    P = W.walkers(w, B=4)
+    P[1, 4] *= 1.03                                    # plunges at node 426
+    P[2, 4] *= 0.97                                    # at node 508 (walker 0: 465)
+    P[3, 1] = 2e5                                      # mu > M: invalid, lnL = -inf
+    d, S = oracle_dataset(w, noise=False)
+    ref = O.loglike(P, d, S, ocfg(w))
+    cfg = E.Config.from_workload(w)
+    dd, ss = to_device_data(d, S)
+    got = E.loglike_batch(gpu_params(P), dd, ss, cfg).cpu().numpy()
+    hh = -2.0 * O.loglike(w.inj[None], np.zeros_like(d), S, ocfg(w))[0]
+    say("plunge lnL ref", ref, "got", got, "<h|h>", hh)
+    assert got[3] == -np.inf and ref[3] == -np.inf
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    assert np.max(np.abs(got[:3] - ref[:3])) <= tol * hh
+
+
 def test_amplitude_table_error_converges():
     """The HIP path interpolates the Peters-Mathews amplitudes (Bessel
     brackets times A) with cubic Hermite polynomials per coarse interval; the

@@ -221,6 +221,41 @@ def run_sampler(E, W, w, data, psd, steps: int, warmup: int):
             "finite_lnp_walkers": int(torch.isfinite(lnp).sum().item())}
 
 
+def run_fmg(E, W, w, data, psd, steps: int, warmup: int):
+    """Likelihood with frequency-dependent alpha_M, alpha_T (three series
+    terms per walker, pivot 10 mHz) on the same walkers and data as the main
+    line, against the constant-propagation path on the resident data set."""
+    import torch
+    cfg = E.Config.from_workload(w)
+    ds = E.dataset_init(data, psd, cfg)
+    P = torch.from_numpy(W.walkers(w)).cuda()
+    C = np.zeros((w.B, 2, 3))
+    C[:, 0] = [0.1, 0.05, 0.01]
+    C[:, 1] = [1e-15, 5e-16, 1e-16]
+    coef = torch.from_numpy(C).cuda()
+    ws = E.alloc_workspace(cfg, w.B)
+    out = torch.empty(w.B, dtype=torch.float64, device="cuda")
+    res = {}
+    for name, call in (("constant", lambda: E.loglike_dataset(P, ds, cfg, out=out, ws=ws)),
+                       ("fmg", lambda: E.loglike_dataset_fmg(P, coef, 1e-2, ds, cfg, out=out,
+                                                             ws=ws))):
+        for _ in range(warmup):
+            call()
+        torch.cuda.synchronize()
+        with E.Tracer() as tr:
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                call()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st = tr.read()
+        res[name] = {"value": steps * w.B / (t1 - t0), "ms_per_step": 1e3 * (t1 - t0) / steps,
+                     "inner_product_ms": st["inner_product"][0] / steps}
+    res.update({"unit": "lnL evals/s", "workload": w.name, "series_terms": 3, "f_star_hz": 1e-2,
+                "fmg_over_constant_step": res["fmg"]["ms_per_step"] / res["constant"]["ms_per_step"]})
+    return res
+
+
 def run_serving(E, W, n_burst: int, n_requests: int, arena_gib: float, n_streams: int,
                 max_batch: int, n_sweep: int = 0):
     """Serving loop (mixed precision): 8 chains x 3 observation times of
@@ -348,6 +383,7 @@ def main():
     ap.add_argument("--serve-sweep", type=int, default=100,
                     help="requests at each of 0.5x and 1.0x the saturated rate")
     ap.add_argument("--no-sampler", action="store_true")
+    ap.add_argument("--no-fmg", action="store_true")
     ap.add_argument("--sampler-steps", type=int, default=4)
     ap.add_argument("--no-config5", action="store_true")
     ap.add_argument("--config5-steps", type=int, default=2)
@@ -434,6 +470,14 @@ def main():
         print(f"[bench] sampler: fp64 {sampler['fp64']['steps_per_s']:.2f} steps/s, mixed "
               f"{sampler['mixed']['steps_per_s']:.2f} steps/s ({2 * w64.B} walkers)",
               file=sys.stderr, flush=True)
+
+    fmg = None
+    if not args.no_fmg:
+        fmg = {"fp64": run_fmg(E, W, w64, data, psd, max(2, args.steps // 2), 1),
+               "mixed": run_fmg(E, W, wmx, data, psd, max(2, args.steps // 2), 1)}
+        print(f"[bench] frequency-dependent propagation: fp64 {fmg['fp64']['fmg']['value']:.1f} "
+              f"evals/s, mixed {fmg['mixed']['fmg']['value']:.1f} evals/s", file=sys.stderr,
+              flush=True)
 
     serving = None
     if not args.no_serving:
@@ -522,6 +566,7 @@ def main():
         "serving": serving,
         "stress": config5,
         "sampler": sampler,
+        "frequency_dependent_propagation": fmg,
         "stages": stages_out,
     }
     print(json.dumps(rec), flush=True)

@@ -53,7 +53,7 @@ extern "C" {
 #endif
 
 #define EMRI_NPAR 17
-#define EMRI_ABI_VERSION 2
+#define EMRI_ABI_VERSION 3
 
 typedef enum {
     EMRI_OK = 0,
@@ -151,6 +151,32 @@ emri_status emri_dataset_init(const double* data, const double* psd, const emri_
 emri_status emri_loglike_dataset(const double* params, int64_t B, const void* ds,
                                  const emri_cfg* cfg, double* lnL, void* ws, size_t ws_bytes,
                                  hipStream_t stream);
+
+/* ---- frequency-dependent propagation --------------------------------------
+ * The variant of Sec. 2 "Waveform propagation" in which alpha_M and alpha_T
+ * depend on the GW frequency, written as power series in x = f / f_star with
+ * coefficients constant in z:
+ *   alpha_M(f) = sum_{n<P} m_n x^n,   alpha_T(f) = p[16] + sum_{n<P} t_n x^n.
+ * The friction integral of Eq. (5) then gives the extra amplitude factor
+ * (1 + z)^(-alpha_M(f)/2) on top of Eq. (6), and the speed the delay
+ * Delta T(f) = (1/c_T(f) - 1) chi / c with c_T(f)^2 = 1 + alpha_T(f) (chi the
+ * comoving distance), applied as exp(-2 pi i f Delta T(f)) bin by bin.  A
+ * walker with 1 + alpha_T(f) <= 0 in any bin 1..N/2-1 gets lnL = -inf. */
+#define EMRI_FMG_MAX 8
+typedef struct {
+    int32_t order;               /* P, 0..EMRI_FMG_MAX (0: the constant propagation, with the
+                                    delay evaluated bin by bin) */
+    int32_t reserved;            /* 0 */
+    double f_star;               /* pivot frequency [Hz], > 0 */
+} emri_fmg;                      /* a HOST struct, read during the call */
+
+/* As emri_loglike_dataset, with the series coefficients coef[B][2][P]
+ * (device; per walker m_0..m_{P-1} then t_0..t_{P-1}; may be NULL when
+ * P = 0).  Errors: order outside 0..8, f_star not positive and finite, or a
+ * NULL pointer: EMRI_EINVAL before anything is launched. */
+emri_status emri_loglike_dataset_fmg(const double* params, int64_t B, const double* coef,
+                                     const emri_fmg* fmg, const void* ds, const emri_cfg* cfg,
+                                     double* lnL, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Frequency-domain model of each walker, the quantity the likelihood
  * compares with the data (Eqs. (4)-(6) applied to the transformed waveform):

@@ -365,7 +365,8 @@ emri_status emri_fft_batch(const void* ht, int64_t B, const emri_cfg* cfg, void*
 
 static emri_status loglike_chunks(const emri_cfg* cfg, const double* params, int64_t B,
                                   const void* ds, double* lnL, void* ws, size_t ws_bytes,
-                                  hipStream_t stream)
+                                  hipStream_t stream, const emri_fmg* fmg = nullptr,
+                                  const double* coef = nullptr)
 {
     Plan p1;
     const char* err;
@@ -382,7 +383,11 @@ static emri_status loglike_chunks(const emri_cfg* cfg, const double* params, int
                                 (char*)ws + p.off_z, false, stream)))
             return st;
         if ((st = check_launch(launch_fft_cols(p, nb, ws, stream), "fft columns"))) return st;
-        if ((st = check_launch(launch_likelihood(p, nb, ds, ws, lnL + w0, stream), "likelihood")))
+        FmgArgs fa{fmg ? fmg->order : 0, fmg ? fmg->f_star : 0.0,
+                   coef ? coef + w0 * 2 * (fmg ? fmg->order : 0) : nullptr};
+        if ((st = check_launch(launch_likelihood(p, nb, ds, ws, lnL + w0, fmg ? &fa : nullptr,
+                                                 stream),
+                               "likelihood")))
             return st;
     }
     return EMRI_OK;
@@ -430,6 +435,26 @@ emri_status emri_loglike_dataset(const double* params, int64_t B, const void* ds
     if (B == 0) return EMRI_OK;
     if (!params || !ds || !lnL || !ws) return fail(EMRI_EINVAL, "null pointer argument");
     return loglike_chunks(cfg, params, B, ds, lnL, ws, ws_bytes, stream);
+}
+
+emri_status emri_loglike_dataset_fmg(const double* params, int64_t B, const double* coef,
+                                     const emri_fmg* fmg, const void* ds, const emri_cfg* cfg,
+                                     double* lnL, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    Plan p;
+    const char* err;
+    emri_status st = make_plan(cfg, 1, &p, &err);
+    if (st != EMRI_OK) return fail(st, err);
+    if (!fmg) return fail(EMRI_EINVAL, "null fmg descriptor");
+    if (fmg->order < 0 || fmg->order > EMRI_FMG_MAX)
+        return fail(EMRI_EINVAL, "fmg: order must be in 0..8");
+    if (!(fmg->f_star > 0.0) || !isfinite(fmg->f_star))
+        return fail(EMRI_EINVAL, "fmg: f_star must be positive and finite");
+    if (B < 0) return fail(EMRI_EINVAL, "B must be >= 0");
+    if (B == 0) return EMRI_OK;
+    if (!params || !ds || !lnL || !ws || (fmg->order > 0 && !coef))
+        return fail(EMRI_EINVAL, "null pointer argument");
+    return loglike_chunks(cfg, params, B, ds, lnL, ws, ws_bytes, stream, fmg, coef);
 }
 
 // ---- ensemble sampler step ---------------------------------------------------

@@ -46,6 +46,7 @@ enum {
     WC_KW = 25,     // index of the last orbit node before the LSO
     WC_Z = 26, WC_XI = 27, WC_DT = 28, WC_D = 29,
     WC_HASDT = 30,  // 1 if Delta T != 0
+    WC_AT = 31,     // alpha_T of the parameter row
     WC_KSEG = 32,   // 16 slots: K_w as known after orbit segment i (the
                     // segment's end when the orbit is still before the LSO)
     WC = 48
@@ -150,9 +151,17 @@ hipError_t launch_fft_cols(const Plan& p, int64_t B, void* ws, hipStream_t s);
 hipError_t launch_unpack(const Plan& p, int64_t B, const void* ws, void* hf, hipStream_t s);
 hipError_t launch_dataset(const Plan& p, const double* data, const double* psd, void* ds,
                           hipStream_t s);
-// fused pass B + inner product + per-walker sum; expects pass A done on z
+// frequency-dependent propagation: P series terms per walker, coef [B][2][P]
+// (alpha_M coefficients, then alpha_T's) of the walkers of this launch
+struct FmgArgs {
+    int P;
+    double f_star;
+    const double* coef;
+};
+// fused pass B + inner product + per-walker sum; expects pass A done on z;
+// fmg NULL: constant propagation
 hipError_t launch_likelihood(const Plan& p, int64_t B, const void* ds, void* ws, double* lnL,
-                             hipStream_t s);
+                             const FmgArgs* fmg, hipStream_t s);
 
 hipError_t launch_model_unpack(const Plan& p, int64_t B, const void* ws, void* mf,
                                hipStream_t s);  // unpack with 1/(Xi d_L) and delay

@@ -141,6 +141,61 @@ __device__ inline void delay_rotation(int64_t k, double phi, double* c, double* 
     sincospi(-2.0 * f, s, c);
 }
 
+// Propagation factor of one walker per bin k, as a rotation (cr, ci) of the
+// unit-distance spectrum (the walker's g dt is applied separately).
+// Constant alpha_M, alpha_T (Eqs. (4)-(6)): exp(-2 pi i k phi), or nothing
+// when Delta T = 0.
+struct PropConst {
+    bool hasdt;
+    double phi;
+    __device__ __forceinline__ bool rot(int64_t k, double* cr, double* ci) const
+    {
+        if (!hasdt) return false;
+        delay_rotation(k, phi, cr, ci);
+        return true;
+    }
+};
+
+// Frequency-dependent alpha_M, alpha_T (the variant of Sec. 2 "Waveform
+// propagation", power series in x = f/f* with coefficients constant in z):
+// amplitude (1 + z)^(-alpha_M(f)/2), delay dT(f) = (1/c_T(f) - 1) chi with
+// c_T(f)^2 = 1 + alpha_T(row) + sum t_n x^n, phase exp(-2 pi i f dT(f)).
+// 1 + alpha_T <= 0 gives NaN, which the walker sum turns into lnL = -inf;
+// the DC and Nyquist bins (weight 0) take the factor 1.
+struct PropFmg {
+    const double* cm;     // m_0..m_{P-1}, then t_0..t_{P-1}
+    int P;
+    double xs;            // df / f*
+    double hl;            // -ln(1 + z) / 2
+    double at0;           // alpha_T of the parameter row
+    double cdf;           // chi df: f dT(f) = k cdf (1/c_T - 1)
+    int64_t half;         // N / 2
+    __device__ __forceinline__ bool rot(int64_t k, double* cr, double* ci) const
+    {
+        if (k == 0 || k == half) {
+            *cr = 1.0;
+            *ci = 0.0;
+            return true;
+        }
+        const double x = (double)k * xs;
+        double am = 0.0, at = 0.0;
+        for (int n = P - 1; n >= 0; --n) {
+            am = fma(am, x, cm[n]);
+            at = fma(at, x, cm[P + n]);
+        }
+        at += at0;
+        const double amp = exp(hl * am);
+        const double ct = sqrt(1.0 + at);
+        double cyc = (double)k * cdf * (-at / (ct * (1.0 + ct)));
+        cyc -= floor(cyc);
+        double sn, cs;
+        sincospi(-2.0 * cyc, &sn, &cs);
+        *cr = amp * cs;
+        *ci = amp * sn;
+        return true;
+    }
+};
+
 // Per-lane accumulation of the inner product over the lane's bins.  A bin
 // is given by its packed value z = Z_k and the value m = Z_{N-k} it pairs
 // with; X_I = (z + conj m)/2, X_II = (z - conj m)/(2i), times the propagation
@@ -151,16 +206,16 @@ template <typename R, bool MIXED> struct BinAcc;
 
 template <typename R> struct BinAcc<R, false> {
     double acc = 0.0;
+    template <typename Prop>
     __device__ __forceinline__ void add(R zr, R zi, R mr, R mi, int64_t k, int64_t b,
-                                        double scale, bool hasdt, double phi,
+                                        double scale, const Prop& pr,
                                         const typename C2<R>::T* __restrict__ D,
                                         const R* __restrict__ Wt, int64_t half)
     {
         double xr = 0.5 * (zr + mr), xi = 0.5 * (zi - mi);     // X_I
         double yr = 0.5 * (zi + mi), yi = -0.5 * (zr - mr);    // X_II
-        if (hasdt) {
-            double cr, ci;
-            delay_rotation(k, phi, &cr, &ci);
+        double cr, ci;
+        if (pr.rot(k, &cr, &ci)) {
             double u = xr * cr - xi * ci; xi = xr * ci + xi * cr; xr = u;
             u = yr * cr - yi * ci; yi = yr * ci + yi * cr; yr = u;
         }
@@ -175,16 +230,16 @@ template <typename R> struct BinAcc<R, false> {
 
 template <typename R> struct BinAcc<R, true> {
     float cr_s = 0.f, cr_c = 0.f, mm_s = 0.f, mm_c = 0.f;   // Kahan sums
+    template <typename Prop>
     __device__ __forceinline__ void add(R zr, R zi, R mr, R mi, int64_t k, int64_t b,
-                                        double scale, bool hasdt, double phi,
+                                        double scale, const Prop& pr,
                                         const typename C2<R>::T* __restrict__ D,
                                         const R* __restrict__ Wt, int64_t half)
     {
         float xr = 0.5f * (zr + mr), xi = 0.5f * (zi - mi);
         float yr = 0.5f * (zi + mi), yi = -0.5f * (zr - mr);
-        if (hasdt) {
-            double cr, ci;
-            delay_rotation(k, phi, &cr, &ci);
+        double cr, ci;
+        if (pr.rot(k, &cr, &ci)) {
             const float fr = (float)cr, fi = (float)ci;
             float u = xr * fr - xi * fi; xi = xr * fi + xi * fr; xr = u;
             u = yr * fr - yi * fi; yi = yr * fi + yi * fr; yr = u;
@@ -207,6 +262,21 @@ template <typename R> struct BinAcc<R, true> {
     }
 };
 
+// the propagation factor of walker w (constants c = wc + w WC)
+template <bool FMG>
+__device__ __forceinline__ auto walker_prop(const double* c, int64_t w, int64_t N,
+                                            const double* fcoef, int fP, double fxs, double dt)
+{
+    if constexpr (FMG) {
+        const double z = c[WC_Z];
+        const double df = 1.0 / ((double)N * dt);
+        return PropFmg{fcoef + w * 2 * fP, fP, fxs, -0.5 * log1p(z), c[WC_AT],
+                       c[WC_D] / (1.0 + z) * df, N / 2};
+    } else {
+        return PropConst{c[WC_HASDT] != 0.0, c[WC_PHI]};
+    }
+}
+
 // Fused pass B + inner product.  Workgroup (g, walker tile): rows g and
 // R2 - g of the column-transformed signal (rows 0 and R2/2 pair with
 // themselves), L = R1 points each, L/8 lanes.  For each walker of the tile:
@@ -220,7 +290,7 @@ template <typename R> struct BinAcc<R, true> {
 // One FP64 partial per (g, walker).  Register budget 128 (4 waves per SIMD,
 // two workgroups per CU): occupancy matters more here than the few spills
 // it costs the FP64 variant.
-template <typename R, bool MIXED, int MAXT>
+template <typename R, bool MIXED, int MAXT, bool FMG>
 __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(4)))
 k_rows_like(const typename C2<R>::T* __restrict__ z,
                                                     int64_t N, int L, int lgL, int64_t R2,
@@ -228,7 +298,9 @@ k_rows_like(const typename C2<R>::T* __restrict__ z,
                                                     const void* __restrict__ dsd,
                                                     const void* __restrict__ dsw,
                                                     const typename C2<R>::T* __restrict__ twL,
-                                                    double* __restrict__ part, int64_t B, int WT)
+                                                    double* __restrict__ part, int64_t B, int WT,
+                                                    const double* __restrict__ fcoef, int fP,
+                                                    double fxs)
 {
     using T2 = typename C2<R>::T;
     extern __shared__ unsigned char smem_raw[];
@@ -326,8 +398,7 @@ k_rows_like(const typename C2<R>::T* __restrict__ z,
             }
         }
         const double scale = c[WC_G] * dt;
-        const bool hasdt = c[WC_HASDT] != 0.0;
-        const double phi = c[WC_PHI];
+        const auto pr = walker_prop<FMG>(c, w, N, fcoef, fP, fxs, dt);
         BinAcc<R, MIXED> acc;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
@@ -337,7 +408,7 @@ k_rows_like(const typename C2<R>::T* __restrict__ z,
             if (i < 4) { zr = ar[i]; zi = ai[i]; mr = sre[mp]; mi = sim[mp]; }
             else { zr = sre[mp]; zi = sim[mp]; mr = ar[i]; mi = ai[i]; }
             acc.add(zr, zi, mr, mi, own_row(i) + R2 * own_col(i), own_row(i) * hL + own_col(i),
-                    scale, hasdt, phi, D, Wt, half);
+                    scale, pr, D, Wt, half);
         }
         const double lane_sum = acc.lane_sum();
         const double s = block_sum(lane_sum, sh);
@@ -354,12 +425,13 @@ k_rows_like(const typename C2<R>::T* __restrict__ z,
 // (B, L-1-p) for p >= L/2 (only p < L/2 in a self-paired row).  Register
 // budget 128 (4 waves per SIMD, four workgroups per CU): faster than the
 // spill-free 156 registers at three.
-template <typename R, bool MIXED, int MAXT>
+template <typename R, bool MIXED, int MAXT, bool FMG>
 __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(4)))
 k_rows_like16(const typename C2<R>::T* __restrict__ z, int64_t N, int L, int lgL, int64_t R2,
               double dt, const double* __restrict__ wc, const void* __restrict__ dsd,
               const void* __restrict__ dsw, const typename C2<R>::T* __restrict__ twL,
-              double* __restrict__ part, int64_t B, int WT)
+              double* __restrict__ part, int64_t B, int WT, const double* __restrict__ fcoef,
+              int fP, double fxs)
 {
     using T2 = typename C2<R>::T;
     extern __shared__ unsigned char smem_raw[];
@@ -428,8 +500,7 @@ k_rows_like16(const typename C2<R>::T* __restrict__ z, int64_t N, int L, int lgL
         }
         __syncthreads();
         const double scale = c[WC_G] * dt;
-        const bool hasdt = c[WC_HASDT] != 0.0;
-        const double phi = c[WC_PHI];
+        const auto pr = walker_prop<FMG>(c, w, N, fcoef, fP, fxs, dt);
         BinAcc<R, MIXED> acc;
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
@@ -437,11 +508,11 @@ k_rows_like16(const typename C2<R>::T* __restrict__ z, int64_t N, int L, int lgL
             if (p < hL) {
                 const int mp = (self && g == 0) ? ((L - p) & (L - 1)) : (L - 1 - p);
                 acc.add(ar[s], ai[s], sre[px<R>(mp)], sim[px<R>(mp)], rowA + R2 * p,
-                        rowA * hL + p, scale, hasdt, phi, D, Wt, half);
+                        rowA * hL + p, scale, pr, D, Wt, half);
             } else if (!self) {
                 const int q = L - 1 - p;
                 acc.add(sre[px<R>(q)], sim[px<R>(q)], ar[s], ai[s], rowB + R2 * q, rowB * hL + q,
-                        scale, hasdt, phi, D, Wt, half);
+                        scale, pr, D, Wt, half);
             }
         }
         const double s = block_sum(acc.lane_sum(), sh);
@@ -469,7 +540,7 @@ __global__ void __launch_bounds__(256) k_walker_sum(const double* __restrict__ p
 }
 
 hipError_t launch_likelihood(const Plan& p, int64_t B, const void* ds, void* ws, double* lnL,
-                             hipStream_t s)
+                             const FmgArgs* fmg, hipStream_t s)
 {
     char* base = (char*)ws;
     const char* db = (const char*)ds;
@@ -487,8 +558,13 @@ hipError_t launch_likelihood(const Plan& p, int64_t B, const void* ds, void* ws,
     // FP32 rows take 16 values per lane; FP64 keeps 8: two rows of 16 FP64
     // values do not fit 128 registers
     const int E = (p.prec == EMRI_FP64) ? 8 : 16;
-    const void* kern = (p.prec == EMRI_FP64) ? (const void*)k_rows_like<double, false, 512>
-                                             : (const void*)k_rows_like16<float, true, 256>;
+    const bool f = fmg != nullptr;
+    const void* kern =
+        (p.prec == EMRI_FP64)
+            ? (f ? (const void*)k_rows_like<double, false, 512, true>
+                 : (const void*)k_rows_like<double, false, 512, false>)
+            : (f ? (const void*)k_rows_like16<float, true, 256, true>
+                 : (const void*)k_rows_like16<float, true, 256, false>);
     hipError_t ae = allow_lds(kern, lds);
     if (ae != hipSuccess) return ae;
     if (L / E > 512 || L < 16 * (E / 8)) return hipErrorInvalidValue;   // rows of 2^7 .. 2^12 points
@@ -504,8 +580,11 @@ hipError_t launch_likelihood(const Plan& p, int64_t B, const void* ds, void* ws,
         const double* a_wc = wc;
         const void* a_tw = (const void*)(twb + (p.prec == EMRI_FP64 ? tl.oB : tl.fB));
         double* a_part = part;
+        const double* a_fc = f ? fmg->coef : nullptr;
+        int a_fP = f ? fmg->P : 0;
+        double a_fxs = f ? 1.0 / ((double)p.N * p.dt * fmg->f_star) : 0.0;
         void* args[] = {&a_z, &a_N, &a_L, &a_lgL, &a_R2, &a_dt, &a_wc, (void*)&dsd,
-                        (void*)&dsw, &a_tw, &a_part, &a_B, &a_WT};
+                        (void*)&dsw, &a_tw, &a_part, &a_B, &a_WT, &a_fc, &a_fP, &a_fxs};
         ae = hipLaunchKernel(kern, grid, blk, args, lds, s);
     }
     trace_mark(ST_LIKE, s, false);

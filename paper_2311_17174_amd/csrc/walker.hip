@@ -206,6 +206,7 @@ __global__ void __launch_bounds__(64) k_walker_setup(const double* __restrict__ 
     c[WC_DOP] = 2.0 * kPi * kAuSeconds * sts;
     c[WC_Z] = z; c[WC_XI] = Xi; c[WC_DT] = dT; c[WC_D] = D;
     c[WC_HASDT] = (dT != 0.0) ? 1.0 : 0.0;
+    c[WC_AT] = at;
 
     // orbit: classical RK4, nodes t_k = k h
     double Y0 = p[5], Y1 = nu0, Y2 = p[6], Y3 = e0, Y4 = p[7];

@@ -26,7 +26,7 @@ EXPORTED = ("emri_abi_version", "emri_last_error", "emri_workspace_bytes",
             "emri_dataset_bytes", "emri_dataset_init", "emri_loglike_dataset",
             "emri_model_batch", "emri_noise_psd", "emri_trace_enable", "emri_trace_read",
             "emri_trace_stage_name", "emri_sampler_workspace_bytes", "emri_ensemble_lnprob",
-            "emri_stretch_step")
+            "emri_stretch_step", "emri_loglike_dataset_fmg")
 
 
 class EmriError(RuntimeError):
@@ -56,6 +56,11 @@ def make_prior(free_idx, lo, hi) -> _Prior:
     for d, (i, a, b) in enumerate(zip(free_idx, lo, hi)):
         pr.idx[d], pr.lo[d], pr.hi[d] = int(i), float(a), float(b)
     return pr
+
+
+class _Fmg(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("f_star", ctypes.c_double)]
 
 
 @dataclass(frozen=True)
@@ -107,6 +112,8 @@ def _load():
         "emri_sampler_workspace_bytes": ([cp, i64], sz),
         "emri_ensemble_lnprob": ([vp, i64, ctypes.POINTER(_Prior), vp, cp, vp, vp, sz, vp],
                                  ctypes.c_int),
+        "emri_loglike_dataset_fmg": ([vp, i64, vp, ctypes.POINTER(_Fmg), vp, cp, vp, vp, sz, vp],
+                                     ctypes.c_int),
         "emri_stretch_step": ([vp, vp, i64, ctypes.POINTER(_Prior), d, vp, vp, cp, vp, vp, sz,
                                vp], ctypes.c_int),
     }
@@ -245,6 +252,28 @@ def loglike_dataset(params: torch.Tensor, ds: torch.Tensor, cfg: Config,
     c = cfg.c()
     _check(lib.emri_loglike_dataset(pp, B, ds.data_ptr(), ctypes.byref(c), op, ws.data_ptr(),
                                     ws.numel(), _stream(stream)), "emri_loglike_dataset")
+    return out
+
+
+def loglike_dataset_fmg(params: torch.Tensor, coef: torch.Tensor, f_star: float,
+                        ds: torch.Tensor, cfg: Config, out: torch.Tensor | None = None,
+                        ws: torch.Tensor | None = None, stream=None, order: int | None = None):
+    """lnL with frequency-dependent alpha_M, alpha_T: coef [B][2][P] (device,
+    float64): per walker the alpha_M series coefficients, then alpha_T's."""
+    B = params.shape[0]
+    pp = _dev(params, torch.float64, (B, NPAR), "params")
+    P = coef.shape[2] if order is None else order
+    cp_ = _dev(coef, torch.float64, (B, 2, P), "coef") if coef.numel() else None
+    if out is None:
+        out = torch.empty(B, dtype=torch.float64, device=params.device)
+    op = _dev(out, torch.float64, (B,), "out")
+    if ws is None:
+        ws = alloc_workspace(cfg, max(B, 1), params.device)
+    c = cfg.c()
+    f = _Fmg(int(P), 0, float(f_star))
+    _check(lib.emri_loglike_dataset_fmg(pp, B, cp_, ctypes.byref(f), ds.data_ptr(),
+                                        ctypes.byref(c), op, ws.data_ptr(), ws.numel(),
+                                        _stream(stream)), "emri_loglike_dataset_fmg")
     return out
 
 

@@ -38,13 +38,17 @@ def test_library_exports_every_declared_symbol(E):
     missing = [n for n in declared_functions() if n not in exported]
     assert not missing, missing
     assert set(E.EXPORTED) == set(declared_functions())
-    assert E.lib.emri_abi_version() == 2
+    assert E.lib.emri_abi_version() == 3
 
 
 def test_struct_layout_matches_header(E):
     # int64 N at offset 16, then four int32: 40 bytes in total
     assert ctypes.sizeof(E._Cfg) == 40
     assert E._Cfg.N.offset == 16 and E._Cfg.n_harm.offset == 24
+    # emri_fmg: two int32 then the pivot frequency; emri_prior: n_free, idx[17], lo, hi
+    assert ctypes.sizeof(E._Fmg) == 16 and E._Fmg.f_star.offset == 8
+    assert E._Prior.idx.offset == 4 and E._Prior.lo.offset == 72
+    assert E._Prior.hi.offset == 72 + 17 * 8 and ctypes.sizeof(E._Prior) == 72 + 34 * 8
 
 
 @pytest.mark.parametrize("bad", [

@@ -1,0 +1,110 @@
+"""GPU parity of the likelihood with frequency-dependent alpha_M, alpha_T
+(power series in f/f*) through the C ABI, against the CPU oracle.
+
+Tolerances as for the constant propagation: FP64 relative 1e-10, mixed
+relative 1e-4; the -inf pattern (a superluminal break in some bin, invalid
+rows) must match exactly.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2311_17174_amd import workloads as W
+from tests.gpu_common import ocfg, oracle_dataset, say, to_device_data
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+EINVAL = -1
+F_STAR = 1e-2
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_2311_17174_amd import emri
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return emri
+
+
+def fmg_case(prec):
+    w = W.small(prec, n_harm=6, Xi0=0.9, n_Xi=2.0)
+    P = W.walkers(w, B=7)
+    P[5, 16] = -1.2e-14                          # a GW-speed shift of the parameter row too
+    P[6, 1] = 2e6                                # invalid row (mu > M)
+    C = np.zeros((7, 2, 3))
+    C[1, 0] = [0.3, -0.2, 0.1]                   # friction only
+    C[2, 1] = [1e-14, 2e-14, -5e-15]             # speed only, phases of order one
+    C[3, 0] = [-0.5, 0.4, 0.0]; C[3, 1] = [0.0, 3e-14, 1e-14]
+    C[4, 1] = [0.0, -200.0, 0.0]                 # 1 + alpha_T < 0 above f*/200: -inf
+    C[5, 0] = [0.1, 0.0, 0.2]; C[5, 1] = [2e-15, 0.0, 1e-14]
+    return w, P, C
+
+
+def run(E, w, P, C, d, S, ws=None):
+    cfg = E.Config.from_workload(w)
+    dd, ss = to_device_data(d, S)
+    ds = E.dataset_init(dd, ss, cfg)
+    coef = torch.from_numpy(np.ascontiguousarray(C)).cuda()
+    return E.loglike_dataset_fmg(torch.from_numpy(P).cuda(), coef, F_STAR, ds, cfg,
+                                 ws=ws).cpu().numpy(), cfg, ds
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fmg_parity(E, prec):
+    w, P, C = fmg_case(prec)
+    d, S = oracle_dataset(w, True)
+    ref = O.loglike_fmg(P, C, F_STAR, d, S, ocfg(w))
+    got, cfg, ds = run(E, w, P, C, d, S)
+    say("fmg lnL ref", ref)
+    say("fmg lnL got", got)
+    fin = np.isfinite(ref)
+    assert list(np.where(~fin)[0]) == [4, 6]
+    assert np.array_equal(fin, np.isfinite(got)) and np.all(got[~fin] == -np.inf)
+    rel = np.abs(got[fin] - ref[fin]) / np.abs(ref[fin])
+    say("rel err", rel)
+    assert np.all(rel <= (1e-10 if prec == "fp64" else 1e-4))
+    # the series moves lnL by far more than the tolerance
+    base = O.loglike(P, d, S, ocfg(w))
+    assert np.all(np.abs(ref[1:4] - base[1:4]) > 1e3 * 1e-10 * np.abs(base[1:4]))
+
+
+def test_fmg_signal_part_parity(E):
+    """Noise-less data, where lnL is the signal part alone (tens, not 3e4):
+    FP64 parity 1e-10 of <h|h>."""
+    w, P, C = fmg_case("fp64")
+    d, S = oracle_dataset(w, False)
+    ref = O.loglike_fmg(P, C, F_STAR, d, S, ocfg(w))
+    got, _, _ = run(E, w, P, C, d, S)
+    hh = -2.0 * O.loglike(w.inj[None], np.zeros_like(d), S, ocfg(w))[0]
+    fin = np.isfinite(ref)
+    say("signal-part lnL ref", ref, "got", got, "<h|h>", hh)
+    assert np.max(np.abs(got[fin] - ref[fin])) <= 1e-10 * hh
+
+
+def test_fmg_order_zero_chunks_and_errors(E):
+    """P = 0 is the constant propagation (to rounding of the per-bin delay);
+    a workspace of 2 walkers gives bitwise the same results; bad descriptors
+    are rejected."""
+    w, P, C = fmg_case("fp64")
+    d, S = oracle_dataset(w, True)
+    cfg = E.Config.from_workload(w)
+    dd, ss = to_device_data(d, S)
+    ds = E.dataset_init(dd, ss, cfg)
+    Pd = torch.from_numpy(P).cuda()
+    plain = E.loglike_dataset(Pd, ds, cfg).cpu().numpy()
+    empty = torch.zeros((7, 2, 0), dtype=torch.float64, device="cuda")
+    zero = E.loglike_dataset_fmg(Pd, empty, F_STAR, ds, cfg).cpu().numpy()
+    fin = np.isfinite(plain)
+    assert np.array_equal(fin, np.isfinite(zero))
+    assert np.all(np.abs(zero[fin] - plain[fin]) <= 1e-12 * np.abs(plain[fin]))
+    coef = torch.from_numpy(np.ascontiguousarray(C)).cuda()
+    full = E.loglike_dataset_fmg(Pd, coef, F_STAR, ds, cfg).cpu().numpy()
+    ws = torch.empty(E.workspace_bytes(cfg, 2), dtype=torch.uint8, device="cuda")
+    chunked = E.loglike_dataset_fmg(Pd, coef, F_STAR, ds, cfg, ws=ws).cpu().numpy()
+    assert np.array_equal(full, chunked)
+    for fs, order in ((0.0, 3), (float("nan"), 3), (F_STAR, 9), (F_STAR, -1)):
+        c9 = torch.zeros((7, 2, max(order, 0)), dtype=torch.float64, device="cuda")
+        with pytest.raises(E.EmriError) as ei:
+            E.loglike_dataset_fmg(Pd, c9, fs, ds, cfg, order=order)
+        assert ei.value.status == EINVAL

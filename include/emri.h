@@ -190,9 +190,16 @@ emri_status emri_model_batch(const double* params, int64_t B, const emri_cfg* cf
                              void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* One-sided LISA noise PSD on the frequency grid f_k = k/(N dt), k = 0..N/2
- * (the paper's get_noise(), Sec. 3).  model 0: instrumental noise of Barack
- * & Cutler 2004, S(f) = 9.18e-52 f^-4 + 1.59e-41 + 9.18e-38 f^2 [1/Hz];
- * psd[0] = +infinity.  Other models: EMRI_EUNSUPPORTED.
+ * (the paper's get_noise(), Sec. 3, which has two noise models), in 1/Hz;
+ * psd[0] = +infinity.
+ *  model 0: instrumental noise of Barack & Cutler 2004,
+ *           S(f) = 9.18e-52 f^-4 + 1.59e-41 + 9.18e-38 f^2;
+ *  model 1: the sky-averaged sensitivity of Robson, Cornish & Liu 2019,
+ *           10/(3 L^2) [P_OMS + 2 (1 + cos^2(f/f*)) P_acc/(2 pi f)^4]
+ *           (1 + 0.6 (f/f*)^2), L = 2.5e9 m, f* = c/(2 pi L);
+ *  models 2..5: model 1 plus their galactic confusion noise for 0.5, 1, 2
+ *           and 4 years of observation.
+ * Other models: EMRI_EUNSUPPORTED.
  *  psd  [N/2+1] fp64 device output */
 emri_status emri_noise_psd(int model, int64_t N, double dt, double* psd, hipStream_t stream);
 

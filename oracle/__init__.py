@@ -98,6 +98,7 @@ def lib():
             "oracle_loglike_fmg": ([dp, i64, dp, ctypes.c_int32, ctypes.c_double, dp, dp, cp,
                                     dp], ctypes.c_int),
             "oracle_psd_bc04": ([dp, i64, dp], ctypes.c_int),
+            "oracle_psd_rcl": ([dp, i64, ctypes.c_int32, dp], ctypes.c_int),
             "oracle_make_data": ([dp, dp, dp, dp, i64, ctypes.c_double, dp], ctypes.c_int),
             "oracle_besselj": ([ctypes.c_int, ctypes.c_double], ctypes.c_double),
             "oracle_pm_coeffs": ([ctypes.c_int, ctypes.c_double, dp], ctypes.c_int),
@@ -243,6 +244,16 @@ def psd_bc04(f) -> np.ndarray:
     f = _f64(f)
     S = np.zeros_like(f)
     lib().oracle_psd_bc04(_p(f), f.size, _p(S))
+    return S
+
+
+def psd_rcl(f, confusion_years: float | None = None) -> np.ndarray:
+    """Robson-Cornish-Liu sky-averaged sensitivity; confusion noise for 0.5,
+    1, 2 or 4 years of observation, or none."""
+    f = _f64(f)
+    S = np.zeros_like(f)
+    conf = -1 if confusion_years is None else {0.5: 0, 1.0: 1, 2.0: 2, 4.0: 3}[float(confusion_years)]
+    _check(lib().oracle_psd_rcl(_p(f), f.size, conf, _p(S)), "psd_rcl")
     return S
 
 

@@ -821,6 +821,49 @@ int oracle_psd_bc04(const double *f, int64_t n, double *S)
     return 0;
 }
 
+/* The second noise model of the paper (Sec. 3, `get_noise()`): the LISA
+ * sensitivity of Robson, Cornish & Liu 2019 (CQG 36, 105011), sky-averaged,
+ * one-sided, in Hz^-1:
+ *   S_n = 10/(3 L^2) [P_OMS + 2 (1 + cos^2(f/f*)) P_acc / (2 pi f)^4]
+ *         (1 + (6/10) (f/f*)^2) + S_c,
+ * L = 2.5e9 m, f* = c / (2 pi L),
+ * P_OMS = (1.5e-11 m)^2 (1 + (2 mHz / f)^4),
+ * P_acc = (3e-15 m s^-2)^2 (1 + (0.4 mHz / f)^2) (1 + (f / 8 mHz)^4),
+ * and the galactic confusion noise
+ *   S_c = A f^(-7/3) exp(-f^al + be f sin(ka f)) (1 + tanh(ga (f_k - f))),
+ * A = 9e-45, (al, be, ka, ga, f_k) for 0.5, 1, 2 and 4 years of
+ * observation.  conf = -1: no confusion noise; 0..3: those four periods.
+ * Parity unpinned in its constants (no printed values are at hand); the
+ * tests pin its limits and shape. */
+int oracle_psd_rcl(const double *f, int64_t n, int32_t conf, double *S)
+{
+    static const double tab[4][5] = {
+        {0.133, 243.0, 482.0, 917.0, 0.00258},
+        {0.171, 292.0, 1020.0, 1680.0, 0.00215},
+        {0.165, 299.0, 611.0, 1340.0, 0.00173},
+        {0.138, -221.0, 521.0, 1680.0, 0.00113},
+    };
+    if (conf < -1 || conf > 3) return -1;
+    const double L = 2.5e9, fs = O_CLIGHT / (2.0 * O_PI * L);
+    for (int64_t i = 0; i < n; ++i) {
+        double v = f[i];
+        if (!(v > 0.0)) { S[i] = INFINITY; continue; }
+        double poms = 1.5e-11 * 1.5e-11 * (1.0 + pow(2e-3 / v, 4.0));
+        double pacc = 3e-15 * 3e-15 * (1.0 + pow(0.4e-3 / v, 2.0)) * (1.0 + pow(v / 8e-3, 4.0));
+        double cs = cos(v / fs);
+        double w4 = pow(2.0 * O_PI * v, 4.0);
+        double sn = 10.0 / (3.0 * L * L) * (poms + 2.0 * (1.0 + cs * cs) * pacc / w4) *
+                    (1.0 + 0.6 * (v / fs) * (v / fs));
+        if (conf >= 0) {
+            const double *t = tab[conf];
+            sn += 9e-45 * pow(v, -7.0 / 3.0) * exp(-pow(v, t[0]) + t[1] * v * sin(t[2] * v)) *
+                  (1.0 + tanh(t[3] * (t[4] - v)));
+        }
+        S[i] = sn;
+    }
+    return 0;
+}
+
 /* data = m[theta_inj] + n, with n_k = sqrt(S_k N dt / 4) (x_k + i y_k) for the
  * standard normal draws gauss[2][N/2+1][2] (NULL: noise-less data); bins 0
  * and N/2 carry no noise.  hinj is the unit-distance GR spectrum. */

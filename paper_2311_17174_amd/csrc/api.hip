@@ -507,11 +507,12 @@ emri_status emri_model_batch(const double* params, int64_t B, const emri_cfg* cf
 
 emri_status emri_noise_psd(int model, int64_t N, double dt, double* psd, hipStream_t stream)
 {
-    if (model != 0) return fail(EMRI_EUNSUPPORTED, "only noise model 0 (BC04 instrumental) exists");
+    if (model < 0 || model > 5)
+        return fail(EMRI_EUNSUPPORTED, "noise models are 0 (BC04) and 1..5 (Robson-Cornish-Liu)");
     if (N < 2 || (N & (N - 1)) || !(dt > 0.0) || !isfinite(dt))
         return fail(EMRI_EINVAL, "N must be a power of two >= 2 and dt positive");
     if (!psd) return fail(EMRI_EINVAL, "null pointer argument");
-    return check_launch(launch_noise_psd(N, dt, psd, stream), "noise psd");
+    return check_launch(launch_noise_psd(model, N, dt, psd, stream), "noise psd");
 }
 
 emri_status emri_trace_enable(int on)

@@ -336,21 +336,57 @@ hipError_t launch_model_unpack(const Plan& p, int64_t B, const void* ws, void* m
 }
 
 // one-sided LISA noise PSD (instrumental noise of Barack & Cutler 2004)
-__global__ void k_noise_psd(int64_t H, double df, double* __restrict__ psd)
+// galactic confusion noise shape (alpha, beta, kappa, gamma, f_knee) for 0.5,
+// 1, 2 and 4 years of observation (Robson, Cornish & Liu 2019)
+struct Confusion { double al, be, ka, ga, fk; };
+__constant__ Confusion kConfusion[4] = {
+    {0.133, 243.0, 482.0, 917.0, 0.00258},
+    {0.171, 292.0, 1020.0, 1680.0, 0.00215},
+    {0.165, 299.0, 611.0, 1340.0, 0.00173},
+    {0.138, -221.0, 521.0, 1680.0, 0.00113},
+};
+
+// model 0: BC04 instrumental noise; model 1: the sky-averaged sensitivity of
+// Robson, Cornish & Liu 2019 (arm L = 2.5 Gm, transfer frequency
+// f* = c / (2 pi L), optical-metrology and acceleration noise); models 2..5:
+// the same plus galactic confusion noise for 0.5, 1, 2, 4 years
+__global__ void k_noise_psd(int64_t H, double df, int model, double* __restrict__ psd)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= H) return;
     const double f = (double)k * df;
-    const double f2 = f * f;
-    psd[k] = (k == 0) ? INFINITY : 9.18e-52 / (f2 * f2) + 1.59e-41 + 9.18e-38 * f2;
+    if (k == 0) {
+        psd[k] = INFINITY;
+        return;
+    }
+    if (model == 0) {
+        const double f2 = f * f;
+        psd[k] = 9.18e-52 / (f2 * f2) + 1.59e-41 + 9.18e-38 * f2;
+        return;
+    }
+    const double L = 2.5e9, fs = kLightSpeed / (2.0 * kPi * L);
+    const double a = 2e-3 / f, b = 0.4e-3 / f, c = f / 8e-3;
+    const double poms = 1.5e-11 * 1.5e-11 * (1.0 + (a * a) * (a * a));
+    const double pacc = 3e-15 * 3e-15 * (1.0 + b * b) * (1.0 + (c * c) * (c * c));
+    const double cs = cos(f / fs);
+    const double w = 2.0 * kPi * f, w2 = w * w;
+    const double x = f / fs;
+    double sn = 10.0 / (3.0 * L * L) * (poms + 2.0 * (1.0 + cs * cs) * pacc / (w2 * w2)) *
+                (1.0 + 0.6 * x * x);
+    if (model >= 2) {
+        const Confusion t = kConfusion[model - 2];
+        sn += 9e-45 * pow(f, -7.0 / 3.0) * exp(-pow(f, t.al) + t.be * f * sin(t.ka * f)) *
+              (1.0 + tanh(t.ga * (t.fk - f)));
+    }
+    psd[k] = sn;
 }
 
-hipError_t launch_noise_psd(int64_t N, double dt, double* psd, hipStream_t s)
+hipError_t launch_noise_psd(int model, int64_t N, double dt, double* psd, hipStream_t s)
 {
     const int64_t H = N / 2 + 1;
     trace_mark(ST_PSD, s, true);
     hipLaunchKernelGGL(k_noise_psd, dim3((unsigned)((H + 255) / 256)), dim3(256), 0, s, H,
-                       1.0 / ((double)N * dt), psd);
+                       1.0 / ((double)N * dt), model, psd);
     trace_mark(ST_PSD, s, false);
     return hipGetLastError();
 }

@@ -165,7 +165,7 @@ hipError_t launch_likelihood(const Plan& p, int64_t B, const void* ds, void* ws,
 
 hipError_t launch_model_unpack(const Plan& p, int64_t B, const void* ws, void* mf,
                                hipStream_t s);  // unpack with 1/(Xi d_L) and delay
-hipError_t launch_noise_psd(int64_t N, double dt, double* psd, hipStream_t s);
+hipError_t launch_noise_psd(int model, int64_t N, double dt, double* psd, hipStream_t s);
 
 // ---- per-stage event tracing (see emri_trace_enable) ---------------------
 enum Stage {

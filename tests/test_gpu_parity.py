@@ -362,6 +362,19 @@ def test_noise_psd_parity(E):
     np.testing.assert_allclose(got[1:], ref[1:], rtol=4e-15)   # a few ulps
 
 
+@pytest.mark.parametrize("model,years", [(1, None), (2, 0.5), (3, 1.0), (4, 2.0), (5, 4.0)])
+def test_noise_psd_rcl_parity(E, model, years):
+    """Robson-Cornish-Liu sensitivity, with and without confusion noise, at
+    dt = 5 s (up to 0.1 Hz): pow/exp/tanh/cos of two libraries, relative 1e-13."""
+    N, dt = 1 << 20, 5.0
+    got = E.noise_psd(N, dt, model=model).cpu().numpy()
+    ref = O.psd_rcl(W.frequencies(N, dt), years)
+    assert np.isinf(got[0])
+    np.testing.assert_allclose(got[1:], ref[1:], rtol=1e-13)
+    with pytest.raises(E.EmriError):
+        E.noise_psd(N, dt, model=6)
+
+
 def test_config5_stress_chunked(E):
     """Config 5 (B=1024, 2 yr at dt = 5 s, 2^24 samples, 40 harmonics; the
     injection plunges at ~0.6 yr) through workspaces that hold a quarter and a

@@ -53,7 +53,7 @@ extern "C" {
 #endif
 
 #define EMRI_NPAR 17
-#define EMRI_ABI_VERSION 3
+#define EMRI_ABI_VERSION 4
 
 typedef enum {
     EMRI_OK = 0,
@@ -78,7 +78,17 @@ typedef enum {
  *  precision    emri_precision
  *  coarse_log2  the orbit is integrated with step h = dt * 2^coarse_log2
  *               (8..12) and read between nodes by cubic Hermite interpolation
- *  reserved     must be 0 */
+ *  ic           where the parameter row's orbital state applies:
+ *               EMRI_IC_START: at t = 0, nu0 = p[4], integrated forward to the
+ *               LSO (samples after it are zero);
+ *               EMRI_IC_LSO: the paper's convention (Sec. 3 "Waveform
+ *               computation"): e = p[3], Phi = p[5], gamma~ = p[6],
+ *               alpha = p[7] at the last stable orbit, nu = nu_LSO(e) (p[4]
+ *               unused), integrated backward; the LSO is the last coarse
+ *               node, t = K h with K = ceil(N_valid / 2^coarse_log2), so the
+ *               window ends within one coarse step of the plunge.  A walker
+ *               whose backward history leaves 0 <= e < 1, nu > 0 is invalid. */
+typedef enum { EMRI_IC_START = 0, EMRI_IC_LSO = 1 } emri_ic;
 typedef struct {
     double T_obs;
     double dt;
@@ -86,7 +96,7 @@ typedef struct {
     int32_t n_harm;
     int32_t precision;
     int32_t coarse_log2;
-    int32_t reserved;
+    int32_t ic;                  /* emri_ic */
 } emri_cfg;
 
 /* Library ABI version (EMRI_ABI_VERSION). */

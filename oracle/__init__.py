@@ -38,7 +38,7 @@ NPAR = 17
 class _Cfg(ctypes.Structure):
     _fields_ = [("T_obs", ctypes.c_double), ("dt", ctypes.c_double), ("N", ctypes.c_int64),
                 ("n_harm", ctypes.c_int32), ("coarse_log2", ctypes.c_int32),
-                ("lo_only", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("lo_only", ctypes.c_int32), ("ic_lso", ctypes.c_int32)]
 
 
 @dataclass(frozen=True)
@@ -49,6 +49,7 @@ class OracleConfig:
     n_harm: int
     coarse_log2: int = 10
     lo_only: bool = False
+    ic_lso: bool = False      # initial conditions at the LSO, orbit integrated backward
 
     @property
     def n_valid(self) -> int:
@@ -61,7 +62,7 @@ class OracleConfig:
 
     def c(self) -> _Cfg:
         return _Cfg(self.T_obs, self.dt, self.N, self.n_harm, self.coarse_log2,
-                    1 if self.lo_only else 0, 0)
+                    1 if self.lo_only else 0, 1 if self.ic_lso else 0)
 
 
 def build(force: bool = True) -> str:

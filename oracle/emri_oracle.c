@@ -85,7 +85,7 @@ typedef struct {
     int32_t n_harm;      /* n_max of Eq. (2)                                 */
     int32_t coarse_log2; /* coarse ODE step = dt * 2^coarse_log2            */
     int32_t lo_only;     /* test hook: leading-order (Peters-Mathews) ODE    */
-    int32_t pad;
+    int32_t ic_lso;      /* 1: initial conditions at the LSO, integrated backward */
 } oracle_cfg;
 
 int oracle_num_threads(void);
@@ -173,7 +173,8 @@ static double nu_lso(double M_s, double e)
     return pow((1.0 - e * e) / (6.0 + 2.0 * e), 1.5) / (2.0 * O_PI * M_s);
 }
 
-static void walker_scalars(const double *p, double out[8])
+/* ic_lso: the row gives e, Phi, gamma~, alpha at the LSO and nu0 is unused */
+static void walker_scalars(const double *p, int ic_lso, double out[8])
 {
     memset(out, 0, 8 * sizeof(double));
     for (int i = 0; i < NPAR; ++i)
@@ -181,11 +182,11 @@ static void walker_scalars(const double *p, double out[8])
     double M = p[I_M], mu = p[I_MU], a = p[I_A], e0 = p[I_E0], nu0 = p[I_NU0];
     double dl = p[I_DL], at = p[I_AT], cl = p[I_CLAM];
     int ok = (mu > 0.0) && (mu < M) && (a >= 0.0) && (a <= 1.0) && (e0 >= 0.0) &&
-             (e0 < 1.0) && (nu0 > 0.0) && (dl > 0.0) && (at > -1.0) && (cl >= -1.0) &&
+             (e0 < 1.0) && (ic_lso || nu0 > 0.0) && (dl > 0.0) && (at > -1.0) && (cl >= -1.0) &&
              (cl <= 1.0);
     if (!ok) return;
     double M_s = M * O_TSUN;
-    if (!(nu0 < nu_lso(M_s, e0))) return;
+    if (!ic_lso && !(nu0 < nu_lso(M_s, e0))) return;
     double D = dl * 1e9 * O_PARSEC / O_CLIGHT;
     double z = oracle_z_of_dl(D);
     /* Eq. (6) */
@@ -209,7 +210,7 @@ static void walker_scalars(const double *p, double out[8])
 
 int oracle_scalars(const double *params, int64_t B, double *out)
 {
-    for (int64_t w = 0; w < B; ++w) walker_scalars(params + w * NPAR, out + w * 8);
+    for (int64_t w = 0; w < B; ++w) walker_scalars(params + w * NPAR, 0, out + w * 8);
     return 0;
 }
 
@@ -282,8 +283,50 @@ static int node_ok(const double y[5], double M_s)
 /* Classical RK4 on t_k = k h, h = dt 2^coarse_log2 (reading R3).
  * orb[(K+1)][10]: Y_k then f(Y_k).  Returns K_w, the index of the last node
  * before the LSO (reading R5); nodes after it are zero. */
+/* a finite state with 0 <= e < 1 and nu > 0 (the backward integration has
+ * no LSO to stop at) */
+static int node_sane(const double y[5])
+{
+    for (int i = 0; i < 5; ++i)
+        if (!isfinite(y[i])) return 0;
+    return y[3] >= 0.0 && y[3] < 1.0 && y[1] > 0.0;
+}
+
+/* The paper's convention (Sec. 3 "Waveform computation"): the state is given
+ * at the last stable orbit, nu = nu_LSO(e_LSO), and the orbit is integrated
+ * backward over the window.  Reading: the LSO is node K (the end of the last
+ * coarse interval covering the window); classical RK4 with step -h fills
+ * nodes K-1 .. 0.  Returns K, or -1 if the state leaves the physical range
+ * on the way back. */
+static int64_t walker_orbit_lso(const double *p, const oracle_cfg *c, double *orb)
+{
+    int64_t K = n_intervals_of(c);
+    double h = -c->dt * (double)((int64_t)1 << c->coarse_log2);
+    double M_s = p[I_M] * O_TSUN, mu_s = p[I_MU] * O_TSUN, a = p[I_A], cl = p[I_CLAM];
+    memset(orb, 0, (size_t)(K + 1) * 10 * sizeof(double));
+    double y[5] = {p[I_PHI0], nu_lso(M_s, p[I_E0]), p[I_GT0], p[I_E0], p[I_AL0]};
+    double k1[5], k2[5], k3[5], k4[5], yt[5];
+    ak_rhs(y, M_s, mu_s, a, cl, c->lo_only, k1);
+    for (int i = 0; i < 5; ++i) { orb[K * 10 + i] = y[i]; orb[K * 10 + 5 + i] = k1[i]; }
+    for (int64_t k = K; k > 0; --k) {
+        for (int i = 0; i < 5; ++i) yt[i] = y[i] + 0.5 * h * k1[i];
+        ak_rhs(yt, M_s, mu_s, a, cl, c->lo_only, k2);
+        for (int i = 0; i < 5; ++i) yt[i] = y[i] + 0.5 * h * k2[i];
+        ak_rhs(yt, M_s, mu_s, a, cl, c->lo_only, k3);
+        for (int i = 0; i < 5; ++i) yt[i] = y[i] + h * k3[i];
+        ak_rhs(yt, M_s, mu_s, a, cl, c->lo_only, k4);
+        for (int i = 0; i < 5; ++i) y[i] = y[i] + h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+        if (!node_sane(y)) return -1;
+        ak_rhs(y, M_s, mu_s, a, cl, c->lo_only, k1);
+        double *o = orb + (k - 1) * 10;
+        for (int i = 0; i < 5; ++i) { o[i] = y[i]; o[5 + i] = k1[i]; }
+    }
+    return K;
+}
+
 static int64_t walker_orbit(const double *p, const oracle_cfg *c, double *orb)
 {
+    if (c->ic_lso) return walker_orbit_lso(p, c, orb);
     int64_t K = n_intervals_of(c);
     double h = c->dt * (double)((int64_t)1 << c->coarse_log2);
     double M_s = p[I_M] * O_TSUN, mu_s = p[I_MU] * O_TSUN, a = p[I_A], cl = p[I_CLAM];
@@ -314,7 +357,7 @@ int oracle_orbit(const double *params, int64_t B, const oracle_cfg *c, double *o
     int64_t K = n_intervals_of(c);
     for (int64_t w = 0; w < B; ++w) {
         double s[8];
-        walker_scalars(params + w * NPAR, s);
+        walker_scalars(params + w * NPAR, c->ic_lso, s);
         double *o = orb + w * (K + 1) * 10;
         if (s[0] == 0.0) {
             memset(o, 0, (size_t)(K + 1) * 10 * sizeof(double));
@@ -546,12 +589,13 @@ int oracle_waveform(const double *params, int64_t B, const oracle_cfg *c, double
     for (int64_t w = 0; w < B; ++w) {
         double s[8];
         const double *p = params + w * NPAR;
-        walker_scalars(p, s);
+        walker_scalars(p, c->ic_lso, s);
         double *xw = x + w * 2 * c->N;
         if (s[0] == 0.0) { memset(xw, 0, (size_t)(2 * c->N) * sizeof(double)); continue; }
         double *orb = (double *)malloc((size_t)(K + 1) * 10 * sizeof(double));
         int64_t Kw = walker_orbit(p, c, orb);
-        walker_waveform(p, c, orb, Kw, xw, NULL);
+        if (Kw >= 0) walker_waveform(p, c, orb, Kw, xw, NULL);
+        else memset(xw, 0, (size_t)(2 * c->N) * sizeof(double));
         free(orb);
     }
     return 0;
@@ -562,11 +606,12 @@ int oracle_waveform_diag(const double *p, const oracle_cfg *c, double *x, double
 {
     if (!cfg_ok(c)) return -1;
     double s[8];
-    walker_scalars(p, s);
+    walker_scalars(p, c->ic_lso, s);
     if (s[0] == 0.0) return -2;
     int64_t K = n_intervals_of(c);
     double *orb = (double *)malloc((size_t)(K + 1) * 10 * sizeof(double));
     int64_t Kw = walker_orbit(p, c, orb);
+    if (Kw < 0) { free(orb); return -2; }
     walker_waveform(p, c, orb, Kw, x, diag);
     free(orb);
     return 0;
@@ -661,11 +706,12 @@ static double walker_loglike(const double *p, const double *data, const double *
                              const oracle_cfg *c, double *scratch_x, double *scratch_X)
 {
     double s[8];
-    walker_scalars(p, s);
+    walker_scalars(p, c->ic_lso, s);
     if (s[0] == 0.0) return -INFINITY;
     int64_t N = c->N, K = n_intervals_of(c), H = N / 2 + 1;
     double *orb = (double *)malloc((size_t)(K + 1) * 10 * sizeof(double));
     int64_t Kw = walker_orbit(p, c, orb);
+    if (Kw < 0) { free(orb); return -INFINITY; }   /* left the physical range backward */
     walker_waveform(p, c, orb, Kw, scratch_x, NULL);
     free(orb);
     /* FFT both channels */
@@ -717,11 +763,12 @@ static double walker_loglike_fmg(const double *p, const double *coef, int P, dou
                                  double *scratch_x, double *scratch_X)
 {
     double s[8];
-    walker_scalars(p, s);
+    walker_scalars(p, c->ic_lso, s);
     if (s[0] == 0.0) return -INFINITY;
     int64_t N = c->N, K = n_intervals_of(c), H = N / 2 + 1;
     double *orb = (double *)malloc((size_t)(K + 1) * 10 * sizeof(double));
     int64_t Kw = walker_orbit(p, c, orb);
+    if (Kw < 0) { free(orb); return -INFINITY; }   /* left the physical range backward */
     walker_waveform(p, c, orb, Kw, scratch_x, NULL);
     free(orb);
     for (int ch = 0; ch < 2; ++ch) {
@@ -871,7 +918,7 @@ int oracle_make_data(const double *hinj, const double *pinj, const double *psd,
                      const double *gauss, int64_t N, double dt, double *data)
 {
     double s[8];
-    walker_scalars(pinj, s);
+    walker_scalars(pinj, 0, s);
     if (s[0] == 0.0) return -2;
     int64_t H = N / 2 + 1;
     double g = s[5];

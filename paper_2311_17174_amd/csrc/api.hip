@@ -115,12 +115,16 @@ emri_status make_plan(const emri_cfg* cfg, int64_t B, Plan* p, const char** err)
         *err = "coarse_log2 must be in [8, 12]";
         return EMRI_EUNSUPPORTED;
     }
-    if (cfg->reserved != 0) { *err = "reserved must be 0"; return EMRI_EINVAL; }
+    if (cfg->ic != EMRI_IC_START && cfg->ic != EMRI_IC_LSO) {
+        *err = "ic must be EMRI_IC_START or EMRI_IC_LSO";
+        return EMRI_EINVAL;
+    }
     if (B < 0) { *err = "B must be >= 0"; return EMRI_EINVAL; }
 
     Plan& q = *p;
     memset(&q, 0, sizeof q);
     q.T_obs = cfg->T_obs;
+    q.ic = cfg->ic;
     q.dt = cfg->dt;
     q.N = cfg->N;
     q.Nv = Nv;
@@ -232,6 +236,9 @@ static emri_status get_pipe(hipStream_t s, Pipe** out)
 // (EMRI_ORBIT_SEGMENTS overrides, 1 .. 16, for tuning and tests)
 static int orbit_segments(const Plan& p)
 {
+    // from the LSO the orbit is integrated backward: its first segment would
+    // hold the last intervals, so it runs as one segment
+    if (p.ic == EMRI_IC_LSO) return 1;
     int64_t S = p.K / 384;
     if (const char* env = getenv("EMRI_ORBIT_SEGMENTS")) S = atoi(env);
     else if (S > 8) S = 8;

@@ -74,6 +74,7 @@ struct Plan {
     int nh;                // harmonics
     int prec;              // emri_precision
     int cl;                // coarse_log2
+    int ic;                // emri_cfg.ic: initial conditions at t = 0 or at the LSO
     int64_t L;             // samples per coarse interval, 2^cl
     int64_t K;             // coarse intervals covering N_valid
     // FFT: N = R1 * R2; pass A: R2-point column FFTs (stride R1), T per WG;

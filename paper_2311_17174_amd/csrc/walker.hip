@@ -136,12 +136,40 @@ __device__ __forceinline__ int64_t rk4_steps(double& Y0, double& Y1, double& Y2,
     return k1;
 }
 
+// From the LSO backward: RK4 steps with -h from the state Y at node K (f its
+// derivative) down to node 0, writing nodes K-1 .. 0.  false if the state
+// leaves the physical range (finite, 0 <= e < 1, nu > 0) on the way.
+__device__ __forceinline__ bool rk4_back(double Y0, double Y1, double Y2, double Y3, double Y4,
+                                         Rhs f, int64_t K, double h, double Ms, double mus,
+                                         double a, double cl, double* __restrict__ o)
+{
+    const double hb = -h, hh = 0.5 * hb, h6 = hb / 6.0;
+    for (int64_t k = K; k > 0; --k) {
+        const Rhs k2 = ak_rhs(Y1 + hh * f.dnu, Y3 + hh * f.de, Ms, mus, a, cl);
+        const Rhs k3 = ak_rhs(Y1 + hh * k2.dnu, Y3 + hh * k2.de, Ms, mus, a, cl);
+        const Rhs k4 = ak_rhs(Y1 + hb * k3.dnu, Y3 + hb * k3.de, Ms, mus, a, cl);
+        Y0 += h6 * (f.dPhi + 2.0 * k2.dPhi + 2.0 * k3.dPhi + k4.dPhi);
+        Y1 += h6 * (f.dnu + 2.0 * k2.dnu + 2.0 * k3.dnu + k4.dnu);
+        Y2 += h6 * (f.dgt + 2.0 * k2.dgt + 2.0 * k3.dgt + k4.dgt);
+        Y3 += h6 * (f.de + 2.0 * k2.de + 2.0 * k3.de + k4.de);
+        Y4 += h6 * (f.dal + 2.0 * k2.dal + 2.0 * k3.dal + k4.dal);
+        if (!(isfinite(Y0) && isfinite(Y1) && isfinite(Y2) && isfinite(Y3) && isfinite(Y4) &&
+              Y3 >= 0.0 && Y3 < 1.0 && Y1 > 0.0))
+            return false;
+        f = ak_rhs(Y1, Y3, Ms, mus, a, cl);
+        double* q = o + (k - 1) * 10;
+        q[0] = Y0; q[1] = Y1; q[2] = Y2; q[3] = Y3; q[4] = Y4;
+        q[5] = f.dPhi; q[6] = f.dnu; q[7] = f.dgt; q[8] = f.de; q[9] = f.dal;
+    }
+    return true;
+}
+
 // The orbit kernels run one lane per walker, a few waves for the whole batch,
 // beside the table and synthesis kernels of earlier segments: they raise
 // their waves' issue priority so those do not stretch the integration.
 __global__ void __launch_bounds__(64) k_walker_setup(const double* __restrict__ params, int64_t B,
                                                      int64_t K, double h, double Ndt, GL8 gl,
-                                                     int64_t k1, double* __restrict__ wc,
+                                                     int64_t k1, int ic, double* __restrict__ wc,
                                                      double* __restrict__ orb)
 {
     __builtin_amdgcn_s_setprio(3);
@@ -156,11 +184,12 @@ __global__ void __launch_bounds__(64) k_walker_setup(const double* __restrict__ 
     for (int i = 0; i < EMRI_NPAR; ++i) ok = ok && isfinite(p[i]);
     const double M = p[0], mu = p[1], a = p[2], e0 = p[3], nu0 = p[4];
     const double cl = p[8], dl = p[13], xi0 = p[14], nxi = p[15], at = p[16];
+    const bool lso = ic == EMRI_IC_LSO;
     ok = ok && mu > 0.0 && mu < M && a >= 0.0 && a <= 1.0 && e0 >= 0.0 && e0 < 1.0 &&
-         nu0 > 0.0 && dl > 0.0 && at > -1.0 && cl >= -1.0 && cl <= 1.0;
+         (lso || nu0 > 0.0) && dl > 0.0 && at > -1.0 && cl >= -1.0 && cl <= 1.0;
     const double Ms = M * kSunSeconds, mus = mu * kSunSeconds;
     double x13_0;
-    ok = ok && before_lso(p[5], nu0, p[6], e0, p[7], Ms, &x13_0);
+    ok = ok && (lso || before_lso(p[5], nu0, p[6], e0, p[7], Ms, &x13_0));
     if (!ok) return;
 
     // distance, redshift, Eq. (6), delay, overall factor
@@ -208,9 +237,23 @@ __global__ void __launch_bounds__(64) k_walker_setup(const double* __restrict__ 
     c[WC_HASDT] = (dT != 0.0) ? 1.0 : 0.0;
     c[WC_AT] = at;
 
+    double* o = orb + w * (K + 1) * 10;
+    if (lso) {
+        // nu_LSO(e) = ((1 - e^2)/(6 + 2e))^{3/2} / (2 pi M) at node K, then backward
+        const double r = (1.0 - e0) * (1.0 + e0) / (6.0 + 2.0 * e0);
+        const double nuL = r * sqrt(r) / (2.0 * kPi * Ms);
+        const Rhs f = ak_rhs(nuL, e0, Ms, mus, a, cl);
+        double* q = o + K * 10;
+        q[0] = p[5]; q[1] = nuL; q[2] = p[6]; q[3] = e0; q[4] = p[7];
+        q[5] = f.dPhi; q[6] = f.dnu; q[7] = f.dgt; q[8] = f.de; q[9] = f.dal;
+        if (!rk4_back(p[5], nuL, p[6], e0, p[7], f, K, h, Ms, mus, a, cl, o)) return;
+        c[WC_KSEG] = (double)K;
+        c[WC_KW] = (double)K;
+        c[WC_VALID] = 1.0;
+        return;
+    }
     // orbit: classical RK4, nodes t_k = k h
     double Y0 = p[5], Y1 = nu0, Y2 = p[6], Y3 = e0, Y4 = p[7];
-    double* o = orb + w * (K + 1) * 10;
     Rhs f = ak_rhs(Y1, Y3, Ms, mus, a, cl);
     o[0] = Y0; o[1] = Y1; o[2] = Y2; o[3] = Y3; o[4] = Y4;
     o[5] = f.dPhi; o[6] = f.dnu; o[7] = f.dgt; o[8] = f.de; o[9] = f.dal;
@@ -467,8 +510,9 @@ hipError_t launch_walker_setup(const Plan& p, const double* params, int64_t B, v
     const double h = p.dt * (double)p.L;
     dim3 grid((unsigned)((B + 63) / 64));
     trace_mark(ST_SETUP, s, true);
+    if (p.ic == EMRI_IC_LSO && k1 != p.K) return hipErrorInvalidValue;   // one segment only
     hipLaunchKernelGGL(k_walker_setup, grid, dim3(64), 0, s, params, B, p.K, h,
-                       (double)p.N * p.dt, gl, k1, (double*)(base + p.off_wc),
+                       (double)p.N * p.dt, gl, k1, p.ic, (double*)(base + p.off_wc),
                        (double*)(base + p.off_orb));
     trace_mark(ST_SETUP, s, false);
     return hipGetLastError();

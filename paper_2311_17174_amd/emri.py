@@ -20,6 +20,8 @@ NPAR = 17
 FP64 = 0
 MIXED = 1
 PRECISIONS = {"fp64": FP64, "mixed": MIXED}
+IC_START = 0     # initial conditions at t = 0
+IC_LSO = 1       # at the last stable orbit, integrated backward (the paper's convention)
 
 EXPORTED = ("emri_abi_version", "emri_last_error", "emri_workspace_bytes",
             "emri_waveform_batch", "emri_fft_batch", "emri_loglike_batch",
@@ -38,7 +40,7 @@ class EmriError(RuntimeError):
 class _Cfg(ctypes.Structure):
     _fields_ = [("T_obs", ctypes.c_double), ("dt", ctypes.c_double), ("N", ctypes.c_int64),
                 ("n_harm", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("coarse_log2", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("coarse_log2", ctypes.c_int32), ("ic", ctypes.c_int32)]
 
 
 class _Prior(ctypes.Structure):
@@ -71,14 +73,16 @@ class Config:
     n_harm: int
     precision: int = FP64
     coarse_log2: int = 10
+    ic: int = IC_START       # IC_LSO: the row's orbital state is at the LSO
 
     @staticmethod
     def from_workload(w) -> "Config":
-        return Config(w.T_obs, w.dt, w.N, w.n_harm, PRECISIONS[w.precision], w.coarse_log2)
+        return Config(w.T_obs, w.dt, w.N, w.n_harm, PRECISIONS[w.precision], w.coarse_log2,
+                      w.ic)
 
     def c(self) -> _Cfg:
         return _Cfg(float(self.T_obs), float(self.dt), int(self.N), int(self.n_harm),
-                    int(self.precision), int(self.coarse_log2), 0)
+                    int(self.precision), int(self.coarse_log2), int(self.ic))
 
     @property
     def real_dtype(self) -> torch.dtype:

@@ -56,6 +56,7 @@ class Workload:
     inj: np.ndarray = field(compare=False, repr=False, default=None)
     walker_seed: int = 0
     noise_seed: int = 1
+    ic: int = 0                       # 1: the orbital state of a row is at the LSO
 
     @property
     def n_valid(self) -> int:

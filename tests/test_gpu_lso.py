@@ -1,0 +1,70 @@
+"""GPU parity of the LSO convention for initial conditions (Sec. 3
+"Waveform computation": state at the last stable orbit, orbit integrated
+backward) through the C ABI, against the CPU oracle.  Tolerances as for the
+t = 0 convention."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2311_17174_amd import workloads as W
+from tests.gpu_common import EPS64, max_phase, ocfg, oracle_dataset, say, to_device_data
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_2311_17174_amd import emri
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return emri
+
+
+def lso_walkers(w):
+    P = list(W.walkers(w, B=4))
+    p = W.injection(M=1e5, e0=0.8); P.append(p)            # fast: e 0.81 -> 0.80 over the window
+    p = w.inj.copy(); p[4] = -1.0; P.append(p)              # nu0 is unused at the LSO
+    p = W.injection(M=2e4, mu=10.0, e0=0.7); P.append(p)    # backward history leaves the range
+    return np.array(P)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_lso_waveform_parity(E, prec):
+    w = W.small(prec, n_harm=6).with_(ic=1)
+    P = lso_walkers(w)
+    orb, kw = O.orbit(P, ocfg(w))
+    say("LSO nodes", kw)
+    assert list(kw[:6]) == [w.n_intervals] * 6 and kw[6] == -1
+    cfg = E.Config.from_workload(w)
+    got = E.waveform_batch(torch.from_numpy(P).cuda(), cfg).cpu().numpy().astype(np.float64)
+    got = got.transpose(0, 2, 1)
+    ref = O.waveform(P, ocfg(w))
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(got - ref), axis=(1, 2)) / scale
+    say("max rel err per walker", err)
+    tol = 64 * w.n_harm * max_phase(w, P[:6]) * EPS64 if prec == "fp64" else 2e-5
+    assert np.all(err <= tol), (err, tol)
+    assert np.all(got[6] == 0.0)
+    assert np.array_equal(got[5], got[0])                 # only the unused nu0 differs
+    # the same row under the t = 0 convention is a different signal
+    cfg0 = E.Config.from_workload(w.with_(ic=0))
+    g0 = E.waveform_batch(torch.from_numpy(P[:1]).cuda(), cfg0).cpu().numpy()
+    assert np.max(np.abs(g0[0].T - got[0])) > 0.1 * scale
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_lso_loglike_parity(E, prec):
+    w = W.small(prec, n_harm=6).with_(ic=1)
+    P = lso_walkers(w)
+    d, S = oracle_dataset(w, True)
+    ref = O.loglike(P, d, S, ocfg(w))
+    cfg = E.Config.from_workload(w)
+    dd, ss = to_device_data(d, S)
+    got = E.loglike_batch(torch.from_numpy(P).cuda(), dd, ss, cfg).cpu().numpy()
+    say("lnL ref", ref, "got", got)
+    fin = np.isfinite(ref)
+    assert list(np.where(~fin)[0]) == [6]
+    assert np.array_equal(fin, np.isfinite(got)) and got[6] == -np.inf
+    rel = np.abs(got[fin] - ref[fin]) / np.abs(ref[fin])
+    assert np.all(rel <= (1e-10 if prec == "fp64" else 1e-4)), rel

@@ -165,6 +165,7 @@ emri_status make_plan(const emri_cfg* cfg, int64_t B, Plan* p, const char** err)
     q.off_orb = o; o += align256((size_t)B * (q.K + 1) * 10 * 8);
     q.off_nv = o; o += align256((size_t)B * (q.K + 1) * q.nh * 6 * 8);
     q.off_co = o; o += align256((size_t)B * q.K * 16 * 8);
+    q.off_az = o; o += align256((size_t)q.K * 16);
     q.off_ch = o; o += align256((size_t)B * q.K * q.nh * 12 * q.hsz);
     q.off_z = o; o += align256((size_t)B * q.N * q.esz);
     q.off_part = o; o += align256((size_t)B * q.R2 * 8);
@@ -264,6 +265,7 @@ static emri_status run_waveforms(const Plan& p, const double* params, int64_t B,
         return p.K * (int64_t)(1 + 4 * (i - 1)) / (int64_t)(1 + 4 * (S - 1));
     };
     emri_status st;
+    if ((st = check_launch(launch_azimuth(p, ws, s), "azimuth table"))) return st;
     if (S == 1) {
         if ((st = check_launch(launch_walker_setup(p, params, B, ws, p.K, s), "walker setup")))
             return st;

@@ -86,7 +86,7 @@ struct Plan {
     size_t hsz;            // bytes per harmonic coefficient (8 or 4)
     // workspace (bytes, for B walkers)
     int64_t B;
-    size_t off_tw, off_wc, off_orb, off_nv, off_co, off_ch, off_z, off_part, total;
+    size_t off_tw, off_wc, off_orb, off_nv, off_co, off_az, off_ch, off_z, off_part, total;
     // dataset buffer
     size_t ds_off_d, ds_off_w, ds_off_norm, ds_off_npart, ds_total;
 };
@@ -127,6 +127,8 @@ hipError_t launch_tables(const Plan& p, int64_t B, void* ws, int64_t k0, int64_t
 hipError_t launch_synth(const Plan& p, int64_t B, void* ws, void* out, int64_t k0, int64_t k1,
                         int seg, bool zfill, hipStream_t s);
 hipError_t launch_twiddles(const Plan& p, void* ws, hipStream_t s);
+// detector azimuth at the start of each coarse interval (read by the synthesis)
+hipError_t launch_azimuth(const Plan& p, void* ws, hipStream_t s);
 // ensemble sampler step (sampler.hip); the prior box by value
 struct PriorBox {
     int32_t D;

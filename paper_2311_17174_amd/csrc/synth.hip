@@ -53,6 +53,23 @@ template <typename R> struct Degenerate;
 template <> struct Degenerate<double> { static constexpr double v = 1e-24; };
 template <> struct Degenerate<float> { static constexpr float v = 1e-10f; };
 
+// 1/x for the normalisation of the tangent pairs (x is a product of squared
+// norms in [1e-72, 1e3]): the hardware reciprocal refined by Newton steps,
+// two in FP64 (from about 2^-29 to full precision), one in FP32
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 // sin/cos of an FP64 angle in precision R: FP64 uses the library sincos;
 // FP32 reduces the angle modulo 2 pi in FP64 first.
 __device__ inline void angle_sincos(double a, double* s, double* c) { sincos(a, s, c); }
@@ -94,6 +111,7 @@ k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
                                                double dt, const double* __restrict__ wc,
                                                const double* __restrict__ co,
                                                const HT* __restrict__ ch,
+                                               const double2* __restrict__ az,
                                                typename V2<R>::T* __restrict__ out)
 {
     using R2 = typename V2<R>::T;
@@ -118,8 +136,8 @@ k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
     const double* q = co + (w * K + k) * 16;
     const double dop = c[WC_DOP];
     const double cps = c[WC_CPS], sps = c[WC_SPS];
-    double sb0, cb0;                                   // detector azimuth at j0
-    sincospi(2.0 * (double)j0 * dt / kYearSeconds, &sb0, &cb0);
+    const double2 a0 = az[k];                          // detector azimuth at j0
+    const double cb0 = a0.x, sb0 = a0.y;
     const double dphi = 2.0 * kPi * dt / kYearSeconds;   // per sample
     const double invL = 1.0 / (double)L;
     // largest per-sample step of Phi' (plus a Doppler margin), 2 gamma~, alpha
@@ -268,7 +286,7 @@ k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
         if (!okb) nb = R(1);
         if (!okd) nd = R(1);
         if (!okp) np = R(1);
-        const R inv = R(1) / (nb * nd * np);
+        const R inv = recip(nb * nd * np);
         const R ib = nd * np * inv, idd = nb * np * inv, ip = nb * nd * inv;
         const R c2b = okb ? (bx * bx - by * by) * ib : R(1);
         const R s2b = okb ? R(2) * bx * by * ib : R(0);
@@ -303,10 +321,11 @@ static hipError_t synth_dispatch(const Plan& p, int64_t B, const char* base, voi
     const double* wc = (const double*)(base + p.off_wc);
     const double* co = (const double*)(base + p.off_co);
     const HT* ch = (const HT*)(base + p.off_ch);
+    const double2* az = (const double2*)(base + p.off_az);
     R2* o = (R2*)out;
 #define EMRI_SYNTH(SPT)                                                                        \
     hipLaunchKernelGGL((k_synth<R, HT, SPT>), grid, dim3(256), 0, s, p.K, p.Nv, p.N, p.nh, k0, \
-                       seg, zfill, p.dt, wc, co, ch, o)
+                       seg, zfill, p.dt, wc, co, ch, az, o)
     switch (p.cl) {
     case 8: EMRI_SYNTH(1); break;
     case 9: EMRI_SYNTH(2); break;
@@ -333,6 +352,26 @@ hipError_t launch_synth(const Plan& p, int64_t B, void* ws, void* out, int64_t k
             : synth_dispatch<float, float>(p, B, base, out, k0, k1, seg, zfill ? 1 : 0, s);
     trace_mark(ST_SYNTH, s, false);
     return e;
+}
+
+// detector azimuth phibar = 2 pi t / yr at the first sample of each coarse
+// interval: az[k] = (cos, sin) of it, shared by all walkers of a batch
+__global__ void __launch_bounds__(256) k_azimuth(int64_t K, int64_t L, double dt,
+                                                 double2* __restrict__ az)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    double s, c;
+    sincospi(2.0 * (double)(k * L) * dt / kYearSeconds, &s, &c);
+    az[k] = double2{c, s};
+}
+
+hipError_t launch_azimuth(const Plan& p, void* ws, hipStream_t s)
+{
+    double2* az = (double2*)((char*)ws + p.off_az);
+    hipLaunchKernelGGL(k_azimuth, dim3((unsigned)((p.K + 255) / 256)), dim3(256), 0, s, p.K, p.L,
+                       p.dt, az);
+    return hipGetLastError();
 }
 
 }  // namespace emri

@@ -21,7 +21,9 @@
  *    keeps per (device, caller stream), created on the first call; it is
  *    forked from and joined back into `stream` by events within the call
  *    (also under stream capture), so `stream` alone orders the call.  The
- *    auxiliary streams are the only resources the library keeps.
+ *    auxiliary streams are the only resources the library keeps.  Calls on
+ *    one stream must come from one host thread at a time (as for any
+ *    stream); calls on different streams may run concurrently.
  *  - Call-level errors (null pointer, bad configuration, workspace too
  *    small, launch failure) return a negative status and launch nothing new;
  *    emri_last_error() then describes the error (per host thread).
@@ -36,6 +38,8 @@
  *      13 d_L [Gpc] > 0   14 Xi0   15 n (Eq. (6))
  *      16 alpha_T > -1: constant GW-speed parameter, c_T^2 = 1 + alpha_T
  *         (Eq. (3)); 0 is General Relativity.
+ *    With cfg->ic = EMRI_IC_LSO, entries 3, 5, 6, 7 are the state at the
+ *    last stable orbit and entry 4 is unused (see emri_cfg).
  *    The first three entries are the masses and spin, as in the paper's
  *    parameter-vector convention (Sec. 3).  The state Y = (Phi, nu, gamma~,
  *    e, alpha) of Eq. (1) starts at t = 0 from entries 3..7.

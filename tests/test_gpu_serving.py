@@ -101,6 +101,28 @@ def test_served_matches_oracle(E):
     assert np.all(np.abs(got - ref) / np.abs(ref) <= 1e-4)
 
 
+def test_served_lso_dataset(E):
+    """A data set in the LSO convention (orbits integrated backward from the
+    last stable orbit) served eagerly, captured and replayed: bitwise the
+    same walkers evaluated alone, and those agree with the oracle (FP64)."""
+    w = W.small("fp64", n_harm=6).with_(ic=1)
+    d, S = oracle_dataset(w, True)
+    dd, ss = to_device_data(d, S)
+    cfg = E.Config.from_workload(w)
+    P = W.walkers(w, B=9, seed=5)
+    ref = O.loglike(P, d, S, ocfg(w))
+    expect = alone(E, cfg, dd, ss, P)
+    assert np.all(np.abs(expect - ref) <= 1e-10 * np.abs(ref))
+    arena = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    with E.Server(arena, n_streams=1, max_batch=16, use_graphs=True) as srv:
+        i = srv.add_dataset(dd, ss, cfg)
+        for _ in range(3):                          # eager, captured, replayed
+            got, _ = srv.wait(srv.submit(i, P), timeout=120.0)
+            assert np.array_equal(got, expect)
+        st = srv.stats()
+    assert st["graph_launches"] >= 1
+
+
 def test_admission_by_footprint(E):
     """An arena that holds one batch block at a time still serves every
     request (admission waits for memory); a request larger than the budget is

@@ -114,7 +114,7 @@ def test_served_lso_dataset(E):
     expect = alone(E, cfg, dd, ss, P)
     assert np.all(np.abs(expect - ref) <= 1e-10 * np.abs(ref))
     arena = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
-    with E.Server(arena, n_streams=1, max_batch=16, use_graphs=True) as srv:
+    with E.Server(arena, n_streams=1, max_batch=32, use_graphs=True) as srv:
         i = srv.add_dataset(dd, ss, cfg)
         for _ in range(3):                          # eager, captured, replayed
             got, _ = srv.wait(srv.submit(i, P), timeout=120.0)

@@ -86,6 +86,27 @@ def profiled_traffic(stage: str):
     return rec["traffic_bytes"]
 
 
+def plain_copy_gbs(gib: int = 4, reps: int = 5) -> float:
+    """Read + write rate of a plain device-to-device copy of `gib` GiB (HIP
+    events), the practical HBM ceiling next to the 8 TB/s peak."""
+    import torch
+    n = (gib << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * (gib << 30) / (ms * 1e-3) / 1e9
+
+
 def run_path(E, W, w, P, data, psd, steps, warmup):
     import torch
     cfg = E.Config.from_workload(w)
@@ -369,7 +390,7 @@ def run_serving(E, W, n_burst: int, n_requests: int, arena_gib: float, n_streams
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
@@ -529,6 +550,12 @@ def main():
                 "traffic": profiled_traffic(dom)}
     roof["ms_per_launch"] = dms
     roof["launches_per_step"] = st64[dom][1] / args.steps
+    # the HBM-bound stages against a plain copy measured on the same device
+    copy = plain_copy_gbs()
+    roof["plain_copy_gbs"] = copy
+    for ent in stages_out.values():
+        if "achieved_gbs" in ent:
+            ent["frac_of_plain_copy"] = ent["achieved_gbs"] / copy
 
     cpu = None
     if not args.no_cpu_baseline:

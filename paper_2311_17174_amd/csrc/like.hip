@@ -289,9 +289,12 @@ __device__ __forceinline__ auto walker_prop(const double* c, int64_t w, int64_t 
 // together on one XCD (see the mapping below), so they hit that XCD's L2.
 // One FP64 partial per (g, walker).  Register budget 128 (4 waves per SIMD,
 // two workgroups per CU): occupancy matters more here than the few spills
-// it costs the FP64 variant.
+// it costs the FP64 variant.  The frequency-dependent propagation keeps its
+// per-bin series and transcendentals live as well: at 128 registers it
+// spills heavily, so it takes 256 (one workgroup per CU, no spills), which
+// measured 13.8 ms against 18.5 ms at config 2.
 template <typename R, bool MIXED, int MAXT, bool FMG>
-__global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(FMG ? 2 : 4)))
 k_rows_like(const typename C2<R>::T* __restrict__ z,
                                                     int64_t N, int L, int lgL, int64_t R2,
                                                     double dt, const double* __restrict__ wc,
@@ -424,9 +427,12 @@ k_rows_like(const typename C2<R>::T* __restrict__ z,
 // holds positions p = t + slot_pos16(s) L/16; it owns (A, p) for p < L/2 and
 // (B, L-1-p) for p >= L/2 (only p < L/2 in a self-paired row).  Register
 // budget 128 (4 waves per SIMD, four workgroups per CU): faster than the
-// spill-free 156 registers at three.
+// spill-free 156 registers at three.  With the frequency-dependent
+// propagation the balance turns: 168 registers at three waves (13 spills
+// instead of 76) measured 6.3 ms against 10.6 ms at config 2 (and 7.6 ms at
+// two waves without spills).
 template <typename R, bool MIXED, int MAXT, bool FMG>
-__global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(FMG ? 3 : 4)))
 k_rows_like16(const typename C2<R>::T* __restrict__ z, int64_t N, int L, int lgL, int64_t R2,
               double dt, const double* __restrict__ wc, const void* __restrict__ dsd,
               const void* __restrict__ dsw, const typename C2<R>::T* __restrict__ twL,

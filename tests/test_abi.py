@@ -101,3 +101,22 @@ def test_call_errors_without_launch(E):
     rc = E.lib.emri_waveform_batch(ctypes.c_void_p(8), 4, ctypes.byref(cc), ctypes.c_void_p(8),
                                    ctypes.c_void_p(8), 16, None)
     assert rc == -2
+
+
+def test_workspace_sizes_are_consistent(E):
+    """Host-side sizing (no GPU): the workspace grows with the batch and by
+    at least the signal per walker; the sampler's adds the proposals'
+    staging to a whole batch of W; the data set does not depend on B."""
+    c = E.Config(T_obs=2.5 * 86400, dt=10.0, N=1 << 15, n_harm=8)
+    sizes = [E.workspace_bytes(c, b) for b in (1, 2, 8, 64)]
+    assert all(b > a for a, b in zip(sizes, sizes[1:]))
+    per = (sizes[3] - sizes[2]) / 56
+    assert per >= c.N * 16                          # the complex FP64 signal
+    assert E.sampler_workspace_bytes(c, 8) >= E.workspace_bytes(c, 8) + 8 * 17 * 8 + 3 * 8 * 8
+    mixed = E.Config(T_obs=2.5 * 86400, dt=10.0, N=1 << 15, n_harm=8, precision=E.MIXED)
+    assert E.workspace_bytes(mixed, 64) < E.workspace_bytes(c, 64)
+    assert E.dataset_bytes(mixed) < E.dataset_bytes(c)
+    lso = E.Config(T_obs=2.5 * 86400, dt=10.0, N=1 << 15, n_harm=8, ic=E.IC_LSO)
+    assert E.workspace_bytes(lso, 8) == E.workspace_bytes(c, 8)
+    bad = E.Config(T_obs=2.5 * 86400, dt=10.0, N=1 << 15, n_harm=8, ic=2)
+    assert E.lib.emri_workspace_bytes(ctypes.byref(bad.c()), 4) == 0

@@ -108,3 +108,17 @@ def test_fmg_order_zero_chunks_and_errors(E):
         with pytest.raises(E.EmriError) as ei:
             E.loglike_dataset_fmg(Pd, c9, fs, ds, cfg, order=order)
         assert ei.value.status == EINVAL
+
+
+def test_fmg_with_lso_convention(E):
+    """Both extensions at once: orbits from the LSO backward and the
+    frequency-dependent propagation, FP64, against the oracle."""
+    w, P, C = fmg_case("fp64")
+    w = w.with_(ic=1)
+    d, S = oracle_dataset(w, True)
+    ref = O.loglike_fmg(P, C, F_STAR, d, S, ocfg(w))
+    got, _, _ = run(E, w, P, C, d, S)
+    fin = np.isfinite(ref)
+    say("LSO + fmg ref", ref, "got", got)
+    assert np.array_equal(fin, np.isfinite(got)) and np.all(got[~fin] == -np.inf)
+    assert np.all(np.abs(got[fin] - ref[fin]) <= 1e-10 * np.abs(ref[fin]))

@@ -405,3 +405,23 @@ def test_config5_stress_chunked(E):
     rmx = np.abs(b[idx] - ref) / np.abs(ref)
     say("config5 rel err fp64", r64, "mixed", rmx)
     assert np.all(r64 <= 1e-10) and np.all(rmx <= 1e-4)
+
+
+def test_gr_limit_of_the_propagation(E):
+    """The modified-gravity factors reduce to GR on the HIP path: Xi0 = 1
+    (any n) and n = 0 (any Xi0) give Xi = 1 up to one rounding of
+    Xi0 + (1 - Xi0), alpha_T = 0 gives no delay; against the GR row."""
+    w = W.small("fp64", n_harm=6)
+    base = w.inj.copy()
+    rows = [base.copy() for _ in range(4)]
+    rows[1][14], rows[1][15] = 1.0, 3.0          # Xi0 = 1, n = 3
+    rows[2][14], rows[2][15] = 0.7, 0.0          # n = 0
+    rows[3][16] = 0.0                            # explicit GR speed
+    P = np.array(rows)
+    d, S = oracle_dataset(w, True)
+    cfg = E.Config.from_workload(w)
+    dd, ss = to_device_data(d, S)
+    got = E.loglike_batch(gpu_params(P), dd, ss, cfg).cpu().numpy()
+    say("GR-limit lnL", got)
+    assert got[1] == got[0] and got[3] == got[0]
+    assert abs(got[2] - got[0]) <= 1e-14 * abs(got[0])

@@ -38,7 +38,9 @@ NPAR = 17
 class _Cfg(ctypes.Structure):
     _fields_ = [("T_obs", ctypes.c_double), ("dt", ctypes.c_double), ("N", ctypes.c_int64),
                 ("n_harm", ctypes.c_int32), ("coarse_log2", ctypes.c_int32),
-                ("lo_only", ctypes.c_int32), ("ic_lso", ctypes.c_int32)]
+                ("lo_only", ctypes.c_int32), ("ic_lso", ctypes.c_int32),
+                ("ode", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("rtol", ctypes.c_double), ("atol", ctypes.c_double)]
 
 
 @dataclass(frozen=True)
@@ -50,6 +52,9 @@ class OracleConfig:
     coarse_log2: int = 10
     lo_only: bool = False
     ic_lso: bool = False      # initial conditions at the LSO, orbit integrated backward
+    ode: int = 0              # 0: classical RK4 on the nodes; 1: adaptive Dormand-Prince 5(4)
+    rtol: float = 1e-10       # tolerances of the adaptive integrator
+    atol: float = 1e-10
 
     @property
     def n_valid(self) -> int:
@@ -62,7 +67,8 @@ class OracleConfig:
 
     def c(self) -> _Cfg:
         return _Cfg(self.T_obs, self.dt, self.N, self.n_harm, self.coarse_log2,
-                    1 if self.lo_only else 0, 1 if self.ic_lso else 0)
+                    1 if self.lo_only else 0, 1 if self.ic_lso else 0, int(self.ode), 0,
+                    float(self.rtol), float(self.atol))
 
 
 def build(force: bool = True) -> str:
@@ -92,6 +98,8 @@ def lib():
             "oracle_scalars": ([dp, i64, dp], ctypes.c_int),
             "oracle_rhs": ([dp, dp, ctypes.c_int, dp], ctypes.c_int),
             "oracle_orbit": ([dp, i64, cp, dp, ip], ctypes.c_int),
+            "oracle_orbit_steps": ([dp, i64, cp, ip], ctypes.c_int),
+            "oracle_dp5_tableau": ([dp], ctypes.c_int),
             "oracle_waveform": ([dp, i64, cp, dp], ctypes.c_int),
             "oracle_waveform_diag": ([dp, cp, dp, dp], ctypes.c_int),
             "oracle_rfft": ([dp, i64, i64, ctypes.c_double, dp], ctypes.c_int),
@@ -166,6 +174,25 @@ def orbit(params, cfg: OracleConfig):
     _check(lib().oracle_orbit(_p(p), B, ctypes.byref(c), _p(orb),
                               kw.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), "orbit")
     return orb, kw
+
+
+def orbit_steps(params, cfg: OracleConfig) -> np.ndarray:
+    """[B][2] accepted and rejected steps of the adaptive integrator (ode=1)."""
+    p = _f64(params).reshape(-1, NPAR)
+    out = np.zeros((p.shape[0], 2), dtype=np.int32)
+    c = cfg.c()
+    _check(lib().oracle_orbit_steps(_p(p), p.shape[0], ctypes.byref(c),
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+           "orbit_steps")
+    return out
+
+
+def dp5_tableau():
+    """The oracle's Dormand-Prince 5(4) constants: c[7], A[7][7], b[7],
+    b - b*[7] and the continuous-extension vector d[7]."""
+    out = np.zeros(77)
+    lib().oracle_dp5_tableau(_p(out))
+    return (out[:7], out[7:56].reshape(7, 7), out[56:63], out[63:70], out[70:77])
 
 
 def waveform(params, cfg: OracleConfig) -> np.ndarray:

@@ -19,7 +19,10 @@
  *      delay Delta T [Eqs. (4)-(5)], overall factor 1/(Xi d_L)
  *   2. orbit: Eq. (1) with Y = {Phi, nu, gamma~, e, alpha}, classical RK4
  *      with a fixed coarse step, stopped at the last stable orbit
- *      (nu_LSO of Sec. 3 "Waveform computation")
+ *      (nu_LSO of Sec. 3 "Waveform computation"); or, optionally, an
+ *      adaptive embedded Runge-Kutta pair whose continuous extension gives
+ *      the same coarse nodes (Sec. 3 "Computational overhead": the ODE
+ *      solver is the method's main cost and its choice is open)
  *   3. time-domain waveform: Eq. (2), Peters-Mathews harmonics n=1..n_max,
  *      projected on the two low-frequency LISA channels with Doppler phase
  *      modulation; the orbit is read between coarse nodes by cubic Hermite
@@ -86,6 +89,9 @@ typedef struct {
     int32_t coarse_log2; /* coarse ODE step = dt * 2^coarse_log2            */
     int32_t lo_only;     /* test hook: leading-order (Peters-Mathews) ODE    */
     int32_t ic_lso;      /* 1: initial conditions at the LSO, integrated backward */
+    int32_t ode;         /* 0: classical RK4 on the nodes; 1: adaptive Dormand-Prince 5(4) */
+    int32_t reserved;
+    double rtol, atol;   /* tolerances of the adaptive integrator (ode = 1)   */
 } oracle_cfg;
 
 int oracle_num_threads(void);
@@ -324,8 +330,12 @@ static int64_t walker_orbit_lso(const double *p, const oracle_cfg *c, double *or
     return K;
 }
 
+static int64_t walker_orbit_dp5(const double *p, const oracle_cfg *c, double *orb, int32_t *stats);
+static int cfg_ok(const oracle_cfg *c);
+
 static int64_t walker_orbit(const double *p, const oracle_cfg *c, double *orb)
 {
+    if (c->ode == 1) return walker_orbit_dp5(p, c, orb, NULL);
     if (c->ic_lso) return walker_orbit_lso(p, c, orb);
     int64_t K = n_intervals_of(c);
     double h = c->dt * (double)((int64_t)1 << c->coarse_log2);
@@ -352,8 +362,188 @@ static int64_t walker_orbit(const double *p, const oracle_cfg *c, double *orb)
     return Kw;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Adaptive orbit (cfg.ode = 1).  Reading: the paper integrates Eq. (1)     */
+/* with a standard adaptive Runge-Kutta solver and names the solver as the  */
+/* main cost (Sec. 3 "Waveform computation", "Computational overhead").     */
+/* Here: the embedded 5(4) pair of Dormand & Prince (J. Comput. Appl. Math. */
+/* 6 (1980) 19), local extrapolation (the order-5 solution is kept), the    */
+/* standard step-size control of Hairer, Norsett & Wanner, "Solving ODEs I" */
+/* Sec. II.4, and the order-4 continuous extension of the pair (Shampine    */
+/* 1986, in the form of HNW Sec. II.6) evaluated at the coarse nodes         */
+/* t_k = k h_c, so that the orbit reaches the waveform step in the same      */
+/* layout as the RK4 path: Y_k and f(Y_k), with f evaluated at the           */
+/* interpolated state.                                                      */
+/*   error norm    sqrt(mean_i (err_i / sc_i)^2) over the five components,  */
+/*                 err = H sum_j (b_j - b*_j) k_j,                          */
+/*                 sc_i = atol + rtol max(|y_i|, |y1_i|), except nu: rtol    */
+/*                 max(|nu|, |nu1|) alone (nu is a frequency, always > 0)   */
+/*   accept        err <= 1; then H <- H min(5, max(0.2, 0.9 err^(-1/5)))   */
+/*                 (factor at most 1 right after a rejection)               */
+/*   reject        H <- H max(0.2, 0.9 err^(-1/5)) (a non-finite err: 0.2)  */
+/*   first step    one coarse interval; the last step is cut to end exactly */
+/*                 on the end of the window                                 */
+/*   stop          forward: at the first node past the LSO (K_w = the one   */
+/*                 before it, as with RK4); backward from the LSO: a node   */
+/*                 outside the physical range makes the walker invalid      */
+/*   budget        4 K + 64 step attempts, else the walker is invalid       */
+/* ------------------------------------------------------------------------ */
+static const double DP_C[7] = {0.0, 1.0 / 5.0, 3.0 / 10.0, 4.0 / 5.0, 8.0 / 9.0, 1.0, 1.0};
+static const double DP_A[7][6] = {
+    {0.0},
+    {1.0 / 5.0},
+    {3.0 / 40.0, 9.0 / 40.0},
+    {44.0 / 45.0, -56.0 / 15.0, 32.0 / 9.0},
+    {19372.0 / 6561.0, -25360.0 / 2187.0, 64448.0 / 6561.0, -212.0 / 729.0},
+    {9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0},
+    {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0}};
+/* order-5 weights (the last row of A: the seventh stage is f(y1)) */
+static const double DP_B[7] = {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0,
+                               -2187.0 / 6784.0, 11.0 / 84.0, 0.0};
+/* b - b*, b* the embedded order-4 weights */
+static const double DP_E[7] = {71.0 / 57600.0, 0.0, -71.0 / 16695.0, 71.0 / 1920.0,
+                               -17253.0 / 339200.0, 22.0 / 525.0, -1.0 / 40.0};
+/* continuous extension, fifth coefficient vector */
+static const double DP_D[7] = {-12715105075.0 / 11282082432.0, 0.0,
+                               87487479700.0 / 32700410799.0, -10690763975.0 / 1880347072.0,
+                               701980252875.0 / 199316789632.0, -1453857185.0 / 822651844.0,
+                               69997945.0 / 29380423.0};
+
+int oracle_dp5_tableau(double *out /* [77]: c[7], A[7][7], b[7], b - b*[7], d[7] */)
+{
+    for (int i = 0; i < 7; ++i) {
+        out[i] = DP_C[i];
+        for (int j = 0; j < 7; ++j) out[7 + 7 * i + j] = (j < 6) ? DP_A[i][j] : 0.0;
+        out[56 + i] = DP_B[i];
+        out[63 + i] = DP_E[i];
+        out[70 + i] = DP_D[i];
+    }
+    return 0;
+}
+
+/* stats (optional): [0] accepted steps, [1] rejected steps */
+static int64_t walker_orbit_dp5(const double *p, const oracle_cfg *c, double *orb, int32_t *stats)
+{
+    const int64_t K = n_intervals_of(c);
+    const double hc = c->dt * (double)((int64_t)1 << c->coarse_log2);
+    const double M_s = p[I_M] * O_TSUN, mu_s = p[I_MU] * O_TSUN, a = p[I_A], cl = p[I_CLAM];
+    const int back = c->ic_lso != 0;
+    const double t_end = back ? 0.0 : (double)K * hc;
+    const int64_t budget = 4 * K + 64;
+    memset(orb, 0, (size_t)(K + 1) * 10 * sizeof(double));
+    if (stats) stats[0] = stats[1] = 0;
+
+    double y[5], f[5];
+    int64_t node;     /* the next node to fill */
+    double t;
+    if (back) {
+        y[0] = p[I_PHI0]; y[1] = nu_lso(M_s, p[I_E0]); y[2] = p[I_GT0]; y[3] = p[I_E0];
+        y[4] = p[I_AL0];
+        t = (double)K * hc;
+        node = K - 1;
+    } else {
+        y[0] = p[I_PHI0]; y[1] = p[I_NU0]; y[2] = p[I_GT0]; y[3] = p[I_E0]; y[4] = p[I_AL0];
+        t = 0.0;
+        node = 1;
+    }
+    ak_rhs(y, M_s, mu_s, a, cl, c->lo_only, f);
+    double *o0 = orb + (back ? K : 0) * 10;
+    for (int i = 0; i < 5; ++i) { o0[i] = y[i]; o0[5 + i] = f[i]; }
+
+    double H = back ? -hc : hc;
+    int rejected = 0;
+    for (int64_t att = 0; att < budget; ++att) {
+        /* the step, cut to end on the end of the window */
+        double Hs = H;
+        int last = 0;
+        if (back ? (t + Hs <= t_end) : (t + Hs >= t_end)) { Hs = t_end - t; last = 1; }
+
+        double k[7][5], ys[5];
+        for (int i = 0; i < 5; ++i) k[0][i] = f[i];
+        for (int s = 1; s < 7; ++s) {
+            for (int i = 0; i < 5; ++i) {
+                double acc = 0.0;
+                for (int j = 0; j < s; ++j) acc += DP_A[s][j] * k[j][i];
+                ys[i] = y[i] + Hs * acc;
+            }
+            ak_rhs(ys, M_s, mu_s, a, cl, c->lo_only, k[s]);
+        }
+        /* ys now holds y1, the order-5 solution (seventh stage state), and
+         * k[6] = f(y1) */
+        double sum = 0.0;
+        for (int i = 0; i < 5; ++i) {
+            double err = 0.0;
+            for (int j = 0; j < 7; ++j) err += DP_E[j] * k[j][i];
+            err *= Hs;
+            double sc = (i == 1 ? 0.0 : c->atol) + c->rtol * fmax(fabs(y[i]), fabs(ys[i]));
+            sum += (err / sc) * (err / sc);
+        }
+        double en = sqrt(sum / 5.0);
+        double fac = fmax(0.2, 0.9 * pow(en, -0.2));
+        if (!(en <= 1.0)) {            /* rejected (a NaN norm too) */
+            H = Hs * fac;
+            rejected = 1;
+            if (stats) stats[1]++;
+            continue;
+        }
+        if (stats) stats[0]++;
+        double t1 = last ? t_end : t + Hs;
+
+        /* continuous extension on [t, t1]:
+         * y(th) = r1 + th (r2 + (1 - th) (r3 + th (r4 + (1 - th) r5))) */
+        double r1[5], r2[5], r3[5], r4[5], r5[5];
+        for (int i = 0; i < 5; ++i) {
+            r1[i] = y[i];
+            r2[i] = ys[i] - y[i];
+            r3[i] = Hs * k[0][i] - r2[i];
+            r4[i] = r2[i] - Hs * k[6][i] - r3[i];
+            double dd = 0.0;
+            for (int j = 0; j < 7; ++j) dd += DP_D[j] * k[j][i];
+            r5[i] = Hs * dd;
+        }
+        /* the coarse nodes in (t, t1] */
+        while (back ? (node >= 0 && (double)node * hc >= t1)
+                    : (node <= K && (double)node * hc <= t1)) {
+            double th = ((double)node * hc - t) / Hs, yk[5], fk[5];
+            for (int i = 0; i < 5; ++i)
+                yk[i] = r1[i] + th * (r2[i] + (1.0 - th) * (r3[i] + th * (r4[i] + (1.0 - th) * r5[i])));
+            if (back) {
+                if (!node_sane(yk)) return -1;
+            } else if (!node_ok(yk, M_s)) {
+                return node - 1;       /* node is past the LSO */
+            }
+            ak_rhs(yk, M_s, mu_s, a, cl, c->lo_only, fk);
+            double *o = orb + node * 10;
+            for (int i = 0; i < 5; ++i) { o[i] = yk[i]; o[5 + i] = fk[i]; }
+            node += back ? -1 : 1;
+        }
+        if (last) return K;
+        for (int i = 0; i < 5; ++i) { y[i] = ys[i]; f[i] = k[6][i]; }
+        t = t1;
+        H = Hs * fmin(rejected ? 1.0 : 5.0, fac);
+        rejected = 0;
+    }
+    return -1;                         /* step budget exhausted */
+}
+
+int oracle_orbit_steps(const double *params, int64_t B, const oracle_cfg *c, int32_t *steps /* [B][2] */)
+{
+    if (!cfg_ok(c) || c->ode != 1) return -1;
+    int64_t K = n_intervals_of(c);
+    double *orb = (double *)malloc((size_t)(K + 1) * 10 * sizeof(double));
+    for (int64_t w = 0; w < B; ++w) {
+        steps[2 * w] = steps[2 * w + 1] = 0;
+        double s[8];
+        walker_scalars(params + w * NPAR, c->ic_lso, s);
+        if (s[0] != 0.0) walker_orbit_dp5(params + w * NPAR, c, orb, steps + 2 * w);
+    }
+    free(orb);
+    return 0;
+}
+
 int oracle_orbit(const double *params, int64_t B, const oracle_cfg *c, double *orb, int32_t *Kw)
 {
+    if (!cfg_ok(c)) return -1;
     int64_t K = n_intervals_of(c);
     for (int64_t w = 0; w < B; ++w) {
         double s[8];
@@ -578,6 +768,9 @@ static int cfg_ok(const oracle_cfg *c)
     if (!(c->dt > 0.0) || !(c->T_obs > 0.0) || c->N < 2 || (c->N & (c->N - 1))) return 0;
     if (n_valid_of(c) > c->N || n_valid_of(c) < 1) return 0;
     if (c->n_harm < 1 || c->n_harm > 100 || c->coarse_log2 < 0 || c->coarse_log2 > 30) return 0;
+    if (c->ode != 0 && c->ode != 1) return 0;
+    if (c->ode == 1 && !(c->rtol >= 1e-13 && c->rtol <= 1e-3 && c->atol >= 0.0 && isfinite(c->atol)))
+        return 0;
     return 1;
 }
 

@@ -1,0 +1,257 @@
+"""Pins of the oracle's adaptive orbit integrator (cfg.ode = 1): the embedded
+Dormand-Prince 5(4) pair with step control and its continuous extension
+sampled at the coarse nodes (the ODE solver of Sec. 3 "Waveform computation"
+and "Computational overhead").
+
+The pins do not re-run the oracle's own formulas:
+  * the oracle's constants satisfy the Runge-Kutta order conditions (Butcher
+    rooted trees, generated here): order 5 for b, 4 for the embedded b*, 4
+    for the continuous extension at every theta, which reproduces b at 1;
+  * the nodes agree with an independent integrator (scipy's DOP853 at a far
+    tighter tolerance, sampled with its own dense output) to the requested
+    tolerance;
+  * Peters' closed form nu(e) holds on the adaptive orbit to the tolerance;
+  * the nodes agree with the classical RK4 path (pinned elsewhere).
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy.integrate import solve_ivp
+
+import oracle as O
+from paper_2311_17174_amd import workloads as W
+
+TSUN = 4.925490947641267e-6
+
+
+def cfg(w, **kw):
+    return O.OracleConfig(T_obs=w.T_obs, dt=w.dt, N=w.N, n_harm=w.n_harm,
+                          coarse_log2=w.coarse_log2, **kw)
+
+
+# ---- rooted trees and elementary weights ---------------------------------
+def _trees(n, memo={}):
+    """Rooted trees with n vertices, each a sorted tuple of child trees."""
+    if n in memo:
+        return memo[n]
+    if n == 1:
+        memo[1] = [()]
+        return memo[1]
+    out = set()
+
+    def forests(m, smallest):
+        if m == 0:
+            yield ()
+            return
+        for k in range(1, m + 1):
+            for t in _trees(k):
+                key = (k, t)
+                if smallest is not None and key < smallest:
+                    continue
+                for rest in forests(m - k, key):
+                    yield (t,) + rest
+
+    for f in forests(n - 1, None):
+        out.add(tuple(sorted(f)))
+    memo[n] = sorted(out)
+    return memo[n]
+
+
+def _order(t):
+    return 1 + sum(_order(x) for x in t)
+
+
+def _gamma(t):
+    g = _order(t)
+    for x in t:
+        g *= _gamma(x)
+    return g
+
+
+def _phi(t, A):
+    """Stage vector of the elementary weight of tree t."""
+    v = np.ones(A.shape[0])
+    for ch in t:
+        v = v * (A @ _phi(ch, A))
+    return v
+
+
+def _defects(w, A, p, theta=1.0):
+    """max |sum_i w_i Phi_i(t) - theta^rho / gamma(t)| over trees of order <= p."""
+    return max(abs(w @ _phi(t, A) - theta ** _order(t) / _gamma(t))
+               for n in range(1, p + 1) for t in _trees(n))
+
+
+def test_tree_counts():
+    assert [len(_trees(n)) for n in range(1, 7)] == [1, 1, 2, 4, 9, 20]
+
+
+def test_tableau_order_conditions():
+    c, A, b, e, d = O.dp5_tableau()
+    np.testing.assert_allclose(A.sum(axis=1), c, rtol=0, atol=1e-15)
+    assert np.array_equal(A[6, :6], b[:6]) and b[6] == 0.0     # FSAL: stage 7 is f(y1)
+    assert _defects(b, A, 5) < 2e-15
+    assert _defects(b, A, 6) > 1e-4                              # exactly order 5
+    bs = b - e
+    assert _defects(bs, A, 4) < 2e-15
+    assert _defects(bs, A, 5) > 1e-5                             # exactly order 4
+    # a planted wrong digit in any weight breaks the conditions
+    for i in (0, 2, 3, 4, 5):
+        bad = b.copy()
+        bad[i] *= 1 + 1e-9
+        assert _defects(bad, A, 5) > 1e-11
+
+
+def _dense_weights(theta, b, d):
+    """Weights beta_i(theta) of the continuous extension
+    y(th) = y0 + th (D + (1-th) (h k1 - D + th (2 D - h k7 - h k1 + (1-th) h sum d k))),
+    D = h sum b k, written as y0 + h sum_i beta_i k_i."""
+    e1 = np.eye(7)[0]
+    e7 = np.eye(7)[6]
+    return theta * b + theta * (1 - theta) * (e1 - b + theta * (2 * b - e7 - e1)
+                                              + theta * (1 - theta) * d)
+
+
+def test_continuous_extension_is_order_four():
+    c, A, b, e, d = O.dp5_tableau()
+    for th in (0.1, 0.37, 0.5, 0.81):
+        beta = _dense_weights(th, b, d)
+        assert _defects(beta, A, 4, theta=th) < 3e-15
+    np.testing.assert_allclose(_dense_weights(1.0, b, d), b, rtol=0, atol=1e-16)
+    assert np.all(_dense_weights(0.0, b, d) == 0.0)
+    # the published coefficients are exact rationals: their doubles round-trip
+    exact = [Fraction(-12715105075, 11282082432), Fraction(87487479700, 32700410799),
+             Fraction(-10690763975, 1880347072), Fraction(701980252875, 199316789632),
+             Fraction(-1453857185, 822651844), Fraction(69997945, 29380423)]
+    assert [float(x) for x in exact] == [d[0], d[2], d[3], d[4], d[5], d[6]]
+
+
+# ---- the integrator on the AK orbit ---------------------------------------
+def _scipy_orbit(p, w, t_nodes, rtol=1e-13, lo_only=False, backward_from=None):
+    """Eq. (1) by scipy's DOP853 with the oracle's right-hand side, sampled at
+    t_nodes with scipy's own dense output."""
+    def f(t, y):
+        return O.rhs(y, p, lo_only)
+    if backward_from is None:
+        y0 = np.array([p[5], p[4], p[6], p[3], p[7]])
+        span = (0.0, t_nodes[-1])
+    else:
+        y0 = backward_from
+        span = (t_nodes[-1], 0.0)
+    s = solve_ivp(f, span, y0, method="DOP853", rtol=rtol, atol=1e-30 + rtol * 1e-3,
+                  dense_output=True)
+    assert s.success
+    return s.sol(t_nodes).T
+
+
+@pytest.mark.parametrize("rtol", [1e-8, 1e-11])
+def test_nodes_match_an_independent_integrator(rtol):
+    w = W.config1()
+    p = W.injection()
+    c = cfg(w, ode=1, rtol=rtol, atol=rtol)
+    orb, kw = O.orbit(p[None], c)
+    K = w.n_intervals
+    assert kw[0] == K
+    hc = w.dt * (1 << w.coarse_log2)
+    ref = _scipy_orbit(p, w, np.arange(K + 1) * hc)
+    y = orb[0, :, :5]
+    nu_rel = np.max(np.abs(y[:, 1] / ref[:, 1] - 1))
+    e_abs = np.max(np.abs(y[:, 3] - ref[:, 3]))
+    phi_abs = np.max(np.abs(y[:, 0] - ref[:, 0]))
+    assert nu_rel < rtol and e_abs < rtol
+    assert phi_abs < rtol * np.max(np.abs(ref[:, 0]))
+    assert np.max(np.abs(y[:, 2] - ref[:, 2])) < rtol * np.max(np.abs(ref[:, 2])) + rtol
+    assert np.max(np.abs(y[:, 4] - ref[:, 4])) < rtol * np.max(np.abs(ref[:, 4])) + rtol
+    # node derivatives are the right-hand side at the node state
+    for k in (0, 7, K // 2, K):
+        np.testing.assert_allclose(orb[0, k, 5:], O.rhs(orb[0, k, :5], p), rtol=1e-15, atol=0)
+
+
+def test_peters_invariant_tracks_the_tolerance():
+    """Leading-order ODE, a = 0, backward from the LSO: nu(e) of Peters'
+    closed form through (e_LSO, nu_LSO) holds to about rtol, and tighter
+    tolerances take more steps."""
+    w = W.config2()
+    eL = 0.2
+    p = W.injection(a=0.0, e0=eL)
+    nuL = ((1 - eL * eL) / (6 + 2 * eL)) ** 1.5 / (2 * np.pi * p[0] * TSUN)
+
+    def nu_of_e(e):
+        r = ((1 - e * e) / (1 - eL * eL) * (eL / e) ** (12 / 19) *
+             ((1 + 121 * eL ** 2 / 304) / (1 + 121 * e * e / 304)) ** (870 / 2299))
+        return nuL * r ** 1.5
+
+    prev_err, prev_steps = np.inf, 0
+    for rtol in (1e-6, 1e-8, 1e-10, 1e-12):
+        c = cfg(w, lo_only=True, ic_lso=True, ode=1, rtol=rtol, atol=rtol)
+        orb, kw = O.orbit(p[None], c)
+        assert kw[0] == w.n_intervals
+        assert orb[0, -1, 1] == nuL and orb[0, -1, 3] == eL
+        err = np.max(np.abs(orb[0, :, 1] / nu_of_e(orb[0, :, 3]) - 1))
+        steps = O.orbit_steps(p[None], c)[0]
+        assert err < 5 * rtol and err < prev_err
+        assert steps[0] > prev_steps
+        prev_err, prev_steps = err, steps[0]
+
+
+def test_agrees_with_rk4_and_takes_few_steps():
+    """At a tight tolerance the adaptive nodes agree with the classical RK4
+    nodes within RK4's own error, with a small fraction of its steps."""
+    w = W.config2()
+    K = w.n_intervals
+    P = W.walkers(w, B=4)
+    a, ka = O.orbit(P, cfg(w, ode=1, rtol=1e-12, atol=1e-12))
+    r, kr = O.orbit(P, cfg(w))
+    assert np.array_equal(ka, kr)
+    for b in range(4):
+        n = kr[b] + 1
+        assert np.max(np.abs(a[b, :n, 1] / r[b, :n, 1] - 1)) < 1e-11
+        assert np.max(np.abs(a[b, :n, 0] - r[b, :n, 0])) < 1e-6          # radians
+        assert np.max(np.abs(a[b, :n, 3] - r[b, :n, 3])) < 1e-11
+    steps = O.orbit_steps(P, cfg(w, ode=1, rtol=1e-10, atol=1e-10))
+    assert np.all(steps[:, 0] < K / 20)
+
+
+def test_plunge_inside_the_window():
+    """A walker that reaches the LSO inside the window stops at the same node
+    as with RK4 (or one apart, where the crossing falls next to a node)."""
+    w = W.config1()
+    p = W.injection()
+    # start close to the LSO: nu0 at 97% of nu_LSO(e0)
+    e0 = p[3]
+    p[4] = 0.97 * ((1 - e0 * e0) / (6 + 2 * e0)) ** 1.5 / (2 * np.pi * p[0] * TSUN)
+    a, ka = O.orbit(p[None], cfg(w, ode=1, rtol=1e-11, atol=1e-11))
+    r, kr = O.orbit(p[None], cfg(w))
+    assert 0 < kr[0] < w.n_intervals
+    assert abs(int(ka[0]) - int(kr[0])) <= 1
+    n = min(ka[0], kr[0]) + 1
+    assert np.max(np.abs(a[0, :n, 1] / r[0, :n, 1] - 1)) < 1e-9
+    assert np.all(a[0, ka[0] + 1:] == 0.0)
+
+
+def test_lso_mode_matches_rk4_backward():
+    w = W.config1()
+    p = W.injection(e0=0.3)
+    a, ka = O.orbit(p[None], cfg(w, ic_lso=True, ode=1, rtol=1e-12, atol=1e-12))
+    r, kr = O.orbit(p[None], cfg(w, ic_lso=True))
+    assert ka[0] == kr[0] == w.n_intervals
+    assert np.array_equal(a[0, -1], r[0, -1])               # the LSO state itself
+    assert np.max(np.abs(a[0, :, 1] / r[0, :, 1] - 1)) < 1e-11
+    # an unphysical history is still flagged
+    q = W.injection(M=2e4, mu=10.0, e0=0.7)
+    long = O.OracleConfig(T_obs=1.0 * W.YEAR, dt=10.0, N=1 << 22, n_harm=2, ic_lso=True,
+                          ode=1, rtol=1e-10, atol=1e-10)
+    _, kw = O.orbit(q[None], long)
+    assert kw[0] == -1
+
+
+def test_bad_tolerances_are_rejected():
+    w = W.config1()
+    p = W.injection()
+    for rtol, atol in ((0.0, 1e-10), (1e-14, 1e-10), (1e-2, 1e-10), (1e-10, -1.0),
+                       (1e-10, float("inf")), (float("nan"), 1e-10)):
+        with pytest.raises(ValueError):
+            O.orbit(p[None], cfg(w, ode=1, rtol=rtol, atol=atol))
+    with pytest.raises(ValueError):
+        O.orbit(p[None], cfg(w, ode=2))

@@ -277,6 +277,39 @@ def run_fmg(E, W, w, data, psd, steps: int, warmup: int):
     return res
 
 
+def run_dp5(E, W, w, data, psd, steps: int, warmup: int, rtol: float = 1e-12):
+    """The adaptive orbit integrator (Dormand-Prince 5(4), tolerance rtol,
+    continuous extension at the coarse nodes) against the classical RK4 path,
+    on the same walkers and resident data as the main line."""
+    import torch
+    P = torch.from_numpy(W.walkers(w)).cuda()
+    out = torch.empty(w.B, dtype=torch.float64, device="cuda")
+    res = {}
+    lnl = {}
+    for name, wk in (("rk4", w), ("dp5", w.with_(ode=1, ode_rtol=rtol, ode_atol=rtol))):
+        cfg = E.Config.from_workload(wk)
+        ds = E.dataset_init(data, psd, cfg)
+        ws = E.alloc_workspace(cfg, w.B)
+        for _ in range(warmup):
+            E.loglike_dataset(P, ds, cfg, out=out, ws=ws)
+        torch.cuda.synchronize()
+        with E.Tracer() as tr:
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                E.loglike_dataset(P, ds, cfg, out=out, ws=ws)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st = tr.read()
+        lnl[name] = out.cpu().numpy().copy()
+        res[name] = {"value": steps * w.B / (t1 - t0), "ms_per_step": 1e3 * (t1 - t0) / steps,
+                     "orbit_ms_per_step": st["walker_setup"][0] / steps}
+        del ds, ws
+    res.update({"unit": "lnL evals/s", "workload": w.name, "rtol": rtol, "atol": rtol,
+                "max_abs_dlnL_vs_rk4": float(np.max(np.abs(lnl["dp5"] - lnl["rk4"]))),
+                "orbit_speedup": res["rk4"]["orbit_ms_per_step"] / res["dp5"]["orbit_ms_per_step"]})
+    return res
+
+
 def run_serving(E, W, n_burst: int, n_requests: int, arena_gib: float, n_streams: int,
                 max_batch: int, n_sweep: int = 0):
     """Serving loop (mixed precision): 8 chains x 3 observation times of
@@ -405,6 +438,7 @@ def main():
                     help="requests at each of 0.5x and 1.0x the saturated rate")
     ap.add_argument("--no-sampler", action="store_true")
     ap.add_argument("--no-fmg", action="store_true")
+    ap.add_argument("--no-dp5", action="store_true")
     ap.add_argument("--sampler-steps", type=int, default=4)
     ap.add_argument("--no-config5", action="store_true")
     ap.add_argument("--config5-steps", type=int, default=2)
@@ -514,6 +548,14 @@ def main():
               f"evals/s, mixed {fmg['mixed']['fmg']['value']:.1f} evals/s", file=sys.stderr,
               flush=True)
 
+    dp5 = None
+    if not args.no_dp5:
+        dp5 = {"fp64": run_dp5(E, W, w64, data, psd, max(2, args.steps // 2), 1),
+               "mixed": run_dp5(E, W, wmx, data, psd, max(2, args.steps // 2), 1)}
+        print(f"[bench] adaptive orbit: fp64 {dp5['fp64']['dp5']['value']:.1f} evals/s (orbit "
+              f"{dp5['fp64']['orbit_speedup']:.2f}x faster than RK4), mixed "
+              f"{dp5['mixed']['dp5']['value']:.1f} evals/s", file=sys.stderr, flush=True)
+
     serving = None
     if not args.no_serving:
         torch.cuda.empty_cache()
@@ -608,6 +650,7 @@ def main():
         "stress": config5,
         "sampler": sampler,
         "frequency_dependent_propagation": fmg,
+        "adaptive_orbit": dp5,
         "stages": stages_out,
     }
     print(json.dumps(rec), flush=True)

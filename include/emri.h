@@ -57,7 +57,7 @@ extern "C" {
 #endif
 
 #define EMRI_NPAR 17
-#define EMRI_ABI_VERSION 4
+#define EMRI_ABI_VERSION 5
 
 typedef enum {
     EMRI_OK = 0,
@@ -91,8 +91,30 @@ typedef enum {
  *               unused), integrated backward; the LSO is the last coarse
  *               node, t = K h with K = ceil(N_valid / 2^coarse_log2), so the
  *               window ends within one coarse step of the plunge.  A walker
- *               whose backward history leaves 0 <= e < 1, nu > 0 is invalid. */
+ *               whose backward history leaves 0 <= e < 1, nu > 0 is invalid.
+ *  ode          the integrator of Eq. (1) (Sec. 3 "Waveform computation" and
+ *               "Computational overhead": a standard adaptive Runge-Kutta
+ *               solver, the method's main cost):
+ *               EMRI_ODE_RK4: classical RK4 with step h on the coarse nodes;
+ *               EMRI_ODE_DP5: the embedded Dormand-Prince 5(4) pair with
+ *               step-size control (Hairer, Norsett & Wanner, Solving ODEs I,
+ *               Sec. II.4: RMS error norm over the five components, safety
+ *               0.9, step factors in [0.2, 5], no growth right after a
+ *               rejection; first step h; the last step cut to end on the
+ *               window) and its order-4 continuous extension evaluated at the
+ *               coarse nodes, whose derivatives are the right-hand side at
+ *               the interpolated state.  The nodes reach the waveform step in
+ *               the same layout as with RK4.  A walker that needs more than
+ *               4 K + 64 step attempts is invalid (lnL = -inf; its
+ *               time-domain rows then hold whatever was synthesised before
+ *               that was found).
+ *  reserved     0
+ *  ode_rtol     EMRI_ODE_DP5: relative tolerance, 1e-13 .. 1e-3
+ *  ode_atol     EMRI_ODE_DP5: absolute tolerance >= 0 for Phi, gamma~ and
+ *               alpha [rad] and e; nu is held to ode_rtol relative alone.
+ *               Both are ignored with EMRI_ODE_RK4. */
 typedef enum { EMRI_IC_START = 0, EMRI_IC_LSO = 1 } emri_ic;
+typedef enum { EMRI_ODE_RK4 = 0, EMRI_ODE_DP5 = 1 } emri_ode;
 typedef struct {
     double T_obs;
     double dt;
@@ -101,6 +123,10 @@ typedef struct {
     int32_t precision;
     int32_t coarse_log2;
     int32_t ic;                  /* emri_ic */
+    int32_t ode;                 /* emri_ode */
+    int32_t reserved;            /* 0 */
+    double ode_rtol;
+    double ode_atol;
 } emri_cfg;
 
 /* Library ABI version (EMRI_ABI_VERSION). */

@@ -119,12 +119,26 @@ emri_status make_plan(const emri_cfg* cfg, int64_t B, Plan* p, const char** err)
         *err = "ic must be EMRI_IC_START or EMRI_IC_LSO";
         return EMRI_EINVAL;
     }
+    if (cfg->ode != EMRI_ODE_RK4 && cfg->ode != EMRI_ODE_DP5) {
+        *err = "ode must be EMRI_ODE_RK4 or EMRI_ODE_DP5";
+        return EMRI_EINVAL;
+    }
+    if (cfg->reserved != 0) { *err = "reserved must be 0"; return EMRI_EINVAL; }
+    if (cfg->ode == EMRI_ODE_DP5 &&
+        !(cfg->ode_rtol >= 1e-13 && cfg->ode_rtol <= 1e-3 && cfg->ode_atol >= 0.0 &&
+          isfinite(cfg->ode_atol))) {
+        *err = "DP5 tolerances: need 1e-13 <= ode_rtol <= 1e-3 and a finite ode_atol >= 0";
+        return EMRI_EINVAL;
+    }
     if (B < 0) { *err = "B must be >= 0"; return EMRI_EINVAL; }
 
     Plan& q = *p;
     memset(&q, 0, sizeof q);
     q.T_obs = cfg->T_obs;
     q.ic = cfg->ic;
+    q.ode = cfg->ode;
+    q.rtol = cfg->ode_rtol;
+    q.atol = cfg->ode_atol;
     q.dt = cfg->dt;
     q.N = cfg->N;
     q.Nv = Nv;

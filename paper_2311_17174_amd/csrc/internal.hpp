@@ -49,7 +49,16 @@ enum {
     WC_AT = 31,     // alpha_T of the parameter row
     WC_KSEG = 32,   // 16 slots: K_w as known after orbit segment i (the
                     // segment's end when the orbit is still before the LSO)
-    WC = 48
+    // adaptive integrator state between orbit segments (emri_cfg.ode = DP5)
+    WC_OT = 48,     // time of the state
+    WC_OY = 49,     // 5 slots: the state Y
+    WC_OF = 54,     // 5 slots: f(Y) (first stage of the next step)
+    WC_OH = 59,     // proposed next step
+    WC_ONODE = 60,  // next coarse node to fill
+    WC_OATT = 61,   // step attempts so far
+    WC_OREJ = 62,   // 1: the last attempt was rejected
+    WC_ODONE = 63,  // 1: the orbit has ended (window end or LSO)
+    WC = 64
 };
 
 // partial sums of the data norm <d|d> (mixed path data set)
@@ -75,6 +84,8 @@ struct Plan {
     int prec;              // emri_precision
     int cl;                // coarse_log2
     int ic;                // emri_cfg.ic: initial conditions at t = 0 or at the LSO
+    int ode;               // emri_cfg.ode: RK4 or adaptive DP5
+    double rtol, atol;     // DP5 tolerances
     int64_t L;             // samples per coarse interval, 2^cl
     int64_t K;             // coarse intervals covering N_valid
     // FFT: N = R1 * R2; pass A: R2-point column FFTs (stride R1), T per WG;

@@ -2,8 +2,9 @@
 //
 //  k_walker_setup   one lane per walker (FP64): validity, z(d_L), Xi(z),
 //                   propagation delay, geometry constants, then the orbital
-//                   ODE of Eq. (1) by classical RK4 on the coarse grid, stopped
-//                   at the last node before the LSO (Sec. 3).
+//                   ODE of Eq. (1) by classical RK4 on the coarse grid, or by
+//                   the adaptive Dormand-Prince 5(4) pair sampled at the same
+//                   nodes, stopped at the last node before the LSO (Sec. 3).
 //  k_nodes          one lane per (walker, orbit node, harmonic): Bessel
 //                   functions of the Peters-Mathews amplitudes and their time
 //                   derivatives at the node
@@ -164,15 +165,256 @@ __device__ __forceinline__ bool rk4_back(double Y0, double Y1, double Y2, double
     return true;
 }
 
+// ---------------------------------------------------------------------------
+// Adaptive orbit (emri_cfg.ode = EMRI_ODE_DP5): the embedded Dormand-Prince
+// 5(4) pair (J. Comput. Appl. Math. 6 (1980) 19), the order-5 solution kept,
+// step control as in Hairer, Norsett & Wanner, Solving ODEs I, Sec. II.4,
+// and the pair's order-4 continuous extension (Shampine 1986, in the form
+// of HNW Sec. II.6) evaluated at the coarse nodes t_k = k h.  The nodes
+// carry Y_k and f(Y_k) as on the RK4 path, so the tables and synthesis do
+// not know which integrator ran.  The right-hand side depends on (nu, e)
+// alone: a stage only forms those two components of its state.
+// ---------------------------------------------------------------------------
+namespace dp5 {
+constexpr double A21 = 1.0 / 5.0;
+constexpr double A31 = 3.0 / 40.0, A32 = 9.0 / 40.0;
+constexpr double A41 = 44.0 / 45.0, A42 = -56.0 / 15.0, A43 = 32.0 / 9.0;
+constexpr double A51 = 19372.0 / 6561.0, A52 = -25360.0 / 2187.0, A53 = 64448.0 / 6561.0,
+                 A54 = -212.0 / 729.0;
+constexpr double A61 = 9017.0 / 3168.0, A62 = -355.0 / 33.0, A63 = 46732.0 / 5247.0,
+                 A64 = 49.0 / 176.0, A65 = -5103.0 / 18656.0;
+// order-5 weights; the seventh stage is f(y1) (its b is 0)
+constexpr double B1 = 35.0 / 384.0, B3 = 500.0 / 1113.0, B4 = 125.0 / 192.0,
+                 B5 = -2187.0 / 6784.0, B6 = 11.0 / 84.0;
+// b - b*, b* the embedded order-4 weights
+constexpr double E1 = 71.0 / 57600.0, E3 = -71.0 / 16695.0, E4 = 71.0 / 1920.0,
+                 E5 = -17253.0 / 339200.0, E6 = 22.0 / 525.0, E7 = -1.0 / 40.0;
+// continuous extension, fifth coefficient vector
+constexpr double D1 = -12715105075.0 / 11282082432.0, D3 = 87487479700.0 / 32700410799.0,
+                 D4 = -10690763975.0 / 1880347072.0, D5 = 701980252875.0 / 199316789632.0,
+                 D6 = -1453857185.0 / 822651844.0, D7 = 69997945.0 / 29380423.0;
+constexpr double kSafety = 0.9, kFacMin = 0.2, kFacMax = 5.0;
+
+enum { GO = 0, END = 1, FAIL = 2 };
+
+struct State {
+    double t, H;       // time of Y; proposed step (signed)
+    double Y[5];       // Phi, nu, gamma~, e, alpha
+    Rhs f;             // f(Y)
+    int64_t node;      // next coarse node to fill
+    int64_t att;       // step attempts so far
+    int rej;           // the last attempt was rejected
+};
+
+__device__ inline double comp(const Rhs& r, int i)
+{
+    return i == 0 ? r.dPhi : i == 1 ? r.dnu : i == 2 ? r.dgt : i == 3 ? r.de : r.dal;
+}
+
+// steps until node `stop` is filled (forward: nodes up to stop; backward:
+// down to stop).  END: the orbit is complete, *kw its last node (forward:
+// the last before the LSO); FAIL: budget exhausted, or (backward) a node
+// outside the physical range
+// R: this lane's kLdsSlots LDS slots of the continuous extension, stride 64
+constexpr int kLdsSlots = 20;
+__device__ int advance(State& s, int64_t stop, int64_t K, double hc, bool back, double rtol,
+                       double atol, double Ms, double mus, double a, double cl,
+                       double* __restrict__ o, int64_t* kw, double* __restrict__ R)
+{
+    const double t_end = back ? 0.0 : (double)K * hc;
+    const int64_t budget = 4 * K + 64;
+    while (back ? s.node >= stop : s.node <= stop) {
+        if (s.att >= budget) return FAIL;
+        ++s.att;
+        double Hs = s.H;
+        bool last = false;
+        if (back ? (s.t + Hs <= t_end) : (s.t + Hs >= t_end)) {
+            Hs = t_end - s.t;
+            last = true;
+        }
+        // stage j adds b_j k_j, (b_j - b*_j) k_j and d_j k_j to running sums
+        // (the order of the sums is j = 1..7); later stages need only the nu
+        // and e components of earlier ones
+        double sB[5], sE[5], sD[5];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            const double k = comp(s.f, i);
+            sB[i] = B1 * k;
+            sE[i] = E1 * k;
+            sD[i] = D1 * k;
+        }
+        const double n0 = s.Y[1], e0 = s.Y[3];
+        const double n1 = s.f.dnu, m1 = s.f.de;
+        const Rhs k2 = ak_rhs(n0 + Hs * (A21 * n1), e0 + Hs * (A21 * m1), Ms, mus, a, cl);
+        const double n2 = k2.dnu, m2 = k2.de;
+        Rhs k = ak_rhs(n0 + Hs * (A31 * n1 + A32 * n2), e0 + Hs * (A31 * m1 + A32 * m2), Ms, mus,
+                       a, cl);
+        const double n3 = k.dnu, m3 = k.de;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            sB[i] += B3 * comp(k, i);
+            sE[i] += E3 * comp(k, i);
+            sD[i] += D3 * comp(k, i);
+        }
+        k = ak_rhs(n0 + Hs * (A41 * n1 + A42 * n2 + A43 * n3),
+                   e0 + Hs * (A41 * m1 + A42 * m2 + A43 * m3), Ms, mus, a, cl);
+        const double n4 = k.dnu, m4 = k.de;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            sB[i] += B4 * comp(k, i);
+            sE[i] += E4 * comp(k, i);
+            sD[i] += D4 * comp(k, i);
+        }
+        k = ak_rhs(n0 + Hs * (A51 * n1 + A52 * n2 + A53 * n3 + A54 * n4),
+                   e0 + Hs * (A51 * m1 + A52 * m2 + A53 * m3 + A54 * m4), Ms, mus, a, cl);
+        const double n5 = k.dnu, m5 = k.de;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            sB[i] += B5 * comp(k, i);
+            sE[i] += E5 * comp(k, i);
+            sD[i] += D5 * comp(k, i);
+        }
+        k = ak_rhs(n0 + Hs * (A61 * n1 + A62 * n2 + A63 * n3 + A64 * n4 + A65 * n5),
+                   e0 + Hs * (A61 * m1 + A62 * m2 + A63 * m3 + A64 * m4 + A65 * m5), Ms, mus, a,
+                   cl);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            sB[i] += B6 * comp(k, i);
+            sE[i] += E6 * comp(k, i);
+            sD[i] += D6 * comp(k, i);
+        }
+        double y1[5];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) y1[i] = s.Y[i] + Hs * sB[i];
+        const Rhs k7 = ak_rhs(y1[1], y1[3], Ms, mus, a, cl);
+        double sum = 0.0;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            const double err = Hs * (sE[i] + E7 * comp(k7, i));
+            const double sc = (i == 1 ? 0.0 : atol) + rtol * fmax(fabs(s.Y[i]), fabs(y1[i]));
+            const double q = err / sc;
+            sum += q * q;
+        }
+        const double en = sqrt(sum / 5.0);
+        const double fac = fmax(kFacMin, kSafety * pow(en, -0.2));
+        if (!(en <= 1.0)) {              // rejected (a NaN norm too)
+            s.H = Hs * fac;
+            s.rej = 1;
+            continue;
+        }
+        const double t1 = last ? t_end : s.t + Hs;
+        // y(th) = r1 + th (r2 + (1 - th) (r3 + th (r4 + (1 - th) r5))) on [t, t1];
+        // r2..r5 wait in this lane's LDS slots while the nodes are filled
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            const double r2 = y1[i] - s.Y[i];
+            const double r3 = Hs * comp(s.f, i) - r2;
+            R[(0 * 5 + i) * 64] = r2;
+            R[(1 * 5 + i) * 64] = r3;
+            R[(2 * 5 + i) * 64] = r2 - Hs * comp(k7, i) - r3;
+            R[(3 * 5 + i) * 64] = Hs * (sD[i] + D7 * comp(k7, i));
+        }
+        while (back ? (s.node >= 0 && (double)s.node * hc >= t1)
+                    : (s.node <= K && (double)s.node * hc <= t1)) {
+            const double th = ((double)s.node * hc - s.t) / Hs;
+            double yk[5];
+#pragma unroll
+            for (int i = 0; i < 5; ++i)
+                yk[i] = s.Y[i] + th * (R[i * 64] +
+                                       (1.0 - th) * (R[(5 + i) * 64] +
+                                                     th * (R[(10 + i) * 64] +
+                                                           (1.0 - th) * R[(15 + i) * 64])));
+            Rhs fk;
+            if (back) {
+                if (!(isfinite(yk[0]) && isfinite(yk[1]) && isfinite(yk[2]) && isfinite(yk[3]) &&
+                      isfinite(yk[4]) && yk[3] >= 0.0 && yk[3] < 1.0 && yk[1] > 0.0))
+                    return FAIL;
+                fk = ak_rhs(yk[1], yk[3], Ms, mus, a, cl);
+            } else {
+                double x13;
+                if (!before_lso(yk[0], yk[1], yk[2], yk[3], yk[4], Ms, &x13)) {
+                    *kw = s.node - 1;
+                    return END;
+                }
+                fk = ak_rhs_x(yk[1], x13, yk[3], Ms, mus, a, cl);
+            }
+            double* q = o + s.node * 10;
+            q[0] = yk[0]; q[1] = yk[1]; q[2] = yk[2]; q[3] = yk[3]; q[4] = yk[4];
+            q[5] = fk.dPhi; q[6] = fk.dnu; q[7] = fk.dgt; q[8] = fk.de; q[9] = fk.dal;
+            s.node += back ? -1 : 1;
+        }
+        if (last) {
+            *kw = K;
+            return END;
+        }
+#pragma unroll
+        for (int i = 0; i < 5; ++i) s.Y[i] = y1[i];
+        s.f = k7;
+        s.t = t1;
+        s.H = Hs * fmin(s.rej ? 1.0 : kFacMax, fac);
+        s.rej = 0;
+    }
+    return GO;
+}
+
+__device__ inline void save(const State& s, double* __restrict__ c)
+{
+    c[WC_OT] = s.t;
+    c[WC_OH] = s.H;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        c[WC_OY + i] = s.Y[i];
+        c[WC_OF + i] = comp(s.f, i);
+    }
+    c[WC_ONODE] = (double)s.node;
+    c[WC_OATT] = (double)s.att;
+    c[WC_OREJ] = (double)s.rej;
+}
+
+__device__ inline State load(const double* __restrict__ c)
+{
+    State s;
+    s.t = c[WC_OT];
+    s.H = c[WC_OH];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) s.Y[i] = c[WC_OY + i];
+    s.f = Rhs{c[WC_OF], c[WC_OF + 1], c[WC_OF + 2], c[WC_OF + 3], c[WC_OF + 4]};
+    s.node = (int64_t)c[WC_ONODE];
+    s.att = (int64_t)c[WC_OATT];
+    s.rej = (int)c[WC_OREJ];
+    return s;
+}
+
+// after segment seg: K_w as known, and the state for the next segment
+__device__ inline void finish_segment(int r, const State& s, int64_t kw, int seg,
+                                      double* __restrict__ c)
+{
+    if (r == FAIL) {
+        c[WC_VALID] = 0.0;
+        c[WC_KSEG + seg] = -1.0;
+        c[WC_KW] = -1.0;
+        c[WC_ODONE] = 1.0;
+        return;
+    }
+    const int64_t known = (r == END) ? kw : s.node - 1;
+    c[WC_KSEG + seg] = (double)known;
+    c[WC_KW] = (double)known;
+    c[WC_ODONE] = (r == END) ? 1.0 : 0.0;
+    save(s, c);
+}
+}  // namespace dp5
+
 // The orbit kernels run one lane per walker, a few waves for the whole batch,
 // beside the table and synthesis kernels of earlier segments: they raise
 // their waves' issue priority so those do not stretch the integration.
-__global__ void __launch_bounds__(64) k_walker_setup(const double* __restrict__ params, int64_t B,
-                                                     int64_t K, double h, double Ndt, GL8 gl,
-                                                     int64_t k1, int ic, double* __restrict__ wc,
-                                                     double* __restrict__ orb)
+template <int ODE>
+__device__ __forceinline__ void walker_setup(const double* __restrict__ params, int64_t B,
+                                             int64_t K, double h, double Ndt, const GL8& gl,
+                                             int64_t k1, int ic, double rtol, double atol,
+                                             double* __restrict__ wc, double* __restrict__ orb)
 {
     __builtin_amdgcn_s_setprio(3);
+    __shared__ double dense[ODE == EMRI_ODE_DP5 ? dp5::kLdsSlots * 64 : 1];   // DP5 only
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= B) return;
     const double* p = params + w * EMRI_NPAR;
@@ -246,7 +488,15 @@ __global__ void __launch_bounds__(64) k_walker_setup(const double* __restrict__ 
         double* q = o + K * 10;
         q[0] = p[5]; q[1] = nuL; q[2] = p[6]; q[3] = e0; q[4] = p[7];
         q[5] = f.dPhi; q[6] = f.dnu; q[7] = f.dgt; q[8] = f.de; q[9] = f.dal;
-        if (!rk4_back(p[5], nuL, p[6], e0, p[7], f, K, h, Ms, mus, a, cl, o)) return;
+        if constexpr (ODE == EMRI_ODE_DP5) {
+            dp5::State st{(double)K * h, -h, {p[5], nuL, p[6], e0, p[7]}, f, K - 1, 0, 0};
+            int64_t kw = -1;
+            if (dp5::advance(st, 0, K, h, true, rtol, atol, Ms, mus, a, cl, o, &kw,
+                             dense + threadIdx.x) != dp5::END)
+                return;
+        } else {
+            if (!rk4_back(p[5], nuL, p[6], e0, p[7], f, K, h, Ms, mus, a, cl, o)) return;
+        }
         c[WC_KSEG] = (double)K;
         c[WC_KW] = (double)K;
         c[WC_VALID] = 1.0;
@@ -257,14 +507,74 @@ __global__ void __launch_bounds__(64) k_walker_setup(const double* __restrict__ 
     Rhs f = ak_rhs(Y1, Y3, Ms, mus, a, cl);
     o[0] = Y0; o[1] = Y1; o[2] = Y2; o[3] = Y3; o[4] = Y4;
     o[5] = f.dPhi; o[6] = f.dnu; o[7] = f.dgt; o[8] = f.de; o[9] = f.dal;
-    const int64_t Kw = rk4_steps(Y0, Y1, Y2, Y3, Y4, f, 0, k1, h, Ms, mus, a, cl, o);
-    c[WC_KSEG] = (double)Kw;
-    c[WC_KW] = (double)Kw;
-    c[WC_VALID] = 1.0;
+    if constexpr (ODE == EMRI_ODE_DP5) {
+        dp5::State st{0.0, h, {Y0, Y1, Y2, Y3, Y4}, f, 1, 0, 0};
+        int64_t kw = -1;
+        const int r = dp5::advance(st, k1, K, h, false, rtol, atol, Ms, mus, a, cl, o, &kw,
+                                   dense + threadIdx.x);
+        if (r == dp5::FAIL) return;
+        c[WC_VALID] = 1.0;
+        dp5::finish_segment(r, st, kw, 0, c);
+    } else {
+        const int64_t Kw = rk4_steps(Y0, Y1, Y2, Y3, Y4, f, 0, k1, h, Ms, mus, a, cl, o);
+        c[WC_KSEG] = (double)Kw;
+        c[WC_KW] = (double)Kw;
+        c[WC_VALID] = 1.0;
+    }
+}
+
+// One kernel per integrator, each with its own register budget: the orbit
+// runs beside the synthesis waves of earlier segments and its waves must find
+// room between them.  The DP5 kernels are held to three waves per SIMD (168
+// VGPRs, some spills): without the limit they take about 230 and the orbit
+// stage, waiting for room, runs several times slower inside the pipeline.
+__global__ void __launch_bounds__(64) k_walker_setup(const double* __restrict__ params, int64_t B,
+                                                     int64_t K, double h, double Ndt, GL8 gl,
+                                                     int64_t k1, int ic, double* __restrict__ wc,
+                                                     double* __restrict__ orb)
+{
+    walker_setup<EMRI_ODE_RK4>(params, B, K, h, Ndt, gl, k1, ic, 0.0, 0.0, wc, orb);
+}
+
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
+k_walker_setup_dp5(const double* __restrict__ params,
+                                                         int64_t B, int64_t K, double h,
+                                                         double Ndt, GL8 gl, int64_t k1, int ic,
+                                                         double rtol, double atol,
+                                                         double* __restrict__ wc,
+                                                         double* __restrict__ orb)
+{
+    walker_setup<EMRI_ODE_DP5>(params, B, K, h, Ndt, gl, k1, ic, rtol, atol, wc, orb);
 }
 
 // orbit segment seg >= 1: steps [k0, k1) from node k0 (stored by segment
 // seg - 1), unless the orbit reached the LSO before k0
+// adaptive orbit segment seg >= 1: continues from the saved integrator state
+// until node k1 is filled (the step sequence does not depend on where the
+// segments end)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
+k_walker_resume_dp5(int64_t B, int64_t K, double h,
+                                                          int64_t k1, int seg, double rtol,
+                                                          double atol, double* __restrict__ wc,
+                                                          double* __restrict__ orb)
+{
+    __builtin_amdgcn_s_setprio(3);
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= B) return;
+    double* c = wc + w * WC;
+    if (c[WC_VALID] == 0.0) return;
+    if (c[WC_ODONE] != 0.0) {
+        c[WC_KSEG + seg] = c[WC_KW];
+        return;
+    }
+    dp5::State st = dp5::load(c);
+    int64_t kw = -1;
+    __shared__ double dense[dp5::kLdsSlots * 64];
+    const int r = dp5::advance(st, k1, K, h, false, rtol, atol, c[WC_MS], c[WC_MUS], c[WC_A],
+                               c[WC_CL], orb + w * (K + 1) * 10, &kw, dense + threadIdx.x);
+    dp5::finish_segment(r, st, kw, seg, c);
+}
+
 __global__ void __launch_bounds__(64) k_walker_resume(int64_t B, int64_t K, double h, int64_t k0,
                                                       int64_t k1, int seg,
                                                       double* __restrict__ wc,
@@ -511,9 +821,14 @@ hipError_t launch_walker_setup(const Plan& p, const double* params, int64_t B, v
     dim3 grid((unsigned)((B + 63) / 64));
     trace_mark(ST_SETUP, s, true);
     if (p.ic == EMRI_IC_LSO && k1 != p.K) return hipErrorInvalidValue;   // one segment only
-    hipLaunchKernelGGL(k_walker_setup, grid, dim3(64), 0, s, params, B, p.K, h,
-                       (double)p.N * p.dt, gl, k1, p.ic, (double*)(base + p.off_wc),
-                       (double*)(base + p.off_orb));
+    if (p.ode == EMRI_ODE_DP5)
+        hipLaunchKernelGGL(k_walker_setup_dp5, grid, dim3(64), 0, s, params, B, p.K, h,
+                           (double)p.N * p.dt, gl, k1, p.ic, p.rtol, p.atol,
+                           (double*)(base + p.off_wc), (double*)(base + p.off_orb));
+    else
+        hipLaunchKernelGGL(k_walker_setup, grid, dim3(64), 0, s, params, B, p.K, h,
+                           (double)p.N * p.dt, gl, k1, p.ic, (double*)(base + p.off_wc),
+                           (double*)(base + p.off_orb));
     trace_mark(ST_SETUP, s, false);
     return hipGetLastError();
 }
@@ -526,8 +841,12 @@ hipError_t launch_walker_resume(const Plan& p, int64_t B, void* ws, int64_t k0, 
     const double h = p.dt * (double)p.L;
     dim3 grid((unsigned)((B + 63) / 64));
     trace_mark(ST_SETUP, s, true);
-    hipLaunchKernelGGL(k_walker_resume, grid, dim3(64), 0, s, B, p.K, h, k0, k1, seg,
-                       (double*)(base + p.off_wc), (double*)(base + p.off_orb));
+    if (p.ode == EMRI_ODE_DP5)
+        hipLaunchKernelGGL(k_walker_resume_dp5, grid, dim3(64), 0, s, B, p.K, h, k1, seg, p.rtol,
+                           p.atol, (double*)(base + p.off_wc), (double*)(base + p.off_orb));
+    else
+        hipLaunchKernelGGL(k_walker_resume, grid, dim3(64), 0, s, B, p.K, h, k0, k1, seg,
+                           (double*)(base + p.off_wc), (double*)(base + p.off_orb));
     trace_mark(ST_SETUP, s, false);
     return hipGetLastError();
 }

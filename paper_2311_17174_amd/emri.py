@@ -22,6 +22,8 @@ MIXED = 1
 PRECISIONS = {"fp64": FP64, "mixed": MIXED}
 IC_START = 0     # initial conditions at t = 0
 IC_LSO = 1       # at the last stable orbit, integrated backward (the paper's convention)
+ODE_RK4 = 0      # classical RK4 on the coarse nodes
+ODE_DP5 = 1      # adaptive Dormand-Prince 5(4), continuous extension at the nodes
 
 EXPORTED = ("emri_abi_version", "emri_last_error", "emri_workspace_bytes",
             "emri_waveform_batch", "emri_fft_batch", "emri_loglike_batch",
@@ -40,7 +42,9 @@ class EmriError(RuntimeError):
 class _Cfg(ctypes.Structure):
     _fields_ = [("T_obs", ctypes.c_double), ("dt", ctypes.c_double), ("N", ctypes.c_int64),
                 ("n_harm", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("coarse_log2", ctypes.c_int32), ("ic", ctypes.c_int32)]
+                ("coarse_log2", ctypes.c_int32), ("ic", ctypes.c_int32),
+                ("ode", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("ode_rtol", ctypes.c_double), ("ode_atol", ctypes.c_double)]
 
 
 class _Prior(ctypes.Structure):
@@ -74,15 +78,19 @@ class Config:
     precision: int = FP64
     coarse_log2: int = 10
     ic: int = IC_START       # IC_LSO: the row's orbital state is at the LSO
+    ode: int = ODE_RK4       # ODE_DP5: adaptive integrator with the tolerances below
+    ode_rtol: float = 1e-12
+    ode_atol: float = 1e-12
 
     @staticmethod
     def from_workload(w) -> "Config":
         return Config(w.T_obs, w.dt, w.N, w.n_harm, PRECISIONS[w.precision], w.coarse_log2,
-                      w.ic)
+                      w.ic, w.ode, w.ode_rtol, w.ode_atol)
 
     def c(self) -> _Cfg:
         return _Cfg(float(self.T_obs), float(self.dt), int(self.N), int(self.n_harm),
-                    int(self.precision), int(self.coarse_log2), int(self.ic))
+                    int(self.precision), int(self.coarse_log2), int(self.ic), int(self.ode), 0,
+                    float(self.ode_rtol), float(self.ode_atol))
 
     @property
     def real_dtype(self) -> torch.dtype:

@@ -57,6 +57,9 @@ class Workload:
     walker_seed: int = 0
     noise_seed: int = 1
     ic: int = 0                       # 1: the orbital state of a row is at the LSO
+    ode: int = 0                      # 0: RK4 on the coarse nodes; 1: adaptive DP5(4)
+    ode_rtol: float = 1e-12           # tolerances of the adaptive integrator
+    ode_atol: float = 1e-12
 
     @property
     def n_valid(self) -> int:

@@ -19,7 +19,8 @@ def say(*a):
 
 def ocfg(w) -> O.OracleConfig:
     return O.OracleConfig(T_obs=w.T_obs, dt=w.dt, N=w.N, n_harm=w.n_harm,
-                          coarse_log2=w.coarse_log2, ic_lso=bool(w.ic))
+                          coarse_log2=w.coarse_log2, ic_lso=bool(w.ic), ode=w.ode,
+                          rtol=w.ode_rtol, atol=w.ode_atol)
 
 
 _DATA_CACHE: dict = {}
@@ -28,7 +29,7 @@ _DATA_CACHE: dict = {}
 def oracle_dataset(w, noise: bool = True):
     """(data[2][N/2+1] complex, psd[N/2+1]) for workload w, from the oracle."""
     key = (w.T_obs, w.dt, w.N, w.n_harm, w.coarse_log2, w.noise_seed, w.inj.tobytes(), noise,
-           w.ic)
+           w.ic, w.ode, w.ode_rtol, w.ode_atol)
     if key not in _DATA_CACHE:
         _DATA_CACHE[key] = _oracle_dataset(w, noise)
     return _DATA_CACHE[key]

@@ -38,13 +38,15 @@ def test_library_exports_every_declared_symbol(E):
     missing = [n for n in declared_functions() if n not in exported]
     assert not missing, missing
     assert set(E.EXPORTED) == set(declared_functions())
-    assert E.lib.emri_abi_version() == 4
+    assert E.lib.emri_abi_version() == 5
 
 
 def test_struct_layout_matches_header(E):
-    # int64 N at offset 16, then four int32: 40 bytes in total
-    assert ctypes.sizeof(E._Cfg) == 40
+    # int64 N at offset 16, six int32, then the two integrator tolerances: 64 bytes
+    assert ctypes.sizeof(E._Cfg) == 64
     assert E._Cfg.N.offset == 16 and E._Cfg.n_harm.offset == 24
+    assert E._Cfg.ode.offset == 40 and E._Cfg.reserved.offset == 44
+    assert E._Cfg.ode_rtol.offset == 48 and E._Cfg.ode_atol.offset == 56
     # emri_fmg: two int32 then the pivot frequency; emri_prior: n_free, idx[17], lo, hi
     assert ctypes.sizeof(E._Fmg) == 16 and E._Fmg.f_star.offset == 8
     assert E._Prior.idx.offset == 4 and E._Prior.lo.offset == 72
@@ -54,7 +56,10 @@ def test_struct_layout_matches_header(E):
 @pytest.mark.parametrize("bad", [
     dict(N=3 << 12), dict(N=1 << 11), dict(N=1 << 25), dict(dt=0.0), dict(T_obs=-1.0),
     dict(n_harm=0), dict(n_harm=65), dict(precision=2), dict(coarse_log2=7),
-    dict(coarse_log2=13), dict(T_obs=1e7),
+    dict(coarse_log2=13), dict(T_obs=1e7), dict(ode=2), dict(ode=-1),
+    dict(ode=1, ode_rtol=0.0), dict(ode=1, ode_rtol=1e-14), dict(ode=1, ode_rtol=1e-2),
+    dict(ode=1, ode_rtol=float("nan")), dict(ode=1, ode_atol=-1e-12),
+    dict(ode=1, ode_atol=float("inf")),
 ])
 def test_invalid_configurations_are_rejected(E, bad):
     base = dict(T_obs=2.5 * 86400, dt=10.0, N=1 << 15, n_harm=8, precision=0, coarse_log2=10)
@@ -62,6 +67,16 @@ def test_invalid_configurations_are_rejected(E, bad):
     c = E.Config(**base)
     assert E.lib.emri_workspace_bytes(ctypes.byref(c.c()), 4) == 0
     assert E.lib.emri_dataset_bytes(ctypes.byref(c.c())) == 0
+
+
+def test_reserved_field_and_ignored_tolerances(E):
+    c = E.Config(T_obs=2.5 * 86400, dt=10.0, N=1 << 15, n_harm=8).c()
+    assert E.lib.emri_workspace_bytes(ctypes.byref(c), 4) > 0
+    c.reserved = 1
+    assert E.lib.emri_workspace_bytes(ctypes.byref(c), 4) == 0
+    c.reserved = 0
+    c.ode_rtol = -1.0                  # RK4 ignores the tolerances
+    assert E.lib.emri_workspace_bytes(ctypes.byref(c), 4) > 0
 
 
 def test_workspace_grows_with_batch_and_precision(E):

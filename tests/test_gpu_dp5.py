@@ -1,0 +1,151 @@
+"""GPU parity of the adaptive orbit integrator (emri_cfg.ode = EMRI_ODE_DP5:
+the Dormand-Prince 5(4) pair with step control, sampled at the coarse nodes
+by its continuous extension) through the C ABI, against the CPU oracle.
+Tolerances as for the RK4 path: the two sides run the same steps, so they
+differ by rounding alone."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2311_17174_amd import workloads as W
+from tests.gpu_common import EPS64, max_phase, ocfg, oracle_dataset, say, to_device_data
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_2311_17174_amd import emri
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return emri
+
+
+def dp5(w, rtol=1e-12):
+    return w.with_(ode=1, ode_rtol=rtol, ode_atol=rtol)
+
+
+def gpu(P):
+    return torch.from_numpy(np.ascontiguousarray(P)).cuda()
+
+
+def fast_inspiral(prec):
+    """M = 1e5: reaches the LSO mid-window; coarse step 2560 s, 675 nodes."""
+    w = W.small(prec, n_harm=6, days=20.0, N=1 << 18, M=1e5, e0=0.5, a=0.9, nu0=6.3e-3)
+    return w.with_(coarse_log2=8)
+
+
+def edge_rows(w):
+    P = list(W.walkers(w, B=3))
+    p = w.inj.copy(); p[3] = 0.0; P.append(p)              # circular: e stays 0
+    p = w.inj.copy(); p[1] = 2e6; P.append(p)              # mu > M: invalid
+    p = w.inj.copy(); p[4] = 1.0; P.append(p)              # starts past the LSO
+    return np.array(P)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("rtol", [1e-6, 1e-12])
+def test_dp5_waveform_parity(E, prec, rtol):
+    """rtol 1e-6 takes rejected steps; both plunge mid-window."""
+    w = dp5(fast_inspiral(prec), rtol)
+    P = edge_rows(w)
+    _, kw = O.orbit(P, ocfg(w))
+    steps = O.orbit_steps(P, ocfg(w))
+    say("DP5", prec, rtol, "plunge nodes", kw, "of", w.n_intervals, "steps", steps.tolist())
+    assert np.all(kw[:3] < w.n_intervals - 8) and kw[3] == w.n_intervals
+    assert kw[4] == kw[5] == -1
+    if rtol == 1e-6:
+        assert steps[0, 1] > 0
+    got = E.waveform_batch(gpu(P), E.Config.from_workload(w)).cpu().numpy().astype(np.float64)
+    got = got.transpose(0, 2, 1)
+    ref = O.waveform(P, ocfg(w))
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(got - ref), axis=(1, 2)) / scale
+    say("max rel err per walker", err)
+    tol = 64 * w.n_harm * max_phase(w, P[:4]) * EPS64 if prec == "fp64" else 2e-5
+    assert np.all(err <= tol), (err, tol)
+    assert np.all(got[4] == 0.0) and np.all(got[5] == 0.0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_dp5_loglike_parity(E, prec):
+    """30 days at 2^18 samples: a handful of steps of about 50 nodes each."""
+    w = dp5(W.config1().with_(n_harm=6, precision=prec), 1e-10)
+    P = np.concatenate([W.walkers(w, B=6), edge_rows(w)[3:]])
+    d, S = oracle_dataset(w, True)
+    ref = O.loglike(P, d, S, ocfg(w))
+    dd, ss = to_device_data(d, S)
+    got = E.loglike_batch(gpu(P), dd, ss, E.Config.from_workload(w)).cpu().numpy()
+    say("lnL ref", ref, "got", got)
+    fin = np.isfinite(ref)
+    assert list(np.where(~fin)[0]) == [7, 8]
+    assert np.array_equal(fin, np.isfinite(got))
+    rel = np.abs(got[fin] - ref[fin]) / np.abs(ref[fin])
+    assert np.all(rel <= (1e-10 if prec == "fp64" else 1e-4)), rel
+
+
+def test_dp5_lso_convention(E):
+    """Backward from the LSO, one segment; an unphysical history is invalid."""
+    w = dp5(W.small("fp64", n_harm=6, days=20.0, N=1 << 18).with_(ic=1), 1e-10)
+    P = list(W.walkers(w, B=4))
+    P.append(W.injection(M=1e5, e0=0.8))
+    P.append(W.injection(M=2e4, mu=10.0, e0=0.7))
+    P = np.array(P)
+    _, kw = O.orbit(P, ocfg(w))
+    assert list(kw[:5]) == [w.n_intervals] * 5 and kw[5] == -1
+    d, S = oracle_dataset(w, True)
+    ref = O.loglike(P, d, S, ocfg(w))
+    dd, ss = to_device_data(d, S)
+    got = E.loglike_batch(gpu(P), dd, ss, E.Config.from_workload(w)).cpu().numpy()
+    say("LSO lnL ref", ref, "got", got)
+    assert got[5] == -np.inf and np.all(np.isfinite(got[:5]))
+    rel = np.abs(got[:5] - ref[:5]) / np.abs(ref[:5])
+    assert np.all(rel <= 1e-10), rel
+
+
+@pytest.mark.parametrize("segs", [3, 7])
+def test_dp5_segments_bitwise(E, monkeypatch, segs):
+    """The step sequence does not depend on where orbit segments end: the
+    waveform in segments equals the one-segment waveform bit for bit (with
+    rejected steps, steps spanning segment ends and a plunge)."""
+    w = dp5(fast_inspiral("fp64"), 1e-6)
+    P = edge_rows(w)
+    cfg = E.Config.from_workload(w)
+    monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", "1")
+    one = E.waveform_batch(gpu(P), cfg).cpu().numpy()
+    monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", str(segs))
+    for _ in range(2):
+        assert np.array_equal(E.waveform_batch(gpu(P), cfg).cpu().numpy(), one)
+
+
+def test_dp5_close_to_rk4(E):
+    """At rtol 1e-12 the likelihood moves from the RK4 path's by far less than
+    one unit (both are accurate discretisations of Eq. (1))."""
+    w = W.config1()
+    P = W.walkers(w, B=16)
+    d, S = oracle_dataset(w, True)
+    dd, ss = to_device_data(d, S)
+    a = E.loglike_batch(gpu(P), dd, ss, E.Config.from_workload(w)).cpu().numpy()
+    b = E.loglike_batch(gpu(P), dd, ss, E.Config.from_workload(dp5(w))).cpu().numpy()
+    say("RK4 - DP5", np.max(np.abs(a - b)))
+    assert np.max(np.abs(a - b)) < 1e-3 and not np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_dp5_config2_sampled_parity(E, prec):
+    """B=256, 1 yr, 2^22 samples, 30 harmonics in the benchmark's launch
+    configuration (orbit segments on); the oracle checks sampled walkers."""
+    base = W.config2() if prec == "fp64" else W.config3()
+    w = dp5(base)
+    P = W.walkers(w)
+    d, S = oracle_dataset(dp5(W.config2()), True)
+    dd, ss = to_device_data(d, S)
+    got = E.loglike_batch(gpu(P), dd, ss, E.Config.from_workload(w)).cpu().numpy()
+    assert np.all(np.isfinite(got))
+    idx = np.array([3, 254])
+    say("DP5 config2 oracle lnL for", idx)
+    ref = O.loglike(P[idx], d, S, ocfg(w))
+    rel = np.abs(got[idx] - ref) / np.abs(ref)
+    say(prec, "rel err", rel)
+    assert np.all(rel <= (1e-10 if prec == "fp64" else 1e-4))

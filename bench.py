@@ -280,33 +280,38 @@ def run_fmg(E, W, w, data, psd, steps: int, warmup: int):
 def run_dp5(E, W, w, data, psd, steps: int, warmup: int, rtol: float = 1e-12):
     """The adaptive orbit integrator (Dormand-Prince 5(4), tolerance rtol,
     continuous extension at the coarse nodes) against the classical RK4 path,
-    on the same walkers and resident data as the main line."""
+    on the same walkers and resident data as the main line, with the state at
+    t = 0 (orbit-segment pipeline) and at the LSO (one backward segment)."""
     import torch
     P = torch.from_numpy(W.walkers(w)).cuda()
     out = torch.empty(w.B, dtype=torch.float64, device="cuda")
     res = {}
     lnl = {}
-    for name, wk in (("rk4", w), ("dp5", w.with_(ode=1, ode_rtol=rtol, ode_atol=rtol))):
-        cfg = E.Config.from_workload(wk)
-        ds = E.dataset_init(data, psd, cfg)
-        ws = E.alloc_workspace(cfg, w.B)
-        for _ in range(warmup):
-            E.loglike_dataset(P, ds, cfg, out=out, ws=ws)
-        torch.cuda.synchronize()
-        with E.Tracer() as tr:
-            t0 = time.perf_counter()
-            for _ in range(steps):
+    for ic, tag in ((0, ""), (1, "_lso")):
+        for name, wk in (("rk4", w), ("dp5", w.with_(ode=1, ode_rtol=rtol, ode_atol=rtol))):
+            cfg = E.Config.from_workload(wk.with_(ic=ic))
+            ds = E.dataset_init(data, psd, cfg)
+            ws = E.alloc_workspace(cfg, w.B)
+            for _ in range(warmup):
                 E.loglike_dataset(P, ds, cfg, out=out, ws=ws)
             torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            st = tr.read()
-        lnl[name] = out.cpu().numpy().copy()
-        res[name] = {"value": steps * w.B / (t1 - t0), "ms_per_step": 1e3 * (t1 - t0) / steps,
-                     "orbit_ms_per_step": st["walker_setup"][0] / steps}
-        del ds, ws
+            with E.Tracer() as tr:
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    E.loglike_dataset(P, ds, cfg, out=out, ws=ws)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                st = tr.read()
+            lnl[name + tag] = out.cpu().numpy().copy()
+            res[name + tag] = {"value": steps * w.B / (t1 - t0),
+                               "ms_per_step": 1e3 * (t1 - t0) / steps,
+                               "orbit_ms_per_step": st["walker_setup"][0] / steps}
+            del ds, ws
     res.update({"unit": "lnL evals/s", "workload": w.name, "rtol": rtol, "atol": rtol,
                 "max_abs_dlnL_vs_rk4": float(np.max(np.abs(lnl["dp5"] - lnl["rk4"]))),
-                "orbit_speedup": res["rk4"]["orbit_ms_per_step"] / res["dp5"]["orbit_ms_per_step"]})
+                "orbit_speedup": res["rk4"]["orbit_ms_per_step"] / res["dp5"]["orbit_ms_per_step"],
+                "orbit_speedup_lso": (res["rk4_lso"]["orbit_ms_per_step"]
+                                      / res["dp5_lso"]["orbit_ms_per_step"])})
     return res
 
 
@@ -553,7 +558,9 @@ def main():
         dp5 = {"fp64": run_dp5(E, W, w64, data, psd, max(2, args.steps // 2), 1),
                "mixed": run_dp5(E, W, wmx, data, psd, max(2, args.steps // 2), 1)}
         print(f"[bench] adaptive orbit: fp64 {dp5['fp64']['dp5']['value']:.1f} evals/s (orbit "
-              f"{dp5['fp64']['orbit_speedup']:.2f}x faster than RK4), mixed "
+              f"{dp5['fp64']['orbit_speedup']:.2f}x faster than RK4; LSO convention "
+              f"{dp5['fp64']['dp5_lso']['value']:.1f} evals/s, orbit "
+              f"{dp5['fp64']['orbit_speedup_lso']:.2f}x), mixed "
               f"{dp5['mixed']['dp5']['value']:.1f} evals/s", file=sys.stderr, flush=True)
 
     serving = None

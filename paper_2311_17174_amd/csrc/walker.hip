@@ -215,12 +215,16 @@ __device__ inline double comp(const Rhs& r, int i)
 // down to stop).  END: the orbit is complete, *kw its last node (forward:
 // the last before the LSO); FAIL: budget exhausted, or (backward) a node
 // outside the physical range
-// R: this lane's kLdsSlots LDS slots of the continuous extension, stride 64
+// Run by all 64 lanes of a wave for one walker: every lane takes the same
+// steps (the state is the same in each); the nodes of an accepted step are
+// shared out over the lanes.  R: this lane's kLdsSlots LDS slots of the
+// continuous extension, stride 64.
 constexpr int kLdsSlots = 20;
 __device__ int advance(State& s, int64_t stop, int64_t K, double hc, bool back, double rtol,
                        double atol, double Ms, double mus, double a, double cl,
                        double* __restrict__ o, int64_t* kw, double* __restrict__ R)
 {
+    const int lane = threadIdx.x;
     const double t_end = back ? 0.0 : (double)K * hc;
     const int64_t budget = 4 * K + 64;
     while (back ? s.node >= stop : s.node <= stop) {
@@ -314,34 +318,50 @@ __device__ int advance(State& s, int64_t stop, int64_t K, double hc, bool back, 
             R[(2 * 5 + i) * 64] = r2 - Hs * comp(k7, i) - r3;
             R[(3 * 5 + i) * 64] = Hs * (sD[i] + D7 * comp(k7, i));
         }
-        while (back ? (s.node >= 0 && (double)s.node * hc >= t1)
-                    : (s.node <= K && (double)s.node * hc <= t1)) {
-            const double th = ((double)s.node * hc - s.t) / Hs;
-            double yk[5];
+        // the nodes in (t, t1], 64 at a time: lane l takes the l-th; they
+        // form a prefix of the lanes (the node times increase with l)
+        for (;;) {
+            const int64_t n = back ? s.node - lane : s.node + lane;
+            const bool inside = back ? (n >= 0 && (double)n * hc >= t1)
+                                     : (n <= K && (double)n * hc <= t1);
+            const uint64_t in_mask = __ballot(inside);
+            if (in_mask == 0) break;
+            double yk[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            double x13 = 0.0;
+            bool bad = false;
+            if (inside) {
+                const double th = ((double)n * hc - s.t) / Hs;
 #pragma unroll
-            for (int i = 0; i < 5; ++i)
-                yk[i] = s.Y[i] + th * (R[i * 64] +
-                                       (1.0 - th) * (R[(5 + i) * 64] +
-                                                     th * (R[(10 + i) * 64] +
-                                                           (1.0 - th) * R[(15 + i) * 64])));
-            Rhs fk;
-            if (back) {
-                if (!(isfinite(yk[0]) && isfinite(yk[1]) && isfinite(yk[2]) && isfinite(yk[3]) &&
-                      isfinite(yk[4]) && yk[3] >= 0.0 && yk[3] < 1.0 && yk[1] > 0.0))
-                    return FAIL;
-                fk = ak_rhs(yk[1], yk[3], Ms, mus, a, cl);
-            } else {
-                double x13;
-                if (!before_lso(yk[0], yk[1], yk[2], yk[3], yk[4], Ms, &x13)) {
-                    *kw = s.node - 1;
-                    return END;
-                }
-                fk = ak_rhs_x(yk[1], x13, yk[3], Ms, mus, a, cl);
+                for (int i = 0; i < 5; ++i)
+                    yk[i] = s.Y[i] + th * (R[i * 64] +
+                                           (1.0 - th) * (R[(5 + i) * 64] +
+                                                         th * (R[(10 + i) * 64] +
+                                                               (1.0 - th) * R[(15 + i) * 64])));
+                if (back)
+                    bad = !(isfinite(yk[0]) && isfinite(yk[1]) && isfinite(yk[2]) &&
+                            isfinite(yk[3]) && isfinite(yk[4]) && yk[3] >= 0.0 && yk[3] < 1.0 &&
+                            yk[1] > 0.0);
+                else
+                    bad = !before_lso(yk[0], yk[1], yk[2], yk[3], yk[4], Ms, &x13);
             }
-            double* q = o + s.node * 10;
-            q[0] = yk[0]; q[1] = yk[1]; q[2] = yk[2]; q[3] = yk[3]; q[4] = yk[4];
-            q[5] = fk.dPhi; q[6] = fk.dnu; q[7] = fk.dgt; q[8] = fk.de; q[9] = fk.dal;
-            s.node += back ? -1 : 1;
+            const uint64_t bad_mask = __ballot(inside && bad);
+            if (back && bad_mask) return FAIL;
+            const int nin = __popcll(in_mask);
+            // forward: the nodes before the first one past the LSO
+            const int nok = bad_mask ? __ffsll((unsigned long long)bad_mask) - 1 : nin;
+            if (lane < nok) {
+                const Rhs fk = back ? ak_rhs(yk[1], yk[3], Ms, mus, a, cl)
+                                    : ak_rhs_x(yk[1], x13, yk[3], Ms, mus, a, cl);
+                double* q = o + n * 10;
+                q[0] = yk[0]; q[1] = yk[1]; q[2] = yk[2]; q[3] = yk[3]; q[4] = yk[4];
+                q[5] = fk.dPhi; q[6] = fk.dnu; q[7] = fk.dgt; q[8] = fk.de; q[9] = fk.dal;
+            }
+            if (bad_mask) {
+                *kw = s.node + nok - 1;
+                return END;
+            }
+            s.node += back ? -nin : nin;
+            if (nin < 64) break;
         }
         if (last) {
             *kw = K;
@@ -414,7 +434,6 @@ __device__ __forceinline__ void walker_setup(const double* __restrict__ params, 
                                              double* __restrict__ wc, double* __restrict__ orb)
 {
     __builtin_amdgcn_s_setprio(3);
-    __shared__ double dense[ODE == EMRI_ODE_DP5 ? dp5::kLdsSlots * 64 : 1];   // DP5 only
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= B) return;
     const double* p = params + w * EMRI_NPAR;
@@ -489,11 +508,12 @@ __device__ __forceinline__ void walker_setup(const double* __restrict__ params, 
         q[0] = p[5]; q[1] = nuL; q[2] = p[6]; q[3] = e0; q[4] = p[7];
         q[5] = f.dPhi; q[6] = f.dnu; q[7] = f.dgt; q[8] = f.de; q[9] = f.dal;
         if constexpr (ODE == EMRI_ODE_DP5) {
-            dp5::State st{(double)K * h, -h, {p[5], nuL, p[6], e0, p[7]}, f, K - 1, 0, 0};
-            int64_t kw = -1;
-            if (dp5::advance(st, 0, K, h, true, rtol, atol, Ms, mus, a, cl, o, &kw,
-                             dense + threadIdx.x) != dp5::END)
-                return;
+            // the integration itself is k_orbit_dp5's (one wave per walker)
+            dp5::save(dp5::State{(double)K * h, -h, {p[5], nuL, p[6], e0, p[7]}, f, K - 1, 0, 0},
+                      c);
+            c[WC_ODONE] = 0.0;
+            c[WC_VALID] = 1.0;
+            return;
         } else {
             if (!rk4_back(p[5], nuL, p[6], e0, p[7], f, K, h, Ms, mus, a, cl, o)) return;
         }
@@ -508,13 +528,9 @@ __device__ __forceinline__ void walker_setup(const double* __restrict__ params, 
     o[0] = Y0; o[1] = Y1; o[2] = Y2; o[3] = Y3; o[4] = Y4;
     o[5] = f.dPhi; o[6] = f.dnu; o[7] = f.dgt; o[8] = f.de; o[9] = f.dal;
     if constexpr (ODE == EMRI_ODE_DP5) {
-        dp5::State st{0.0, h, {Y0, Y1, Y2, Y3, Y4}, f, 1, 0, 0};
-        int64_t kw = -1;
-        const int r = dp5::advance(st, k1, K, h, false, rtol, atol, Ms, mus, a, cl, o, &kw,
-                                   dense + threadIdx.x);
-        if (r == dp5::FAIL) return;
+        dp5::save(dp5::State{0.0, h, {Y0, Y1, Y2, Y3, Y4}, f, 1, 0, 0}, c);
+        c[WC_ODONE] = 0.0;
         c[WC_VALID] = 1.0;
-        dp5::finish_segment(r, st, kw, 0, c);
     } else {
         const int64_t Kw = rk4_steps(Y0, Y1, Y2, Y3, Y4, f, 0, k1, h, Ms, mus, a, cl, o);
         c[WC_KSEG] = (double)Kw;
@@ -523,11 +539,9 @@ __device__ __forceinline__ void walker_setup(const double* __restrict__ params, 
     }
 }
 
-// One kernel per integrator, each with its own register budget: the orbit
-// runs beside the synthesis waves of earlier segments and its waves must find
-// room between them.  The DP5 kernels are held to three waves per SIMD (168
-// VGPRs, some spills): without the limit they take about 230 and the orbit
-// stage, waiting for room, runs several times slower inside the pipeline.
+// One set of kernels per integrator, each with its own register budget: the
+// orbit runs beside the synthesis waves of earlier segments and its waves
+// must find room between them (the RK4 kernels hold 130 and 110 VGPRs).
 __global__ void __launch_bounds__(64) k_walker_setup(const double* __restrict__ params, int64_t B,
                                                      int64_t K, double h, double Ndt, GL8 gl,
                                                      int64_t k1, int ic, double* __restrict__ wc,
@@ -536,45 +550,48 @@ __global__ void __launch_bounds__(64) k_walker_setup(const double* __restrict__ 
     walker_setup<EMRI_ODE_RK4>(params, B, K, h, Ndt, gl, k1, ic, 0.0, 0.0, wc, orb);
 }
 
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
-k_walker_setup_dp5(const double* __restrict__ params,
+// constants and the adaptive integrator's starting state (one lane per
+// walker); the integration is k_orbit_dp5's
+__global__ void __launch_bounds__(64) k_walker_setup_dp5(const double* __restrict__ params,
                                                          int64_t B, int64_t K, double h,
-                                                         double Ndt, GL8 gl, int64_t k1, int ic,
-                                                         double rtol, double atol,
+                                                         double Ndt, GL8 gl, int ic,
                                                          double* __restrict__ wc,
                                                          double* __restrict__ orb)
 {
-    walker_setup<EMRI_ODE_DP5>(params, B, K, h, Ndt, gl, k1, ic, rtol, atol, wc, orb);
+    walker_setup<EMRI_ODE_DP5>(params, B, K, h, Ndt, gl, K, ic, 0.0, 0.0, wc, orb);
 }
 
-// orbit segment seg >= 1: steps [k0, k1) from node k0 (stored by segment
-// seg - 1), unless the orbit reached the LSO before k0
-// adaptive orbit segment seg >= 1: continues from the saved integrator state
-// until node k1 is filled (the step sequence does not depend on where the
-// segments end)
+// adaptive orbit segment seg: one wave per walker continues from the saved
+// integrator state until node k1 is filled (backward: down to node 0), so
+// the step sequence does not depend on where the segments end.  Every lane
+// of the wave takes the same steps; the nodes of an accepted step are
+// shared out over the lanes.  The waves are held to three per SIMD (168
+// VGPRs, some spills): they start beside the synthesis waves of earlier
+// segments and wait for room on a SIMD, and with about 230 VGPRs they waited
+// several times longer.
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
-k_walker_resume_dp5(int64_t B, int64_t K, double h,
-                                                          int64_t k1, int seg, double rtol,
-                                                          double atol, double* __restrict__ wc,
-                                                          double* __restrict__ orb)
+k_orbit_dp5(int64_t K, double h, int64_t k1, int seg, int back, double rtol, double atol,
+            double* __restrict__ wc, double* __restrict__ orb)
 {
     __builtin_amdgcn_s_setprio(3);
-    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= B) return;
+    __shared__ double dense[dp5::kLdsSlots * 64];
+    const int64_t w = blockIdx.x;
     double* c = wc + w * WC;
-    if (c[WC_VALID] == 0.0) return;
+    if (c[WC_VALID] == 0.0) return;                  // the same in every lane
     if (c[WC_ODONE] != 0.0) {
-        c[WC_KSEG + seg] = c[WC_KW];
+        if (threadIdx.x == 0) c[WC_KSEG + seg] = c[WC_KW];
         return;
     }
     dp5::State st = dp5::load(c);
     int64_t kw = -1;
-    __shared__ double dense[dp5::kLdsSlots * 64];
-    const int r = dp5::advance(st, k1, K, h, false, rtol, atol, c[WC_MS], c[WC_MUS], c[WC_A],
-                               c[WC_CL], orb + w * (K + 1) * 10, &kw, dense + threadIdx.x);
-    dp5::finish_segment(r, st, kw, seg, c);
+    const int r = dp5::advance(st, back ? 0 : k1, K, h, back != 0, rtol, atol, c[WC_MS],
+                               c[WC_MUS], c[WC_A], c[WC_CL], orb + w * (K + 1) * 10, &kw,
+                               dense + threadIdx.x);
+    if (threadIdx.x == 0) dp5::finish_segment(r, st, kw, seg, c);
 }
 
+// orbit segment seg >= 1 (RK4): steps [k0, k1) from node k0 (stored by
+// segment seg - 1), unless the orbit reached the LSO before k0
 __global__ void __launch_bounds__(64) k_walker_resume(int64_t B, int64_t K, double h, int64_t k0,
                                                       int64_t k1, int seg,
                                                       double* __restrict__ wc,
@@ -821,11 +838,15 @@ hipError_t launch_walker_setup(const Plan& p, const double* params, int64_t B, v
     dim3 grid((unsigned)((B + 63) / 64));
     trace_mark(ST_SETUP, s, true);
     if (p.ic == EMRI_IC_LSO && k1 != p.K) return hipErrorInvalidValue;   // one segment only
-    if (p.ode == EMRI_ODE_DP5)
+    if (p.ode == EMRI_ODE_DP5) {
         hipLaunchKernelGGL(k_walker_setup_dp5, grid, dim3(64), 0, s, params, B, p.K, h,
-                           (double)p.N * p.dt, gl, k1, p.ic, p.rtol, p.atol,
-                           (double*)(base + p.off_wc), (double*)(base + p.off_orb));
-    else
+                           (double)p.N * p.dt, gl, p.ic, (double*)(base + p.off_wc),
+                           (double*)(base + p.off_orb));
+        if (B > 0)
+            hipLaunchKernelGGL(k_orbit_dp5, dim3((unsigned)B), dim3(64), 0, s, p.K, h, k1, 0,
+                               p.ic == EMRI_IC_LSO ? 1 : 0, p.rtol, p.atol,
+                               (double*)(base + p.off_wc), (double*)(base + p.off_orb));
+    } else
         hipLaunchKernelGGL(k_walker_setup, grid, dim3(64), 0, s, params, B, p.K, h,
                            (double)p.N * p.dt, gl, k1, p.ic, (double*)(base + p.off_wc),
                            (double*)(base + p.off_orb));
@@ -841,10 +862,12 @@ hipError_t launch_walker_resume(const Plan& p, int64_t B, void* ws, int64_t k0, 
     const double h = p.dt * (double)p.L;
     dim3 grid((unsigned)((B + 63) / 64));
     trace_mark(ST_SETUP, s, true);
-    if (p.ode == EMRI_ODE_DP5)
-        hipLaunchKernelGGL(k_walker_resume_dp5, grid, dim3(64), 0, s, B, p.K, h, k1, seg, p.rtol,
-                           p.atol, (double*)(base + p.off_wc), (double*)(base + p.off_orb));
-    else
+    if (p.ode == EMRI_ODE_DP5) {
+        if (B > 0)
+            hipLaunchKernelGGL(k_orbit_dp5, dim3((unsigned)B), dim3(64), 0, s, p.K, h, k1, seg,
+                               0, p.rtol, p.atol, (double*)(base + p.off_wc),
+                               (double*)(base + p.off_orb));
+    } else
         hipLaunchKernelGGL(k_walker_resume, grid, dim3(64), 0, s, B, p.K, h, k0, k1, seg,
                            (double*)(base + p.off_wc), (double*)(base + p.off_orb));
     trace_mark(ST_SETUP, s, false);

@@ -123,6 +123,32 @@ def test_served_lso_dataset(E):
     assert st["graph_launches"] >= 1
 
 
+@pytest.mark.parametrize("ic", [0, 1])
+def test_served_adaptive_orbit(E, monkeypatch, ic):
+    """Data sets whose orbits use the adaptive integrator (one wave per
+    walker, lanes sharing each step's nodes; at t = 0 in three pipelined
+    segments, or backward from the LSO) served eagerly, captured and replayed:
+    bitwise the walkers evaluated alone, which agree with the oracle."""
+    monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", "3")
+    w = W.small("fp64", n_harm=6, days=20.0, N=1 << 18).with_(ic=ic, ode=1, ode_rtol=1e-10,
+                                                              ode_atol=1e-10)
+    d, S = oracle_dataset(w, True)
+    dd, ss = to_device_data(d, S)
+    cfg = E.Config.from_workload(w)
+    P = W.walkers(w, B=9, seed=7)
+    ref = O.loglike(P, d, S, ocfg(w))
+    expect = alone(E, cfg, dd, ss, P)
+    assert np.all(np.abs(expect - ref) <= 1e-10 * np.abs(ref))
+    arena = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    with E.Server(arena, n_streams=2, max_batch=32, use_graphs=True) as srv:
+        i = srv.add_dataset(dd, ss, cfg)
+        for _ in range(3):                          # eager, captured, replayed
+            got, _ = srv.wait(srv.submit(i, P), timeout=120.0)
+            assert np.array_equal(got, expect)
+        st = srv.stats()
+    assert st["graph_launches"] >= 1
+
+
 def test_admission_by_footprint(E):
     """An arena that holds one batch block at a time still serves every
     request (admission waits for memory); a request larger than the budget is

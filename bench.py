@@ -454,7 +454,7 @@ def main():
                          "HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for {args.gpus}); the "
+        print(f"bench.py: this benchmark measures one GPU only (asked for {args.gpus}); the "
               "likelihood batch is independent per walker and is not sharded here.",
               file=sys.stderr)
         sys.exit(2)

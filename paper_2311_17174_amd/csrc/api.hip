@@ -154,6 +154,12 @@ emri_status make_plan(const emri_cfg* cfg, int64_t B, Plan* p, const char** err)
     // 2^12 so a row transform has 512 lanes; columns the rest (up to 2^12)
     q.m1 = (m + 1) / 2 + 1;
     if (q.m1 > 12) q.m1 = 12;
+    // EMRI_FFT_M1 overrides the row length 2^m1 (for tuning), within the
+    // ranges both passes support
+    if (const char* env = getenv("EMRI_FFT_M1")) {
+        const int v = atoi(env);
+        if (v >= 7 && v <= 12 && m - v >= 4 && m - v <= 12) q.m1 = v;
+    }
     q.m2 = m - q.m1;
     q.R1 = (int64_t)1 << q.m1;
     q.R2 = (int64_t)1 << q.m2;

@@ -149,3 +149,26 @@ def test_dp5_config2_sampled_parity(E, prec):
     rel = np.abs(got[idx] - ref) / np.abs(ref)
     say(prec, "rel err", rel)
     assert np.all(rel <= (1e-10 if prec == "fp64" else 1e-4))
+
+
+def test_dp5_batch_invariance_chunking_and_paths(E):
+    """Per-walker results do not depend on the batch (permuted, split,
+    chunked through a small workspace) nor on the entry point (resident data
+    set); the model of an invalid walker is zero."""
+    w = dp5(W.small("fp64", n_harm=6, days=20.0, N=1 << 18), 1e-10)
+    P = np.concatenate([W.walkers(w, B=11), edge_rows(w)[4:5]])       # last: invalid
+    d, S = oracle_dataset(w, True)
+    cfg = E.Config.from_workload(w)
+    dd, ss = to_device_data(d, S)
+    full = E.loglike_batch(gpu(P), dd, ss, cfg).cpu().numpy()
+    assert full[-1] == -np.inf and np.all(np.isfinite(full[:-1]))
+    perm = np.random.Generator(np.random.PCG64(3)).permutation(len(P))
+    assert np.array_equal(E.loglike_batch(gpu(P[perm]), dd, ss, cfg).cpu().numpy(), full[perm])
+    assert np.array_equal(E.loglike_batch(gpu(P[2:5]), dd, ss, cfg).cpu().numpy(), full[2:5])
+    n = E.dataset_bytes(cfg) + 256 + E.workspace_bytes(cfg, 5)        # 3 chunks
+    ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+    assert np.array_equal(E.loglike_batch(gpu(P), dd, ss, cfg, ws=ws).cpu().numpy(), full)
+    ds = E.dataset_init(dd, ss, cfg)
+    assert np.array_equal(E.loglike_dataset(gpu(P), ds, cfg).cpu().numpy(), full)
+    m = E.model_batch(gpu(P[-2:]), cfg).cpu().numpy()
+    assert np.all(m[1] == 0) and np.any(m[0] != 0)

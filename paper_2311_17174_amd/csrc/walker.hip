@@ -430,8 +430,8 @@ __device__ inline void finish_segment(int r, const State& s, int64_t kw, int seg
 template <int ODE>
 __device__ __forceinline__ void walker_setup(const double* __restrict__ params, int64_t B,
                                              int64_t K, double h, double Ndt, const GL8& gl,
-                                             int64_t k1, int ic, double rtol, double atol,
-                                             double* __restrict__ wc, double* __restrict__ orb)
+                                             int64_t k1, int ic, double* __restrict__ wc,
+                                             double* __restrict__ orb)
 {
     __builtin_amdgcn_s_setprio(3);
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -547,7 +547,7 @@ __global__ void __launch_bounds__(64) k_walker_setup(const double* __restrict__ 
                                                      int64_t k1, int ic, double* __restrict__ wc,
                                                      double* __restrict__ orb)
 {
-    walker_setup<EMRI_ODE_RK4>(params, B, K, h, Ndt, gl, k1, ic, 0.0, 0.0, wc, orb);
+    walker_setup<EMRI_ODE_RK4>(params, B, K, h, Ndt, gl, k1, ic, wc, orb);
 }
 
 // constants and the adaptive integrator's starting state (one lane per
@@ -558,7 +558,7 @@ __global__ void __launch_bounds__(64) k_walker_setup_dp5(const double* __restric
                                                          double* __restrict__ wc,
                                                          double* __restrict__ orb)
 {
-    walker_setup<EMRI_ODE_DP5>(params, B, K, h, Ndt, gl, K, ic, 0.0, 0.0, wc, orb);
+    walker_setup<EMRI_ODE_DP5>(params, B, K, h, Ndt, gl, K, ic, wc, orb);
 }
 
 // adaptive orbit segment seg: one wave per walker continues from the saved

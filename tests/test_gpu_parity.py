@@ -425,3 +425,24 @@ def test_gr_limit_of_the_propagation(E):
     say("GR-limit lnL", got)
     assert got[1] == got[0] and got[3] == got[0]
     assert abs(got[2] - got[0]) <= 1e-14 * abs(got[0])
+
+
+@pytest.mark.parametrize("ode", [0, 1])
+def test_empty_batches(E, ode):
+    """B = 0 on every batch entry point (both orbit integrators): empty
+    results, nothing launched, no error."""
+    w = W.small("fp64", n_harm=4).with_(ode=ode, ode_rtol=1e-10, ode_atol=1e-10)
+    cfg = E.Config.from_workload(w)
+    P = torch.zeros((0, 17), dtype=torch.float64, device="cuda")
+    assert E.waveform_batch(P, cfg).shape[0] == 0
+    x = torch.zeros((0, w.N, 2), dtype=torch.float64, device="cuda")
+    assert E.fft_batch(x, cfg).shape[0] == 0
+    assert E.model_batch(P, cfg).shape[0] == 0
+    d, S = oracle_dataset(w, True)
+    dd, ss = to_device_data(d, S)
+    assert E.loglike_batch(P, dd, ss, cfg).shape[0] == 0
+    ds = E.dataset_init(dd, ss, cfg)
+    assert E.loglike_dataset(P, ds, cfg).shape[0] == 0
+    # and a batch of one right after
+    one = E.loglike_dataset(gpu_params(w.inj[None]), ds, cfg).cpu().numpy()
+    assert np.isfinite(one[0])

@@ -122,3 +122,17 @@ def test_fmg_with_lso_convention(E):
     say("LSO + fmg ref", ref, "got", got)
     assert np.array_equal(fin, np.isfinite(got)) and np.all(got[~fin] == -np.inf)
     assert np.all(np.abs(got[fin] - ref[fin]) <= 1e-10 * np.abs(ref[fin]))
+
+
+def test_fmg_with_adaptive_orbit(E):
+    """The frequency-dependent propagation on orbits from the adaptive
+    integrator (Dormand-Prince 5(4), rtol 1e-10), FP64, against the oracle."""
+    w, P, C = fmg_case("fp64")
+    w = w.with_(ode=1, ode_rtol=1e-10, ode_atol=1e-10)
+    d, S = oracle_dataset(w, True)
+    ref = O.loglike_fmg(P, C, F_STAR, d, S, ocfg(w))
+    got, _, _ = run(E, w, P, C, d, S)
+    fin = np.isfinite(ref)
+    say("DP5 + fmg ref", ref, "got", got)
+    assert np.array_equal(fin, np.isfinite(got)) and np.all(got[~fin] == -np.inf)
+    assert np.all(np.abs(got[fin] - ref[fin]) <= 1e-10 * np.abs(ref[fin]))

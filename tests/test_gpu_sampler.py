@@ -179,3 +179,21 @@ def test_stretch_step_chunked_and_errors(E):
     assert status(lambda: E.stretch_step(X1, lp1, prior, 2.0, U, ds, cfg, ws=small)) == EWORKSPACE
     torch.cuda.synchronize()
     assert torch.equal(X1, Xs) and torch.equal(lp1, ls)
+
+
+def test_ensemble_lnprob_with_adaptive_orbit(E):
+    """The log-posterior of an ensemble whose orbits use the adaptive
+    integrator (Dormand-Prince 5(4), rtol 1e-10) against the oracle's."""
+    w, fi, lo, hi, X0 = sampler_case()
+    w = w.with_(ode=1, ode_rtol=1e-10, ode_atol=1e-10)
+    X0[1, 0] = 1.0                     # outside the box and unphysical
+    d, S = oracle_dataset(w, True)
+    ref = O.ensemble_lnprob(X0, fi, lo, hi, d, S, ocfg(w))
+    cfg = E.Config.from_workload(w)
+    dd, ss = to_device_data(d, S)
+    ds = E.dataset_init(dd, ss, cfg)
+    got = E.ensemble_lnprob(torch.from_numpy(X0).cuda(), E.make_prior(fi, lo, hi), ds,
+                            cfg).cpu().numpy()
+    say("DP5 lnp ref", ref, "got", got)
+    assert np.sum(np.isfinite(ref)) >= 4
+    assert_lnp_close(got, ref)

@@ -2,9 +2,13 @@
 //
 //  k_walker_setup   one lane per walker (FP64): validity, z(d_L), Xi(z),
 //                   propagation delay, geometry constants, then the orbital
-//                   ODE of Eq. (1) by classical RK4 on the coarse grid, or by
-//                   the adaptive Dormand-Prince 5(4) pair sampled at the same
-//                   nodes, stopped at the last node before the LSO (Sec. 3).
+//                   ODE of Eq. (1) by classical RK4 on the coarse grid,
+//                   stopped at the last node before the LSO (Sec. 3);
+//                   k_walker_resume continues it segment by segment
+//  k_walker_setup_dp5, k_orbit_dp5
+//                   the same constants, then the ODE by the adaptive
+//                   Dormand-Prince 5(4) pair sampled at the same nodes by its
+//                   continuous extension, one wave per walker
 //  k_nodes          one lane per (walker, orbit node, harmonic): Bessel
 //                   functions of the Peters-Mathews amplitudes and their time
 //                   derivatives at the node
@@ -424,9 +428,10 @@ __device__ inline void finish_segment(int r, const State& s, int64_t kw, int seg
 }
 }  // namespace dp5
 
-// The orbit kernels run one lane per walker, a few waves for the whole batch,
-// beside the table and synthesis kernels of earlier segments: they raise
-// their waves' issue priority so those do not stretch the integration.
+// The orbit kernels run a few waves for the whole batch (one lane, or for
+// the adaptive integrator one wave, per walker) beside the table and
+// synthesis kernels of earlier segments: they raise their waves' issue
+// priority so those do not stretch the integration.
 template <int ODE>
 __device__ __forceinline__ void walker_setup(const double* __restrict__ params, int64_t B,
                                              int64_t K, double h, double Ndt, const GL8& gl,

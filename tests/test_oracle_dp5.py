@@ -255,3 +255,15 @@ def test_bad_tolerances_are_rejected():
             O.orbit(p[None], cfg(w, ode=1, rtol=rtol, atol=atol))
     with pytest.raises(ValueError):
         O.orbit(p[None], cfg(w, ode=2))
+
+
+def test_step_count_follows_the_order_five_controller():
+    """A 5(4) pair under error-per-step control takes steps h ~ rtol^(1/5):
+    two decades of tolerance multiply the accepted steps by about
+    100^(1/5) = 2.51 (a controller exponent of 1/4 would give 3.2, 1/6 2.2)."""
+    w = W.config2()
+    for p, kw in ((W.injection(), {}),
+                  (W.injection(a=0.0, e0=0.2), dict(lo_only=True, ic_lso=True))):
+        s = [O.orbit_steps(p[None], cfg(w, ode=1, rtol=r, atol=r, **kw))[0, 0]
+             for r in (1e-11, 1e-13)]
+        assert 2.25 < s[1] / s[0] < 2.75, s

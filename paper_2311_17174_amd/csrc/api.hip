@@ -255,11 +255,14 @@ static emri_status get_pipe(hipStream_t s, Pipe** out)
 
 // number of orbit segments: about 384 coarse steps each, at most 8
 // (EMRI_ORBIT_SEGMENTS overrides, 1 .. 16, for tuning and tests)
-static int orbit_segments(const Plan& p)
+static int orbit_segments(const Plan& p, bool zero_tail)
 {
-    // from the LSO the orbit is integrated backward: its first segment would
-    // hold the last intervals, so it runs as one segment
-    if (p.ic == EMRI_IC_LSO) return 1;
+    // From the LSO the orbit is integrated backward and the segments run in
+    // reverse time order.  A walker found invalid in a later segment would
+    // leave samples of the earlier ones in time-domain output, so there the
+    // backward orbit runs as one segment; the likelihood and model paths
+    // take their samples only from valid walkers.
+    if (p.ic == EMRI_IC_LSO && zero_tail) return 1;
     int64_t S = p.K / 384;
     if (const char* env = getenv("EMRI_ORBIT_SEGMENTS")) S = atoi(env);
     else if (S > 8) S = 8;
@@ -274,20 +277,26 @@ static int orbit_segments(const Plan& p)
 static emri_status run_waveforms(const Plan& p, const double* params, int64_t B, void* ws,
                                  void* out, bool zero_tail, hipStream_t s)
 {
-    const int S = orbit_segments(p);
+    const int S = orbit_segments(p, zero_tail);
+    const bool back = p.ic == EMRI_IC_LSO;
     // synthesis intervals: with the zero tail up to N / L, else those covering N_valid
     const int64_t KT = zero_tail ? p.N / p.L : p.K;
-    // segment bounds: the first segment (integrated before anything else can
-    // start) is a quarter of the others
+    // segment bounds in integration order: the first segment (integrated
+    // before anything else can start) is a quarter of the others
     auto kb = [&](int i) -> int64_t {
         if (i <= 0) return 0;
         if (i >= S) return p.K;
         return p.K * (int64_t)(1 + 4 * (i - 1)) / (int64_t)(1 + 4 * (S - 1));
     };
+    // segment i covers the intervals [lo(i), hi(i)): forward [kb(i), kb(i+1)),
+    // backward from the LSO [K - kb(i+1), K - kb(i))
+    auto lo = [&](int i) -> int64_t { return back ? p.K - kb(i + 1) : kb(i); };
+    auto hi = [&](int i) -> int64_t { return back ? p.K - kb(i) : kb(i + 1); };
     emri_status st;
     if ((st = check_launch(launch_azimuth(p, ws, s), "azimuth table"))) return st;
     if (S == 1) {
-        if ((st = check_launch(launch_walker_setup(p, params, B, ws, p.K, s), "walker setup")))
+        if ((st = check_launch(launch_walker_setup(p, params, B, ws, back ? 0 : p.K, s),
+                               "walker setup")))
             return st;
         if ((st = check_launch(launch_tables(p, B, ws, 0, p.K, 0, s), "amplitude tables")))
             return st;
@@ -295,23 +304,30 @@ static emri_status run_waveforms(const Plan& p, const double* params, int64_t B,
     }
     Pipe* pp = nullptr;
     if ((st = get_pipe(s, &pp))) return st;
-    st = check_launch(launch_walker_setup(p, params, B, ws, kb(1), s), "walker setup");
+    // the first segment's last node: kb(1) forward, K - kb(1) backward
+    st = check_launch(launch_walker_setup(p, params, B, ws, back ? lo(0) : hi(0), s),
+                      "walker setup");
     bool forked = false;
     // the caller's stream integrates segment i and builds its tables (small
     // kernels that fill the issue slots the synthesis leaves); the auxiliary
     // stream synthesises segment i meanwhile
     for (int i = 0; i < S && st == EMRI_OK; ++i) {
+        // resume from the previous segment's last node: forward from lo(i)
+        // up to hi(i), backward from hi(i) down to lo(i)
         if (i > 0 &&
-            (st = check_launch(launch_walker_resume(p, B, ws, kb(i), kb(i + 1), i, s), "orbit")))
+            (st = check_launch(back ? launch_walker_resume(p, B, ws, hi(i), lo(i), i, s)
+                                    : launch_walker_resume(p, B, ws, lo(i), hi(i), i, s),
+                               "orbit")))
             break;
-        if ((st = check_launch(launch_tables(p, B, ws, kb(i), kb(i + 1), i, s), "amplitude tables")))
+        if ((st = check_launch(launch_tables(p, B, ws, lo(i), hi(i), i, s), "amplitude tables")))
             break;
         if ((st = check_launch(hipEventRecord(pp->seg[i], s), "pipeline: event record"))) break;
         if ((st = check_launch(hipStreamWaitEvent(pp->aux, pp->seg[i], 0), "pipeline: wait")))
             break;
         forked = true;
-        if ((st = check_launch(launch_synth(p, B, ws, out, kb(i), i == S - 1 ? KT : kb(i + 1), i,
-                                            zero_tail, pp->aux),
+        // forward, the last segment also takes the zero tail past K
+        const int64_t sh = (!back && i == S - 1) ? KT : hi(i);
+        if ((st = check_launch(launch_synth(p, B, ws, out, lo(i), sh, i, zero_tail, pp->aux),
                                "synthesis")))
             break;
     }

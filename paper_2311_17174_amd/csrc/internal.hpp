@@ -122,10 +122,12 @@ size_t cols_lds_bytes(int prec, int64_t R2, int TA);
 // the amplitude tables and synthesis of finished segments overlap the rest
 // of the integration; kMaxSeg bounds their number
 constexpr int kMaxSeg = 16;
-// walker constants and orbit segment 0 (steps [0, k1))
+// walker constants and orbit segment 0: nodes 0 .. k1 (with the state at
+// the LSO, integrated backward: nodes K .. k1)
 hipError_t launch_walker_setup(const Plan& p, const double* params, int64_t B, void* ws,
                                int64_t k1, hipStream_t s);
-// orbit segment seg >= 1: steps [k0, k1) from the stored node k0
+// orbit segment seg >= 1 from the stored node k0: nodes up to k1 (backward
+// from the LSO: down to k1 < k0)
 hipError_t launch_walker_resume(const Plan& p, int64_t B, void* ws, int64_t k0, int64_t k1,
                                 int seg, hipStream_t s);
 // node amplitudes and interval tables of segment seg (intervals [k0, k1))

@@ -142,14 +142,16 @@ __device__ __forceinline__ int64_t rk4_steps(double& Y0, double& Y1, double& Y2,
 }
 
 // From the LSO backward: RK4 steps with -h from the state Y at node K (f its
-// derivative) down to node 0, writing nodes K-1 .. 0.  false if the state
-// leaves the physical range (finite, 0 <= e < 1, nu > 0) on the way.
+// derivative) down to node k_stop, writing nodes K-1 .. k_stop.  false if
+// the state leaves the physical range (finite, 0 <= e < 1, nu > 0) on the
+// way.
 __device__ __forceinline__ bool rk4_back(double Y0, double Y1, double Y2, double Y3, double Y4,
-                                         Rhs f, int64_t K, double h, double Ms, double mus,
-                                         double a, double cl, double* __restrict__ o)
+                                         Rhs f, int64_t K, int64_t k_stop, double h, double Ms,
+                                         double mus, double a, double cl,
+                                         double* __restrict__ o)
 {
     const double hb = -h, hh = 0.5 * hb, h6 = hb / 6.0;
-    for (int64_t k = K; k > 0; --k) {
+    for (int64_t k = K; k > k_stop; --k) {
         const Rhs k2 = ak_rhs(Y1 + hh * f.dnu, Y3 + hh * f.de, Ms, mus, a, cl);
         const Rhs k3 = ak_rhs(Y1 + hh * k2.dnu, Y3 + hh * k2.de, Ms, mus, a, cl);
         const Rhs k4 = ak_rhs(Y1 + hb * k3.dnu, Y3 + hb * k3.de, Ms, mus, a, cl);
@@ -410,8 +412,9 @@ __device__ inline State load(const double* __restrict__ c)
 }
 
 // after segment seg: K_w as known, and the state for the next segment
-__device__ inline void finish_segment(int r, const State& s, int64_t kw, int seg,
-                                      double* __restrict__ c)
+// (backward from the LSO every node up to K is valid while the walker is)
+__device__ inline void finish_segment(int r, const State& s, int64_t kw, int seg, bool back,
+                                      int64_t K, double* __restrict__ c)
 {
     if (r == FAIL) {
         c[WC_VALID] = 0.0;
@@ -420,7 +423,7 @@ __device__ inline void finish_segment(int r, const State& s, int64_t kw, int seg
         c[WC_ODONE] = 1.0;
         return;
     }
-    const int64_t known = (r == END) ? kw : s.node - 1;
+    const int64_t known = back ? K : (r == END) ? kw : s.node - 1;
     c[WC_KSEG + seg] = (double)known;
     c[WC_KW] = (double)known;
     c[WC_ODONE] = (r == END) ? 1.0 : 0.0;
@@ -520,7 +523,8 @@ __device__ __forceinline__ void walker_setup(const double* __restrict__ params, 
             c[WC_VALID] = 1.0;
             return;
         } else {
-            if (!rk4_back(p[5], nuL, p[6], e0, p[7], f, K, h, Ms, mus, a, cl, o)) return;
+            // k1: the last node of the first (backward) segment
+            if (!rk4_back(p[5], nuL, p[6], e0, p[7], f, K, k1, h, Ms, mus, a, cl, o)) return;
         }
         c[WC_KSEG] = (double)K;
         c[WC_KW] = (double)K;
@@ -567,7 +571,7 @@ __global__ void __launch_bounds__(64) k_walker_setup_dp5(const double* __restric
 }
 
 // adaptive orbit segment seg: one wave per walker continues from the saved
-// integrator state until node k1 is filled (backward: down to node 0), so
+// integrator state until node k1 is filled (backward: down to node k1), so
 // the step sequence does not depend on where the segments end.  Every lane
 // of the wave takes the same steps; the nodes of an accepted step are
 // shared out over the lanes.  The waves are held to three per SIMD (168
@@ -589,10 +593,35 @@ k_orbit_dp5(int64_t K, double h, int64_t k1, int seg, int back, double rtol, dou
     }
     dp5::State st = dp5::load(c);
     int64_t kw = -1;
-    const int r = dp5::advance(st, back ? 0 : k1, K, h, back != 0, rtol, atol, c[WC_MS],
-                               c[WC_MUS], c[WC_A], c[WC_CL], orb + w * (K + 1) * 10, &kw,
+    const int r = dp5::advance(st, k1, K, h, back != 0, rtol, atol, c[WC_MS], c[WC_MUS],
+                               c[WC_A], c[WC_CL], orb + w * (K + 1) * 10, &kw,
                                dense + threadIdx.x);
-    if (threadIdx.x == 0) dp5::finish_segment(r, st, kw, seg, c);
+    if (threadIdx.x == 0) dp5::finish_segment(r, st, kw, seg, back != 0, K, c);
+}
+
+// backward orbit segment seg >= 1 (RK4, from the LSO): steps from node k0
+// (stored by segment seg - 1) down to node k1 < k0
+__global__ void __launch_bounds__(64) k_walker_resume_back(int64_t B, int64_t K, double h,
+                                                           int64_t k0, int64_t k1, int seg,
+                                                           double* __restrict__ wc,
+                                                           double* __restrict__ orb)
+{
+    __builtin_amdgcn_s_setprio(3);
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= B) return;
+    double* c = wc + w * WC;
+    if (c[WC_VALID] == 0.0) return;
+    double* o = orb + w * (K + 1) * 10;
+    const double* q = o + k0 * 10;
+    const Rhs f{q[5], q[6], q[7], q[8], q[9]};
+    if (!rk4_back(q[0], q[1], q[2], q[3], q[4], f, k0, k1, h, c[WC_MS], c[WC_MUS], c[WC_A],
+                  c[WC_CL], o)) {
+        c[WC_VALID] = 0.0;
+        c[WC_KSEG + seg] = -1.0;
+        c[WC_KW] = -1.0;
+        return;
+    }
+    c[WC_KSEG + seg] = (double)K;
 }
 
 // orbit segment seg >= 1 (RK4): steps [k0, k1) from node k0 (stored by
@@ -838,19 +867,21 @@ hipError_t launch_walker_setup(const Plan& p, const double* params, int64_t B, v
                                int64_t k1, hipStream_t s)
 {
     static const GL8 gl = make_gl8();
+    const bool back = p.ic == EMRI_IC_LSO;
+    // forward: nodes 0 .. k1; backward from the LSO: nodes K .. k1
+    if (back ? (k1 < 0 || k1 >= p.K) : (k1 < 0 || k1 > p.K)) return hipErrorInvalidValue;
     char* base = (char*)ws;
     const double h = p.dt * (double)p.L;
     dim3 grid((unsigned)((B + 63) / 64));
     trace_mark(ST_SETUP, s, true);
-    if (p.ic == EMRI_IC_LSO && k1 != p.K) return hipErrorInvalidValue;   // one segment only
     if (p.ode == EMRI_ODE_DP5) {
         hipLaunchKernelGGL(k_walker_setup_dp5, grid, dim3(64), 0, s, params, B, p.K, h,
                            (double)p.N * p.dt, gl, p.ic, (double*)(base + p.off_wc),
                            (double*)(base + p.off_orb));
         if (B > 0)
             hipLaunchKernelGGL(k_orbit_dp5, dim3((unsigned)B), dim3(64), 0, s, p.K, h, k1, 0,
-                               p.ic == EMRI_IC_LSO ? 1 : 0, p.rtol, p.atol,
-                               (double*)(base + p.off_wc), (double*)(base + p.off_orb));
+                               back ? 1 : 0, p.rtol, p.atol, (double*)(base + p.off_wc),
+                               (double*)(base + p.off_orb));
     } else
         hipLaunchKernelGGL(k_walker_setup, grid, dim3(64), 0, s, params, B, p.K, h,
                            (double)p.N * p.dt, gl, k1, p.ic, (double*)(base + p.off_wc),
@@ -862,7 +893,11 @@ hipError_t launch_walker_setup(const Plan& p, const double* params, int64_t B, v
 hipError_t launch_walker_resume(const Plan& p, int64_t B, void* ws, int64_t k0, int64_t k1,
                                 int seg, hipStream_t s)
 {
-    if (seg < 1 || seg >= kMaxSeg || k0 < 0 || k1 < k0 || k1 > p.K) return hipErrorInvalidValue;
+    const bool back = p.ic == EMRI_IC_LSO;
+    // forward: steps from node k0 up to node k1; backward: from k0 down to k1
+    if (seg < 1 || seg >= kMaxSeg ||
+        (back ? (k1 < 0 || k0 <= k1 || k0 > p.K) : (k0 < 0 || k1 < k0 || k1 > p.K)))
+        return hipErrorInvalidValue;
     char* base = (char*)ws;
     const double h = p.dt * (double)p.L;
     dim3 grid((unsigned)((B + 63) / 64));
@@ -870,11 +905,15 @@ hipError_t launch_walker_resume(const Plan& p, int64_t B, void* ws, int64_t k0, 
     if (p.ode == EMRI_ODE_DP5) {
         if (B > 0)
             hipLaunchKernelGGL(k_orbit_dp5, dim3((unsigned)B), dim3(64), 0, s, p.K, h, k1, seg,
-                               0, p.rtol, p.atol, (double*)(base + p.off_wc),
+                               back ? 1 : 0, p.rtol, p.atol, (double*)(base + p.off_wc),
                                (double*)(base + p.off_orb));
-    } else
+    } else if (back) {
+        hipLaunchKernelGGL(k_walker_resume_back, grid, dim3(64), 0, s, B, p.K, h, k0, k1, seg,
+                           (double*)(base + p.off_wc), (double*)(base + p.off_orb));
+    } else {
         hipLaunchKernelGGL(k_walker_resume, grid, dim3(64), 0, s, B, p.K, h, k0, k1, seg,
                            (double*)(base + p.off_wc), (double*)(base + p.off_orb));
+    }
     trace_mark(ST_SETUP, s, false);
     return hipGetLastError();
 }
@@ -889,8 +928,11 @@ hipError_t launch_tables(const Plan& p, int64_t B, void* ws, int64_t k0, int64_t
     const double* orb = (const double*)(base + p.off_orb);
     double* nv = (double*)(base + p.off_nv);
     trace_mark(ST_TABLES, s, true);
-    // nodes k0 .. k1; node k0 of a later segment was the previous one's last
-    const int64_t n0 = (seg == 0) ? 0 : k0 + 1, n1 = k1 + 1;
+    // nodes k0 .. k1 of the intervals [k0, k1); a later segment's node k0
+    // (forward) or k1 (backward from the LSO) was the previous segment's last
+    const bool back = p.ic == EMRI_IC_LSO;
+    const int64_t n0 = (seg == 0 || back) ? k0 : k0 + 1;
+    const int64_t n1 = (seg == 0 || !back) ? k1 + 1 : k1;
     const int64_t nn = (n1 - n0) * p.nh;
     if (nn > 0)   // an empty segment has no nodes of its own
         hipLaunchKernelGGL(k_nodes, dim3((unsigned)((nn + 255) / 256), (unsigned)B), dim3(256),

@@ -68,3 +68,58 @@ def test_lso_loglike_parity(E, prec):
     assert np.array_equal(fin, np.isfinite(got)) and got[6] == -np.inf
     rel = np.abs(got[fin] - ref[fin]) / np.abs(ref[fin])
     assert np.all(rel <= (1e-10 if prec == "fp64" else 1e-4)), rel
+
+
+@pytest.mark.parametrize("ode", [0, 1])
+@pytest.mark.parametrize("segs", [3, 7])
+def test_lso_segments_bitwise(E, monkeypatch, ode, segs):
+    """The backward orbit in segments (reverse time order, each segment's
+    tables and samples built while the orbit goes on back in time) gives the
+    likelihood and the model of one segment bit for bit, with a walker whose
+    history leaves the physical range in a late segment (lnL = -inf, zero
+    model)."""
+    w = W.small("fp64", n_harm=6, days=20.0, N=1 << 18).with_(ic=1, ode=ode, ode_rtol=1e-10,
+                                                              ode_atol=1e-10)
+    # the last two histories leave the range about 14 and 119 nodes before
+    # the LSO: in the first segments and in a late one
+    P = np.concatenate([W.walkers(w, B=4), lso_walkers(w)[4:],
+                        W.injection(M=5e4, mu=10.0, e0=0.6)[None]])
+    _, kw = O.orbit(P, ocfg(w))
+    say("LSO segments", segs, "ode", ode, "K", w.n_intervals, "kw", kw)
+    assert np.all(kw[-2:] == -1) and np.all(kw[:-2] == w.n_intervals)
+    d, S = oracle_dataset(w, True)
+    dd, ss = to_device_data(d, S)
+    cfg = E.Config.from_workload(w)
+    ds = E.dataset_init(dd, ss, cfg)
+    Pt = torch.from_numpy(P).cuda()
+    monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", "1")
+    one = E.loglike_dataset(Pt, ds, cfg).cpu().numpy()
+    m1 = E.model_batch(Pt, cfg).cpu().numpy()
+    monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", str(segs))
+    for _ in range(2):
+        assert np.array_equal(E.loglike_dataset(Pt, ds, cfg).cpu().numpy(), one)
+    assert np.array_equal(E.loglike_batch(Pt, dd, ss, cfg).cpu().numpy(), one)
+    assert np.array_equal(E.model_batch(Pt, cfg).cpu().numpy(), m1)
+    assert np.all(one[-2:] == -np.inf) and np.all(m1[-2:] == 0)
+    ref = O.loglike(P, d, S, ocfg(w))
+    fin = np.isfinite(ref)
+    assert np.array_equal(fin, np.isfinite(one))
+    assert np.all(np.abs(one[fin] - ref[fin]) <= 1e-10 * np.abs(ref[fin]))
+
+
+def test_lso_config2_sampled_parity(E):
+    """The paper's convention at full size (256 walkers, 1 yr, 2^22 samples,
+    30 harmonics; the backward orbit in eight pipelined segments), against
+    the oracle on sampled walkers."""
+    w = W.config2().with_(ic=1)
+    P = W.walkers(w)
+    d, S = oracle_dataset(w, True)
+    dd, ss = to_device_data(d, S)
+    got = E.loglike_batch(torch.from_numpy(P).cuda(), dd, ss, E.Config.from_workload(w)).cpu().numpy()
+    assert np.all(np.isfinite(got))
+    idx = np.array([5, 250])
+    say("LSO config2 oracle lnL for", idx)
+    ref = O.loglike(P[idx], d, S, ocfg(w))
+    rel = np.abs(got[idx] - ref) / np.abs(ref)
+    say("rel err", rel)
+    assert np.all(rel <= 1e-10)

@@ -868,8 +868,9 @@ hipError_t launch_walker_setup(const Plan& p, const double* params, int64_t B, v
 {
     static const GL8 gl = make_gl8();
     const bool back = p.ic == EMRI_IC_LSO;
-    // forward: nodes 0 .. k1; backward from the LSO: nodes K .. k1
-    if (back ? (k1 < 0 || k1 >= p.K) : (k1 < 0 || k1 > p.K)) return hipErrorInvalidValue;
+    // forward: nodes 0 .. k1; backward from the LSO: nodes K .. k1 (k1 = K:
+    // an empty first segment, node K alone)
+    if (k1 < 0 || k1 > p.K) return hipErrorInvalidValue;
     char* base = (char*)ws;
     const double h = p.dt * (double)p.L;
     dim3 grid((unsigned)((B + 63) / 64));
@@ -895,8 +896,9 @@ hipError_t launch_walker_resume(const Plan& p, int64_t B, void* ws, int64_t k0, 
 {
     const bool back = p.ic == EMRI_IC_LSO;
     // forward: steps from node k0 up to node k1; backward: from k0 down to k1
+    // (k0 = k1: an empty segment)
     if (seg < 1 || seg >= kMaxSeg ||
-        (back ? (k1 < 0 || k0 <= k1 || k0 > p.K) : (k0 < 0 || k1 < k0 || k1 > p.K)))
+        (back ? (k1 < 0 || k0 < k1 || k0 > p.K) : (k0 < 0 || k1 < k0 || k1 > p.K)))
         return hipErrorInvalidValue;
     char* base = (char*)ws;
     const double h = p.dt * (double)p.L;

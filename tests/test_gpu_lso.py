@@ -107,6 +107,24 @@ def test_lso_segments_bitwise(E, monkeypatch, ode, segs):
     assert np.all(np.abs(one[fin] - ref[fin]) <= 1e-10 * np.abs(ref[fin]))
 
 
+@pytest.mark.parametrize("ode", [0, 1])
+def test_lso_empty_first_segments(E, monkeypatch, ode):
+    """16 segments of a 22-interval orbit: the first backward segments are
+    empty (node K alone); the likelihood equals the one-segment one."""
+    w = W.small("fp64", n_harm=6).with_(ic=1, ode=ode, ode_rtol=1e-10, ode_atol=1e-10)
+    P = lso_walkers(w)
+    d, S = oracle_dataset(w, True)
+    dd, ss = to_device_data(d, S)
+    cfg = E.Config.from_workload(w)
+    ds = E.dataset_init(dd, ss, cfg)
+    Pt = torch.from_numpy(P).cuda()
+    monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", "1")
+    one = E.loglike_dataset(Pt, ds, cfg).cpu().numpy()
+    monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", "16")
+    assert np.array_equal(E.loglike_dataset(Pt, ds, cfg).cpu().numpy(), one)
+    assert one[6] == -np.inf and np.all(np.isfinite(one[:6]))
+
+
 def test_lso_config2_sampled_parity(E):
     """The paper's convention at full size (256 walkers, 1 yr, 2^22 samples,
     30 harmonics; the backward orbit in eight pipelined segments), against

@@ -267,3 +267,20 @@ def test_step_count_follows_the_order_five_controller():
         s = [O.orbit_steps(p[None], cfg(w, ode=1, rtol=r, atol=r, **kw))[0, 0]
              for r in (1e-11, 1e-13)]
         assert 2.25 < s[1] / s[0] < 2.75, s
+
+
+def test_backward_nodes_match_an_independent_integrator():
+    """From the LSO backward: the adaptive oracle's nodes against SciPy's
+    DOP853 integrated backward from the same state (rtol 1e-13)."""
+    w = W.config1()
+    p = W.injection(e0=0.3)
+    rtol = 1e-10
+    orb, kw = O.orbit(p[None], cfg(w, ic_lso=True, ode=1, rtol=rtol, atol=rtol))
+    K = w.n_intervals
+    assert kw[0] == K
+    hc = w.dt * (1 << w.coarse_log2)
+    ref = _scipy_orbit(p, w, np.arange(K + 1) * hc, backward_from=orb[0, K, :5].copy())
+    y = orb[0, :, :5]
+    assert np.max(np.abs(y[:, 1] / ref[:, 1] - 1)) < rtol
+    assert np.max(np.abs(y[:, 3] - ref[:, 3])) < rtol
+    assert np.max(np.abs(y[:, 0] - ref[:, 0])) < rtol * np.max(np.abs(ref[:, 0])) + rtol

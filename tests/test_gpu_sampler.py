@@ -93,7 +93,19 @@ def test_stretch_chain_parity(E):
     """Six steps of 2W = 16 walkers, D = 8, against the oracle chain; the
     narrow box puts walkers and proposals outside it, so both -inf rules are
     taken."""
-    w, fi, lo, hi, X0 = sampler_case()
+    run_chain(E, *sampler_case())
+
+
+def test_stretch_chain_parity_lso(E):
+    """The paper's own setting (Sec. 3): orbital state at the LSO, fixed
+    eccentricity and angles, free masses, spin and Xi0 (D = 4)."""
+    fi = (0, 1, 2, 14)
+    w = W.small("fp64", n_harm=6, Xi0=0.9, n_Xi=2.0).with_(ic=1)
+    lo, hi = W.sampler_prior(w, fi, width=2.0)
+    run_chain(E, w, fi, lo, hi, W.sampler_ensemble(w, 8, fi, seed=3))
+
+
+def run_chain(E, w, fi, lo, hi, X0):
     Wh, steps, a = X0.shape[0] // 2, 6, 2.0
     U = W.sampler_uniforms(Wh, steps, seed=11)
     d, S = oracle_dataset(w, True)

@@ -203,14 +203,14 @@ def run_config5(E, W, steps: int, warmup: int, ws_gib: float):
     return out
 
 
-def run_sampler(E, W, w, data, psd, steps: int, warmup: int):
+def run_sampler(E, W, w, data, psd, steps: int, warmup: int, fi=None):
     """Ensemble sampler on the likelihood's workload: 2W walkers with W the
     workload's batch, so each half is one batch; stretch scale 2, box prior on
-    the free parameters of the sampler workloads.  The uniforms of every step
-    are resident before the timed steps."""
+    the free parameters fi (default: those of the sampler workloads).  The
+    uniforms of every step are resident before the timed steps."""
     import torch
     Wh = w.B
-    fi = W.SAMPLER_FREE
+    fi = W.SAMPLER_FREE if fi is None else tuple(fi)
     lo, hi = W.sampler_prior(w, fi)
     cfg = E.Config.from_workload(w)
     prior = E.make_prior(fi, lo, hi)
@@ -541,8 +541,18 @@ def main():
         for wk in (w64, wmx):
             sampler["fp64" if wk is w64 else "mixed"] = run_sampler(
                 E, W, wk, data, psd, args.sampler_steps, 1)
+        # the paper's own setting (Sec. 3): state at the LSO, free masses, spin
+        # and Xi0, against the injection's noise-less model
+        wl = w64.with_(ic=1)
+        cl = E.Config.from_workload(wl)
+        ml = E.model_batch(torch.from_numpy(wl.inj[None]).cuda(), cl)[0]
+        dl = torch.view_as_real(ml).double().contiguous()
+        sampler["fp64_lso_masses_spin_xi0"] = run_sampler(E, W, wl, dl, psd, args.sampler_steps,
+                                                          1, fi=(0, 1, 2, 14))
+        del ml, dl
         print(f"[bench] sampler: fp64 {sampler['fp64']['steps_per_s']:.2f} steps/s, mixed "
-              f"{sampler['mixed']['steps_per_s']:.2f} steps/s ({2 * w64.B} walkers)",
+              f"{sampler['mixed']['steps_per_s']:.2f} steps/s ({2 * w64.B} walkers); the paper's "
+              f"setting {sampler['fp64_lso_masses_spin_xi0']['steps_per_s']:.2f} steps/s",
               file=sys.stderr, flush=True)
 
     fmg = None

@@ -1,0 +1,44 @@
+"""Pin of the 1PN terms of the oracle's orbital equations (Eq. (1), the
+BC04 forms) against the post-Newtonian chirp of a test mass on a circular
+orbit, a result independent of BC04.
+
+At e = 0 and a = 0, BC04 evolve the radial (mean-motion) frequency nu with
+dnu/dt = (96 / 10 pi) (mu / M^3) x^{11/3} (1 + (1273/336) x^{2/3}), and the
+pericentre with dgamma~/dt = 6 pi nu x^{2/3} (1 + ...), x = 2 pi M nu.  The
+orbital (azimuthal) frequency is nu_phi = nu + (dgamma~/dt) / (2 pi); in its
+variable y = (2 pi M nu_phi)^{2/3} the chirp of a test mass at 1PN order is
+dnu_phi/dt = (96 / 10 pi) (mu / M^3) (2 pi M nu_phi)^{11/3} (1 - (743/336) y + ...)
+(the 1PN flux and binding energy, mass ratio -> 0).  The two forms agree
+only if both 1PN coefficients of the oracle are right: 1273/336 - 6 = -743/336.
+"""
+import numpy as np
+
+import oracle as O
+from paper_2311_17174_amd import workloads as W
+
+TSUN = 4.925490947641267e-6
+
+
+def _coef(p, nu):
+    """(dnu_phi/dt / leading - 1) / y at nu, from the oracle's right-hand side."""
+    M, mu = p[0] * TSUN, p[1] * TSUN
+    f = O.rhs(np.array([0.0, nu, 0.0, 0.0, 0.0]), p)
+    dn = nu * 1e-5
+    dg = (O.rhs(np.array([0.0, nu + dn, 0.0, 0.0, 0.0]), p)[2] -
+          O.rhs(np.array([0.0, nu - dn, 0.0, 0.0, 0.0]), p)[2]) / (2 * dn)
+    nuphi = nu + f[2] / (2 * np.pi)
+    dnuphi = f[1] * (1.0 + dg / (2 * np.pi))
+    x = 2 * np.pi * M * nuphi
+    lead = 96.0 / (10.0 * np.pi) * (mu / M ** 3) * x ** (11.0 / 3.0)
+    y = x ** (2.0 / 3.0)
+    return (dnuphi / lead - 1.0) / y
+
+
+def test_circular_1pn_chirp_of_a_test_mass():
+    p = W.injection(a=0.0, e0=0.0)
+    nu = 1e-8                        # y ~ 5e-5: deep in the post-Newtonian regime
+    # Richardson in y (y doubles when nu grows by 2^{3/2}) removes the O(y) term
+    c = 2 * _coef(p, nu) - _coef(p, nu * 2 ** 1.5)
+    # a wrong digit in 1273/336 moves the limit by at least 1/336 (2e-3
+    # relative), a wrong pericentre-advance coefficient by O(1)
+    assert abs(c / (-743.0 / 336.0) - 1) < 1e-5, c

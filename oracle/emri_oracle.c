@@ -35,9 +35,11 @@
  * Readings where the paper is silent or garbled are listed in the design
  * notes of the repository; each is marked "reading" at the place it is used.
  *
- * Parity pins: see tests/test_oracle_*.py.  The 1PN and spin coefficients of
- * the BC04 orbital equations and the absolute sign / orientation conventions
- * of the response are parity unpinned (no printed values exist to check).
+ * Parity pins: see tests/test_oracle_*.py.  The spin coefficients and the
+ * eccentricity-dependent 1PN terms of the BC04 orbital equations and the
+ * absolute sign / orientation conventions of the response are parity
+ * unpinned (no printed values exist to check); the 1PN terms at e = 0 are
+ * pinned against the 1PN chirp of a test mass.
  */
 #include <math.h>
 #include <stdint.h>

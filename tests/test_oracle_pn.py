@@ -42,3 +42,21 @@ def test_circular_1pn_chirp_of_a_test_mass():
     # a wrong digit in 1273/336 moves the limit by at least 1/336 (2e-3
     # relative), a wrong pericentre-advance coefficient by O(1)
     assert abs(c / (-743.0 / 336.0) - 1) < 1e-5, c
+
+
+def test_1pn_pericentre_advance_at_any_eccentricity():
+    """The 1PN pericentre advance per radial period, 6 pi M / (a (1 - e^2)),
+    i.e. (dgamma~/dt) / (2 pi nu) -> 3 x^{2/3} / (1 - e^2) as x -> 0, for
+    circular and eccentric orbits (Richardson-extrapolated in x^{2/3})."""
+    for e in (0.0, 0.3, 0.6, 0.8):
+        p = W.injection(a=0.0, e0=e)
+        M = p[0] * TSUN
+
+        def ratio(nu):
+            f = O.rhs(np.array([0.0, nu, 0.0, e, 0.0]), p)
+            y = (2 * np.pi * M * nu) ** (2.0 / 3.0)
+            return f[2] / (2 * np.pi * nu) / (3 * y / (1 - e * e))
+
+        nu = 1e-8
+        lim = 2 * ratio(nu) - ratio(nu * 2 ** 1.5)
+        assert abs(lim - 1) < 1e-6, (e, lim)

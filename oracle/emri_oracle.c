@@ -35,11 +35,12 @@
  * Readings where the paper is silent or garbled are listed in the design
  * notes of the repository; each is marked "reading" at the place it is used.
  *
- * Parity pins: see tests/test_oracle_*.py.  The spin coefficients and the
- * eccentricity-dependent 1PN terms of the BC04 orbital equations and the
- * absolute sign / orientation conventions of the response are parity
- * unpinned (no printed values exist to check); the 1PN terms at e = 0 are
- * pinned against the 1PN chirp of a test mass.
+ * Parity pins: see tests/test_oracle_*.py.  The spin-orbit and the
+ * eccentricity-dependent 1PN terms of dnu/dt and de/dt in the BC04 orbital
+ * equations and the absolute sign / orientation conventions of the response
+ * are parity unpinned (no printed values exist to check); the 1PN terms at
+ * e = 0, the 1PN pericentre advance and the Lense-Thirring precessions are
+ * pinned against their textbook forms.
  */
 #include <math.h>
 #include <stdint.h>

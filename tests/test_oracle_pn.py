@@ -60,3 +60,27 @@ def test_1pn_pericentre_advance_at_any_eccentricity():
         nu = 1e-8
         lim = 2 * ratio(nu) - ratio(nu * 2 ** 1.5)
         assert abs(lim - 1) < 1e-6, (e, lim)
+
+
+def test_lense_thirring_precessions():
+    """The spin terms of the precession equations are the Lense-Thirring
+    rates of an orbit around a spinning mass (J = a M^2, Kepler's a_orb =
+    (M / omega^2)^{1/3}, omega = 2 pi nu): the node of L about S advances at
+    2 J / (a_orb^3 (1 - e^2)^{3/2}) (dalpha/dt), the pericentre at
+    -6 J cos(lambda) / (a_orb^3 (1 - e^2)^{3/2}) (the spin part of
+    dgamma~/dt, which is linear in the spin)."""
+    for (a, e, cl, nu) in ((0.9, 0.0, 0.5, 1e-3), (0.5, 0.3, -0.2, 3e-4), (0.3, 0.7, 0.9, 2e-3)):
+        p = W.injection(a=a, e0=e)
+        p[8] = cl
+        q = p.copy()
+        q[2] = 0.0
+        M = p[0] * TSUN
+        om = 2 * np.pi * nu
+        aorb3 = M / om ** 2
+        J = a * M * M
+        f = O.rhs(np.array([0.0, nu, 0.0, e, 0.0]), p)
+        f0 = O.rhs(np.array([0.0, nu, 0.0, e, 0.0]), q)
+        node = 2 * J / (aorb3 * (1 - e * e) ** 1.5)
+        peri = -6 * J * cl / (aorb3 * (1 - e * e) ** 1.5)
+        np.testing.assert_allclose(f[4], node, rtol=1e-13)
+        np.testing.assert_allclose(f[2] - f0[2], peri, rtol=1e-10)

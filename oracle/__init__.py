@@ -104,6 +104,7 @@ def lib():
             "oracle_waveform_diag": ([dp, cp, dp, dp], ctypes.c_int),
             "oracle_rfft": ([dp, i64, i64, ctypes.c_double, dp], ctypes.c_int),
             "oracle_loglike": ([dp, i64, dp, dp, cp, dp], ctypes.c_int),
+            "oracle_loglike_sets": ([dp, i64, dp, ctypes.c_int32, dp, cp, dp], ctypes.c_int),
             "oracle_loglike_fmg": ([dp, i64, dp, ctypes.c_int32, ctypes.c_double, dp, dp, cp,
                                     dp], ctypes.c_int),
             "oracle_psd_bc04": ([dp, i64, dp], ctypes.c_int),
@@ -205,11 +206,12 @@ def waveform(params, cfg: OracleConfig) -> np.ndarray:
 
 
 def waveform_diag(prow, cfg: OracleConfig):
-    """One walker: channels [2][N] and per-sample diagnostics [N][8] =
-    (h+, hx, A, c_iota, Phi', gamma, cos theta_d, 0)."""
+    """One walker: channels [2][N] and per-sample diagnostics [N][16] =
+    (h+, hx, A, c_iota, Phi', gamma, cos theta_d, phi_d, psi, beta, Phi, nu,
+    gamma~, alpha, e, 0); rows past the last sample written are zero."""
     p = _f64(prow).reshape(NPAR)
     x = np.zeros((2, cfg.N))
-    d = np.zeros((cfg.N, 8))
+    d = np.zeros((cfg.N, 16))
     c = cfg.c()
     _check(lib().oracle_waveform_diag(_p(p), ctypes.byref(c), _p(x), _p(d)), "waveform_diag")
     return x, d
@@ -248,6 +250,22 @@ def loglike(params, data, psd, cfg: OracleConfig) -> np.ndarray:
     c = cfg.c()
     _check(lib().oracle_loglike(_p(p), p.shape[0], _p(d), _p(s), ctypes.byref(c), _p(out)),
            "loglike")
+    return out
+
+
+def loglike_sets(params, datasets, psd, cfg: OracleConfig) -> np.ndarray:
+    """[B][nset]: lnL of each walker against each data set [2][N/2+1]
+    complex, from one evaluation of the walker's spectrum (each entry equals
+    loglike() for that data set)."""
+    p = _f64(params).reshape(-1, NPAR)
+    d = np.ascontiguousarray(np.stack([_cplx_pairs(x) for x in datasets]))
+    s = _f64(psd)
+    H = cfg.N // 2 + 1
+    assert d.shape[1:] == (2, H, 2) and s.shape == (H,)
+    out = np.zeros((p.shape[0], d.shape[0]))
+    c = cfg.c()
+    _check(lib().oracle_loglike_sets(_p(p), p.shape[0], _p(d), d.shape[0], _p(s),
+                                     ctypes.byref(c), _p(out)), "loglike_sets")
     return out
 
 

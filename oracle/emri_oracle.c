@@ -37,10 +37,13 @@
  *
  * Parity pins: see tests/test_oracle_*.py.  The spin-orbit and the
  * eccentricity-dependent 1PN terms of dnu/dt and de/dt in the BC04 orbital
- * equations and the absolute sign / orientation conventions of the response
- * are parity unpinned (no printed values exist to check); the 1PN terms at
- * e = 0, the 1PN pericentre advance and the Lense-Thirring precessions are
- * pinned against their textbook forms.
+ * equations are parity unpinned (no printed values exist to check, and the
+ * AK's spin-orbit chirp does not reduce to the test-mass one, so that limit
+ * cannot pin it); the 1PN terms at e = 0, the 1PN pericentre advance and the
+ * Lense-Thirring precessions are pinned against their textbook forms.  The
+ * response (Doppler phase, detector-frame angles, polarisation angle, beta)
+ * is pinned against vector constructions of the same geometry, up to the
+ * constant orientation offsets, which are a convention.
  */
 #include <math.h>
 #include <stdint.h>
@@ -665,7 +668,8 @@ int oracle_antenna(double cth, double phi, double psi, double *out2)
 /* ======================================================================== */
 /* Step 3: time-domain waveform of one walker at unit distance, GR.         */
 /* Writes channels I and II, x[2][N]; optional diagnostics per sample       */
-/* diag[N][8] = {h+, hx, A, c_iota, Phi', gamma, cos theta_d, 0}.           */
+/* diag[N][16] = {h+, hx, A, c_iota, Phi', gamma, cos theta_d, phi_d, psi,   */
+/* beta, Phi, nu, gamma~, alpha, e, 0}.                                       */
 /* ======================================================================== */
 static void walker_waveform(const double *p, const oracle_cfg *c, const double *orb, int64_t Kw,
                             double *x /* [2][N] */, double *diag /* [N][8] or NULL */)
@@ -675,7 +679,7 @@ static void walker_waveform(const double *p, const oracle_cfg *c, const double *
     double h = c->dt * (double)m;
     int nh = c->n_harm;
     memset(x, 0, (size_t)(2 * N) * sizeof(double));
-    if (diag) memset(diag, 0, (size_t)(8 * N) * sizeof(double));
+    if (diag) memset(diag, 0, (size_t)(16 * N) * sizeof(double));
     if (Kw <= 0) return;
 
     double M_s = p[I_M] * O_TSUN, mu_s = p[I_MU] * O_TSUN;
@@ -758,8 +762,10 @@ static void walker_waveform(const double *p, const oracle_cfg *c, const double *
         x[j] = 0.5 * s3 * (FpI * hp + FxI * hx);
         x[N + j] = 0.5 * s3 * (FpII * hp + FxII * hx);
         if (diag) {
-            double *d = diag + 8 * j;
+            double *d = diag + 16 * j;
             d[0] = hp; d[1] = hx; d[2] = A; d[3] = ci; d[4] = Phid; d[5] = gam; d[6] = cthd;
+            d[7] = phid; d[8] = psi; d[9] = beta; d[10] = Phi; d[11] = nu; d[12] = gt;
+            d[13] = al; d[14] = e;
         }
     }
     free(J);
@@ -897,17 +903,19 @@ static void nsum_add(neumaier *a, double v)
     a->s = t;
 }
 
-/* lnL = -1/2 sum_{channels} sum_{k=1}^{N/2-1} (4 df / S_k) |d_k - m_k|^2 (reading R8) */
-static double walker_loglike(const double *p, const double *data, const double *psd,
-                             const oracle_cfg *c, double *scratch_x, double *scratch_X)
+/* Scalars, orbit, waveform and both channels' spectra of one walker: the
+ * spectra (dt * DFT, bins 0..N/2, re/im interleaved) are left at
+ * scratch_X + 2N, channel I then II.  Returns 0, or -1 for an invalid walker
+ * (outside the physical domain, or an orbit that leaves it backward). */
+static int walker_spectrum(const double *p, const oracle_cfg *c, double s[8], double *scratch_x,
+                           double *scratch_X)
 {
-    double s[8];
     walker_scalars(p, c->ic_lso, s);
-    if (s[0] == 0.0) return -INFINITY;
+    if (s[0] == 0.0) return -1;
     int64_t N = c->N, K = n_intervals_of(c), H = N / 2 + 1;
     double *orb = (double *)malloc((size_t)(K + 1) * 10 * sizeof(double));
     int64_t Kw = walker_orbit(p, c, orb);
-    if (Kw < 0) { free(orb); return -INFINITY; }   /* left the physical range backward */
+    if (Kw < 0) { free(orb); return -1; }   /* left the physical range backward */
     walker_waveform(p, c, orb, Kw, scratch_x, NULL);
     free(orb);
     /* FFT both channels */
@@ -920,13 +928,22 @@ static double walker_loglike(const double *p, const double *data, const double *
         double *spec = scratch_X + 2 * N + ch * 2 * H;
         for (int64_t k = 0; k < H; ++k) { spec[2 * k] = c->dt * re[k]; spec[2 * k + 1] = c->dt * im[k]; }
     }
+    return 0;
+}
+
+/* lnL = -1/2 sum_{channels} sum_{k=1}^{N/2-1} (4 df / S_k) |d_k - m_k|^2
+ * (reading R8) from a walker's spectra (walker_spectrum) and scalars */
+static double spectrum_loglike(const double s[8], const double *spectra, const double *data,
+                               const double *psd, const oracle_cfg *c)
+{
+    int64_t N = c->N, H = N / 2 + 1;
     double g = s[5], dT = s[4];
     double df = 1.0 / ((double)N * c->dt);
     double phi = dT / ((double)N * c->dt);
     phi -= floor(phi);
     neumaier acc = {0.0, 0.0};
     for (int ch = 0; ch < 2; ++ch) {
-        const double *spec = scratch_X + 2 * N + ch * 2 * H;
+        const double *spec = spectra + ch * 2 * H;
         const double *d = data + ch * 2 * H;
         for (int64_t k = 1; k < N / 2; ++k) {
             double cr, ci;
@@ -939,6 +956,14 @@ static double walker_loglike(const double *p, const double *data, const double *
         }
     }
     return -0.5 * (acc.s + acc.c);
+}
+
+static double walker_loglike(const double *p, const double *data, const double *psd,
+                             const oracle_cfg *c, double *scratch_x, double *scratch_X)
+{
+    double s[8];
+    if (walker_spectrum(p, c, s, scratch_x, scratch_X)) return -INFINITY;
+    return spectrum_loglike(s, scratch_X + 2 * c->N, data, psd, c);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1043,6 +1068,32 @@ int oracle_loglike(const double *params, int64_t B, const double *data /* [2][N/
 #pragma omp for schedule(dynamic, 1)
         for (int64_t w = 0; w < B; ++w)
             lnL[w] = walker_loglike(params + w * NPAR, data, psd, c, sx, sX);
+        free(sx);
+        free(sX);
+    }
+    return 0;
+}
+
+/* The likelihood of each walker against several data sets (data
+ * [nset][2][N/2+1][2]) from one evaluation of its spectrum: lnL[B][nset].
+ * Each entry equals oracle_loglike's for that data set. */
+int oracle_loglike_sets(const double *params, int64_t B, const double *data, int32_t nset,
+                        const double *psd, const oracle_cfg *c, double *lnL)
+{
+    if (!cfg_ok(c) || nset < 1) return -1;
+    int64_t N = c->N, H = N / 2 + 1;
+#pragma omp parallel if (B >= oracle_num_threads())
+    {
+        double *sx = (double *)malloc((size_t)(2 * N) * sizeof(double));
+        double *sX = (double *)malloc((size_t)(2 * N + 4 * H) * sizeof(double));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t w = 0; w < B; ++w) {
+            double s[8];
+            int bad = walker_spectrum(params + w * NPAR, c, s, sx, sX);
+            for (int32_t q = 0; q < nset; ++q)
+                lnL[w * nset + q] = bad ? -INFINITY
+                                        : spectrum_loglike(s, sX + 2 * N, data + q * 4 * H, psd, c);
+        }
         free(sx);
         free(sX);
     }

@@ -18,10 +18,13 @@
  *    must stay valid, and outputs must not be read, until the stream has
  *    reached the call's end.  Calls that share a workspace must be ordered.
  *    Waveform generation may also run on an auxiliary stream the library
- *    keeps per (device, caller stream), created on the first call; it is
- *    forked from and joined back into `stream` by events within the call
- *    (also under stream capture), so `stream` alone orders the call.  The
- *    auxiliary streams are the only resources the library keeps.  Calls on
+ *    keeps per (device, caller stream), created on the first call made while
+ *    `stream` is not capturing; it is forked from and joined back into
+ *    `stream` by events within the call (also under stream capture), so
+ *    `stream` alone orders the call.  A call on a capturing stream that has
+ *    no auxiliary stream yet creates none and runs on `stream` alone (same
+ *    results).  The auxiliary streams are the only resources the library
+ *    keeps.  Calls on
  *    one stream must come from one host thread at a time (as for any
  *    stream); calls on different streams may run concurrently.
  *  - Call-level errors (null pointer, bad configuration, workspace too
@@ -57,7 +60,7 @@ extern "C" {
 #endif
 
 #define EMRI_NPAR 17
-#define EMRI_ABI_VERSION 5
+#define EMRI_ABI_VERSION 6
 
 typedef enum {
     EMRI_OK = 0,
@@ -131,6 +134,33 @@ typedef struct {
 
 /* Library ABI version (EMRI_ABI_VERSION). */
 int emri_abi_version(void);
+
+/* Launch-plan overrides (process-wide), for measurement and tests.  Each
+ * field 0 means automatic.  A call plans with one consistent copy of the
+ * overrides taken when it starts; changing them while calls run is safe but
+ * the running calls keep their plan.  Workspace sizes follow the overrides
+ * (size workspaces after setting them).  Results are bitwise independent of
+ * orbit_segments and like_walkers_per_wg; fft_row_log2 and
+ * fft_col_run_bytes change the transform's factorisation and so its
+ * rounding, within the precision's tolerance.
+ *  orbit_segments       orbit segments pipelined against the synthesis, 1..16
+ *                       (automatic: about 384 coarse steps each, at most 8)
+ *  fft_row_log2         log2 of the FFT's row length (the fused likelihood
+ *                       pass), 7..12, applied where both passes support it
+ *  fft_col_run_bytes    bytes of adjacent columns per column-pass row read,
+ *                       a power of two in 8..256 (automatic: 128 FP64, 64 FP32)
+ *  like_walkers_per_wg  walkers per workgroup of the likelihood pass, 1..32
+ * emri_tuning_set(NULL) restores automatic plans.  Out-of-range fields:
+ * EMRI_EINVAL and nothing changes. */
+typedef struct {
+    int32_t orbit_segments;
+    int32_t fft_row_log2;
+    int32_t fft_col_run_bytes;
+    int32_t like_walkers_per_wg;
+    int32_t reserved;            /* 0 */
+} emri_tuning;
+emri_status emri_tuning_set(const emri_tuning* t);
+emri_status emri_tuning_get(emri_tuning* t);
 
 /* Message for the last non-OK status returned on this host thread. */
 const char* emri_last_error(void);

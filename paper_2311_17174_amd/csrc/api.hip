@@ -91,7 +91,20 @@ static emri_status fail_hip(hipError_t e, const char* where)
     return EMRI_EDEVICE;
 }
 
-emri_status make_plan(const emri_cfg* cfg, int64_t B, Plan* p, const char** err)
+// ---- launch-plan overrides --------------------------------------------------
+// Set only through emri_tuning_set; a call takes one copy under the lock and
+// plans with it throughout, so a concurrent change never mixes two plans.
+static std::mutex g_tuning_mu;
+static Tuning g_tuning = {0, 0, 0, 0};
+
+Tuning tuning_now()
+{
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    return g_tuning;
+}
+
+emri_status make_plan(const emri_cfg* cfg, int64_t B, const Tuning& tn, Plan* p,
+                      const char** err)
 {
     *err = nullptr;
     if (!cfg) { *err = "cfg is NULL"; return EMRI_EINVAL; }
@@ -134,6 +147,7 @@ emri_status make_plan(const emri_cfg* cfg, int64_t B, Plan* p, const char** err)
 
     Plan& q = *p;
     memset(&q, 0, sizeof q);
+    q.tn = tn;
     q.T_obs = cfg->T_obs;
     q.ic = cfg->ic;
     q.ode = cfg->ode;
@@ -154,10 +168,9 @@ emri_status make_plan(const emri_cfg* cfg, int64_t B, Plan* p, const char** err)
     // 2^12 so a row transform has 512 lanes; columns the rest (up to 2^12)
     q.m1 = (m + 1) / 2 + 1;
     if (q.m1 > 12) q.m1 = 12;
-    // EMRI_FFT_M1 overrides the row length 2^m1 (for tuning), within the
-    // ranges both passes support
-    if (const char* env = getenv("EMRI_FFT_M1")) {
-        const int v = atoi(env);
+    // an override of the row length 2^m1 applies where both passes support it
+    if (tn.fft_row_log2) {
+        const int v = tn.fft_row_log2;
         if (v >= 7 && v <= 12 && m - v >= 4 && m - v <= 12) q.m1 = v;
     }
     q.m2 = m - q.m1;
@@ -166,10 +179,10 @@ emri_status make_plan(const emri_cfg* cfg, int64_t B, Plan* p, const char** err)
     q.esz = (q.prec == EMRI_FP64) ? 16 : 8;
     q.hsz = (q.prec == EMRI_FP64) ? 8 : 4;
     // pass-A workgroup: TA columns in rows of TA * esz = 128 bytes (FP64) or
-    // 64 bytes (FP32) (EMRI_FFT_TA_BYTES overrides, for tuning), within 1024
-    // lanes (16 values each) and the 160 KiB of LDS a workgroup may hold
+    // 64 bytes (FP32) (or the override), within 1024 lanes (16 values each)
+    // and the 160 KiB of LDS a workgroup may hold
     size_t run_bytes = (q.prec == EMRI_FP64) ? 128 : 64;
-    if (const char* env = getenv("EMRI_FFT_TA_BYTES")) run_bytes = (size_t)atoi(env);
+    if (tn.fft_col_run_bytes) run_bytes = (size_t)tn.fft_col_run_bytes;
     int ta = (int)(run_bytes / q.esz);
     if (ta < 1) ta = 1;
     while (ta > 16) ta /= 2;
@@ -226,8 +239,13 @@ struct Pipe {
 static std::mutex g_pipe_mu;
 static std::map<std::pair<int, hipStream_t>, Pipe> g_pipes;
 
+// the auxiliary stream and events of caller stream s on the current device:
+// found, or created when s is not capturing; *out = nullptr (and EMRI_OK)
+// when s is capturing and has none, so that nothing is created inside a
+// capture (the call then runs its orbit in one segment on s alone)
 static emri_status get_pipe(hipStream_t s, Pipe** out)
 {
+    *out = nullptr;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return fail_hip(e, "pipeline: hipGetDevice");
@@ -237,6 +255,10 @@ static emri_status get_pipe(hipStream_t s, Pipe** out)
         *out = &it->second;
         return EMRI_OK;
     }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    e = hipStreamIsCapturing(s, &cs);
+    if (e != hipSuccess) return fail_hip(e, "pipeline: hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone) return EMRI_OK;
     Pipe q;
     e = hipStreamCreateWithFlags(&q.aux, hipStreamNonBlocking);
     for (int i = 0; i < kMaxSeg && e == hipSuccess; ++i)
@@ -253,8 +275,16 @@ static emri_status get_pipe(hipStream_t s, Pipe** out)
     return EMRI_OK;
 }
 
-// number of orbit segments: about 384 coarse steps each, at most 8
-// (EMRI_ORBIT_SEGMENTS overrides, 1 .. 16, for tuning and tests)
+emri_status prepare_pipe(hipStream_t s)
+{
+    Pipe* pp = nullptr;
+    const emri_status st = get_pipe(s, &pp);
+    if (st == EMRI_OK && !pp) return fail(EMRI_EINVAL, "pipeline: stream is capturing");
+    return st;
+}
+
+// number of orbit segments: about 384 coarse steps each, at most 8 (the
+// override: 1 .. 16)
 static int orbit_segments(const Plan& p, bool zero_tail)
 {
     // From the LSO the orbit is integrated backward and the segments run in
@@ -264,7 +294,7 @@ static int orbit_segments(const Plan& p, bool zero_tail)
     // take their samples only from valid walkers.
     if (p.ic == EMRI_IC_LSO && zero_tail) return 1;
     int64_t S = p.K / 384;
-    if (const char* env = getenv("EMRI_ORBIT_SEGMENTS")) S = atoi(env);
+    if (p.tn.orbit_segments) S = p.tn.orbit_segments;
     else if (S > 8) S = 8;
     if (S > kMaxSeg) S = kMaxSeg;
     if (S > p.K) S = p.K;
@@ -277,7 +307,7 @@ static int orbit_segments(const Plan& p, bool zero_tail)
 static emri_status run_waveforms(const Plan& p, const double* params, int64_t B, void* ws,
                                  void* out, bool zero_tail, hipStream_t s)
 {
-    const int S = orbit_segments(p, zero_tail);
+    int S = orbit_segments(p, zero_tail);
     const bool back = p.ic == EMRI_IC_LSO;
     // synthesis intervals: with the zero tail up to N / L, else those covering N_valid
     const int64_t KT = zero_tail ? p.N / p.L : p.K;
@@ -294,6 +324,11 @@ static emri_status run_waveforms(const Plan& p, const double* params, int64_t B,
     auto hi = [&](int i) -> int64_t { return back ? p.K - kb(i) : kb(i + 1); };
     emri_status st;
     if ((st = check_launch(launch_azimuth(p, ws, s), "azimuth table"))) return st;
+    Pipe* pp = nullptr;
+    if (S > 1) {
+        if ((st = get_pipe(s, &pp))) return st;
+        if (!pp) S = 1;   // first use of s inside a capture: one segment
+    }
     if (S == 1) {
         if ((st = check_launch(launch_walker_setup(p, params, B, ws, back ? 0 : p.K, s),
                                "walker setup")))
@@ -302,8 +337,6 @@ static emri_status run_waveforms(const Plan& p, const double* params, int64_t B,
             return st;
         return check_launch(launch_synth(p, B, ws, out, 0, KT, 0, zero_tail, s), "synthesis");
     }
-    Pipe* pp = nullptr;
-    if ((st = get_pipe(s, &pp))) return st;
     // the first segment's last node: kb(1) forward, K - kb(1) backward
     st = check_launch(launch_walker_setup(p, params, B, ws, back ? lo(0) : hi(0), s),
                       "walker setup");
@@ -340,14 +373,14 @@ static emri_status run_waveforms(const Plan& p, const double* params, int64_t B,
 }
 
 // largest chunk <= B whose plan fits in `bytes`
-static int64_t fit_chunk(const emri_cfg* cfg, int64_t B, size_t bytes)
+static int64_t fit_chunk(const emri_cfg* cfg, int64_t B, size_t bytes, const Tuning& tn)
 {
     Plan p;
     const char* err;
     int64_t lo = 0, hi = B;
     while (lo < hi) {
         const int64_t mid = lo + (hi - lo + 1) / 2;
-        make_plan(cfg, mid, &p, &err);
+        make_plan(cfg, mid, tn, &p, &err);
         if (p.total <= bytes) lo = mid;
         else hi = mid - 1;
     }
@@ -362,13 +395,47 @@ extern "C" {
 
 int emri_abi_version(void) { return EMRI_ABI_VERSION; }
 
+emri_status emri_tuning_set(const emri_tuning* t)
+{
+    Tuning v = {0, 0, 0, 0};
+    if (t) {
+        if (t->orbit_segments < 0 || t->orbit_segments > kMaxSeg)
+            return fail(EMRI_EINVAL, "tuning: orbit_segments must be 0 (automatic) or 1..16");
+        if (t->fft_row_log2 != 0 && (t->fft_row_log2 < 7 || t->fft_row_log2 > 12))
+            return fail(EMRI_EINVAL, "tuning: fft_row_log2 must be 0 (automatic) or 7..12");
+        const int rb = t->fft_col_run_bytes;
+        if (rb != 0 && (rb < 8 || rb > 256 || (rb & (rb - 1))))
+            return fail(EMRI_EINVAL,
+                        "tuning: fft_col_run_bytes must be 0 (automatic) or a power of two in 8..256");
+        if (t->like_walkers_per_wg < 0 || t->like_walkers_per_wg > 32)
+            return fail(EMRI_EINVAL, "tuning: like_walkers_per_wg must be 0 (automatic) or 1..32");
+        if (t->reserved != 0) return fail(EMRI_EINVAL, "tuning: reserved must be 0");
+        v = Tuning{t->orbit_segments, t->fft_row_log2, rb, t->like_walkers_per_wg};
+    }
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    g_tuning = v;
+    return EMRI_OK;
+}
+
+emri_status emri_tuning_get(emri_tuning* t)
+{
+    if (!t) return fail(EMRI_EINVAL, "null pointer argument");
+    const Tuning v = tuning_now();
+    t->orbit_segments = v.orbit_segments;
+    t->fft_row_log2 = v.fft_row_log2;
+    t->fft_col_run_bytes = v.fft_col_run_bytes;
+    t->like_walkers_per_wg = v.like_walkers_per_wg;
+    t->reserved = 0;
+    return EMRI_OK;
+}
+
 const char* emri_last_error(void) { return g_err.c_str(); }
 
 size_t emri_workspace_bytes(const emri_cfg* cfg, int64_t B)
 {
     Plan p;
     const char* err;
-    if (make_plan(cfg, B < 1 ? 1 : B, &p, &err) != EMRI_OK) return 0;
+    if (make_plan(cfg, B < 1 ? 1 : B, tuning_now(), &p, &err) != EMRI_OK) return 0;
     return p.total;
 }
 
@@ -376,7 +443,7 @@ size_t emri_dataset_bytes(const emri_cfg* cfg)
 {
     Plan p;
     const char* err;
-    if (make_plan(cfg, 1, &p, &err) != EMRI_OK) return 0;
+    if (make_plan(cfg, 1, tuning_now(), &p, &err) != EMRI_OK) return 0;
     return p.ds_total;
 }
 
@@ -385,7 +452,7 @@ emri_status emri_waveform_batch(const double* params, int64_t B, const emri_cfg*
 {
     Plan p;
     const char* err;
-    emri_status st = make_plan(cfg, B, &p, &err);
+    emri_status st = make_plan(cfg, B, tuning_now(), &p, &err);
     if (st != EMRI_OK) return fail(st, err);
     if (B == 0) return EMRI_OK;
     if (!params || !ht || !ws) return fail(EMRI_EINVAL, "null pointer argument");
@@ -398,7 +465,7 @@ emri_status emri_fft_batch(const void* ht, int64_t B, const emri_cfg* cfg, void*
 {
     Plan p;
     const char* err;
-    emri_status st = make_plan(cfg, B, &p, &err);
+    emri_status st = make_plan(cfg, B, tuning_now(), &p, &err);
     if (st != EMRI_OK) return fail(st, err);
     if (B == 0) return EMRI_OK;
     if (!ht || !hf || !ws) return fail(EMRI_EINVAL, "null pointer argument");
@@ -413,14 +480,15 @@ static emri_status loglike_chunks(const emri_cfg* cfg, const double* params, int
                                   hipStream_t stream, const emri_fmg* fmg = nullptr,
                                   const double* coef = nullptr)
 {
+    const Tuning tn = tuning_now();
     Plan p1;
     const char* err;
-    emri_status st = make_plan(cfg, 1, &p1, &err);
+    emri_status st = make_plan(cfg, 1, tn, &p1, &err);
     if (st != EMRI_OK) return fail(st, err);
     if (ws_bytes < p1.total) return fail(EMRI_EWORKSPACE, "workspace smaller than emri_workspace_bytes(cfg, 1)");
-    const int64_t chunk = fit_chunk(cfg, B, ws_bytes);
+    const int64_t chunk = fit_chunk(cfg, B, ws_bytes, tn);
     Plan p;
-    make_plan(cfg, chunk, &p, &err);
+    make_plan(cfg, chunk, tn, &p, &err);
     if ((st = check_launch(launch_twiddles(p, ws, stream), "twiddles"))) return st;
     for (int64_t w0 = 0; w0 < B; w0 += chunk) {
         const int64_t nb = (B - w0 < chunk) ? (B - w0) : chunk;
@@ -444,7 +512,7 @@ emri_status emri_loglike_batch(const double* params, int64_t B, const double* da
 {
     Plan p;
     const char* err;
-    emri_status st = make_plan(cfg, 1, &p, &err);
+    emri_status st = make_plan(cfg, 1, tuning_now(), &p, &err);
     if (st != EMRI_OK) return fail(st, err);
     if (T_obs != cfg->T_obs || dt != cfg->dt) return fail(EMRI_EINVAL, "T_obs and dt must equal cfg->T_obs and cfg->dt");
     if (B < 0) return fail(EMRI_EINVAL, "B must be >= 0");
@@ -461,7 +529,7 @@ emri_status emri_dataset_init(const double* data, const double* psd, const emri_
 {
     Plan p;
     const char* err;
-    emri_status st = make_plan(cfg, 1, &p, &err);
+    emri_status st = make_plan(cfg, 1, tuning_now(), &p, &err);
     if (st != EMRI_OK) return fail(st, err);
     if (!data || !psd || !ds) return fail(EMRI_EINVAL, "null pointer argument");
     if (ds_bytes < p.ds_total) return fail(EMRI_EWORKSPACE, "dataset buffer smaller than emri_dataset_bytes(cfg)");
@@ -474,7 +542,7 @@ emri_status emri_loglike_dataset(const double* params, int64_t B, const void* ds
 {
     Plan p;
     const char* err;
-    emri_status st = make_plan(cfg, 1, &p, &err);
+    emri_status st = make_plan(cfg, 1, tuning_now(), &p, &err);
     if (st != EMRI_OK) return fail(st, err);
     if (B < 0) return fail(EMRI_EINVAL, "B must be >= 0");
     if (B == 0) return EMRI_OK;
@@ -488,7 +556,7 @@ emri_status emri_loglike_dataset_fmg(const double* params, int64_t B, const doub
 {
     Plan p;
     const char* err;
-    emri_status st = make_plan(cfg, 1, &p, &err);
+    emri_status st = make_plan(cfg, 1, tuning_now(), &p, &err);
     if (st != EMRI_OK) return fail(st, err);
     if (!fmg) return fail(EMRI_EINVAL, "null fmg descriptor");
     if (fmg->order < 0 || fmg->order > EMRI_FMG_MAX)
@@ -539,7 +607,7 @@ emri_status emri_model_batch(const double* params, int64_t B, const emri_cfg* cf
 {
     Plan p;
     const char* err;
-    emri_status st = make_plan(cfg, B, &p, &err);
+    emri_status st = make_plan(cfg, B, tuning_now(), &p, &err);
     if (st != EMRI_OK) return fail(st, err);
     if (B == 0) return EMRI_OK;
     if (!params || !mf || !ws) return fail(EMRI_EINVAL, "null pointer argument");
@@ -627,7 +695,7 @@ emri_status emri_stretch_step(double* X, double* lnp, int64_t W, const emri_prio
     if (!X || !lnp || !u || !ds || !ws) return fail(EMRI_EINVAL, "null pointer argument");
     Plan p1;
     const char* err;
-    if ((st = make_plan(cfg, 1, &p1, &err)) != EMRI_OK) return fail(st, err);
+    if ((st = make_plan(cfg, 1, tuning_now(), &p1, &err)) != EMRI_OK) return fail(st, err);
     const size_t head = sampler_head_bytes(W);
     if (ws_bytes < head + p1.total)
         return fail(EMRI_EWORKSPACE, "workspace smaller than the proposals plus emri_workspace_bytes(cfg, 1)");

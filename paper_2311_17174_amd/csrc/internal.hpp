@@ -74,8 +74,19 @@ constexpr double kYearSeconds = 365.25 * 86400.0;          // Julian year
 constexpr double kHubble = 67.66;                           // km/s/Mpc
 constexpr double kOmegaM = 0.3111;
 
+// ---- launch-plan overrides (emri_tuning_set); 0 = automatic -------------
+struct Tuning {
+    int orbit_segments;    // 1..kMaxSeg
+    int fft_row_log2;      // 7..12
+    int fft_col_run_bytes; // 8..256, a power of two
+    int like_walkers_per_wg;  // 1..32
+};
+// one consistent copy of the process-wide overrides
+Tuning tuning_now();
+
 // ---- plan: sizes and workspace offsets ----------------------------------
 struct Plan {
+    Tuning tn;             // overrides this plan was made with
     // problem
     double T_obs, dt;
     int64_t N, Nv;         // transform length, valid samples
@@ -102,8 +113,9 @@ struct Plan {
     size_t ds_off_d, ds_off_w, ds_off_norm, ds_off_npart, ds_total;
 };
 
-// fills p; returns EMRI_OK or an error (message in err)
-emri_status make_plan(const emri_cfg* cfg, int64_t B, Plan* p, const char** err);
+// fills p with the overrides tn; returns EMRI_OK or an error (message in err)
+emri_status make_plan(const emri_cfg* cfg, int64_t B, const Tuning& tn, Plan* p,
+                      const char** err);
 
 // twiddle table layout inside the tw region (complex fp64 then fp32 copies)
 struct TwLayout {
@@ -196,6 +208,10 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // is set once per kernel and size, so captured launch sequences make no
 // attribute calls after the first eager use
 hipError_t allow_lds(const void* kernel, size_t bytes);
+
+// create the orbit pipeline's auxiliary stream and events for caller stream
+// s now (not capturing), so that later captures on s can use them
+emri_status prepare_pipe(hipStream_t s);
 
 // record `msg` as the calling thread's last error and return `st`
 emri_status set_error(emri_status st, const char* msg);

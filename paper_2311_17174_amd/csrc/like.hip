@@ -554,11 +554,8 @@ hipError_t launch_likelihood(const Plan& p, int64_t B, const void* ds, void* ws,
     double* part = (double*)(base + p.off_part);
     const int L = (int)p.R1;
     int WT = (B >= 128) ? 8 : (B >= 16 ? 4 : 1);
-    // EMRI_LIKE_WT overrides the walkers per workgroup (for tuning), 1..32
-    if (const char* env = getenv("EMRI_LIKE_WT")) {
-        const int v = atoi(env);
-        if (v >= 1 && v <= 32) WT = v;
-    }
+    if (p.tn.like_walkers_per_wg >= 1 && p.tn.like_walkers_per_wg <= 32)
+        WT = p.tn.like_walkers_per_wg;
     const size_t lds = (p.prec == EMRI_FP64) ? (size_t)padded_len<double>(L) * 2 * 8
                                              : (size_t)padded_len<float>(L) * 2 * 4;
     const int64_t nparts = p.R2 / 2 + 1;

@@ -30,7 +30,8 @@ EXPORTED = ("emri_abi_version", "emri_last_error", "emri_workspace_bytes",
             "emri_dataset_bytes", "emri_dataset_init", "emri_loglike_dataset",
             "emri_model_batch", "emri_noise_psd", "emri_trace_enable", "emri_trace_read",
             "emri_trace_stage_name", "emri_sampler_workspace_bytes", "emri_ensemble_lnprob",
-            "emri_stretch_step", "emri_loglike_dataset_fmg")
+            "emri_stretch_step", "emri_loglike_dataset_fmg", "emri_tuning_set",
+            "emri_tuning_get")
 
 
 class EmriError(RuntimeError):
@@ -62,6 +63,12 @@ def make_prior(free_idx, lo, hi) -> _Prior:
     for d, (i, a, b) in enumerate(zip(free_idx, lo, hi)):
         pr.idx[d], pr.lo[d], pr.hi[d] = int(i), float(a), float(b)
     return pr
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("orbit_segments", ctypes.c_int32), ("fft_row_log2", ctypes.c_int32),
+                ("fft_col_run_bytes", ctypes.c_int32), ("like_walkers_per_wg", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class _Fmg(ctypes.Structure):
@@ -128,6 +135,8 @@ def _load():
                                      ctypes.c_int),
         "emri_stretch_step": ([vp, vp, i64, ctypes.POINTER(_Prior), d, vp, vp, cp, vp, vp, sz,
                                vp], ctypes.c_int),
+        "emri_tuning_set": ([ctypes.POINTER(_Tuning)], ctypes.c_int),
+        "emri_tuning_get": ([ctypes.POINTER(_Tuning)], ctypes.c_int),
     }
     for name, (a, r) in sig.items():
         f = getattr(L, name)
@@ -160,6 +169,41 @@ def _dev(t: torch.Tensor, dtype: torch.dtype, shape, name: str):
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
     return t.data_ptr()
+
+
+TUNING_FIELDS = ("orbit_segments", "fft_row_log2", "fft_col_run_bytes", "like_walkers_per_wg")
+
+
+def get_tuning() -> dict:
+    """The process-wide launch-plan overrides (emri_tuning_get); 0 = automatic."""
+    t = _Tuning()
+    _check(lib.emri_tuning_get(ctypes.byref(t)), "emri_tuning_get")
+    return {n: getattr(t, n) for n in TUNING_FIELDS}
+
+
+def set_tuning(**kw) -> None:
+    """Set the launch-plan overrides (emri_tuning_set); fields not named are
+    automatic (0)."""
+    bad = set(kw) - set(TUNING_FIELDS)
+    if bad:
+        raise KeyError(sorted(bad))
+    t = _Tuning(*[int(kw.get(n, 0)) for n in TUNING_FIELDS], 0)
+    _check(lib.emri_tuning_set(ctypes.byref(t)), "emri_tuning_set")
+
+
+class tuning:
+    """Context manager: the overrides kw inside, the previous ones after."""
+
+    def __init__(self, **kw):
+        self.kw = kw
+
+    def __enter__(self):
+        self.prev = get_tuning()
+        set_tuning(**self.kw)
+        return self
+
+    def __exit__(self, *exc):
+        set_tuning(**self.prev)
 
 
 def workspace_bytes(cfg: Config, B: int) -> int:

@@ -18,3 +18,12 @@ def oracle_lib():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+@pytest.fixture(autouse=True)
+def _automatic_launch_plans():
+    """Launch-plan overrides a test sets (emri.set_tuning) end with it."""
+    yield
+    E = sys.modules.get("paper_2311_17174_amd.emri")
+    if E is not None:
+        E.set_tuning()

@@ -106,16 +106,16 @@ def test_dp5_lso_convention(E, prec):
 
 
 @pytest.mark.parametrize("segs", [3, 7])
-def test_dp5_segments_bitwise(E, monkeypatch, segs):
+def test_dp5_segments_bitwise(E, segs):
     """The step sequence does not depend on where orbit segments end: the
     waveform in segments equals the one-segment waveform bit for bit (with
     rejected steps, steps spanning segment ends and a plunge)."""
     w = dp5(fast_inspiral("fp64"), 1e-6)
     P = edge_rows(w)
     cfg = E.Config.from_workload(w)
-    monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", "1")
+    E.set_tuning(orbit_segments=1)
     one = E.waveform_batch(gpu(P), cfg).cpu().numpy()
-    monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", str(segs))
+    E.set_tuning(orbit_segments=segs)
     for _ in range(2):
         assert np.array_equal(E.waveform_batch(gpu(P), cfg).cpu().numpy(), one)
 

@@ -72,7 +72,7 @@ def test_lso_loglike_parity(E, prec):
 
 @pytest.mark.parametrize("ode", [0, 1])
 @pytest.mark.parametrize("segs", [3, 7])
-def test_lso_segments_bitwise(E, monkeypatch, ode, segs):
+def test_lso_segments_bitwise(E, ode, segs):
     """The backward orbit in segments (reverse time order, each segment's
     tables and samples built while the orbit goes on back in time) gives the
     likelihood and the model of one segment bit for bit, with a walker whose
@@ -92,10 +92,10 @@ def test_lso_segments_bitwise(E, monkeypatch, ode, segs):
     cfg = E.Config.from_workload(w)
     ds = E.dataset_init(dd, ss, cfg)
     Pt = torch.from_numpy(P).cuda()
-    monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", "1")
+    E.set_tuning(orbit_segments=1)
     one = E.loglike_dataset(Pt, ds, cfg).cpu().numpy()
     m1 = E.model_batch(Pt, cfg).cpu().numpy()
-    monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", str(segs))
+    E.set_tuning(orbit_segments=segs)
     for _ in range(2):
         assert np.array_equal(E.loglike_dataset(Pt, ds, cfg).cpu().numpy(), one)
     assert np.array_equal(E.loglike_batch(Pt, dd, ss, cfg).cpu().numpy(), one)
@@ -108,7 +108,7 @@ def test_lso_segments_bitwise(E, monkeypatch, ode, segs):
 
 
 @pytest.mark.parametrize("ode", [0, 1])
-def test_lso_empty_first_segments(E, monkeypatch, ode):
+def test_lso_empty_first_segments(E, ode):
     """16 segments of a 22-interval orbit: the first backward segments are
     empty (node K alone); the likelihood equals the one-segment one."""
     w = W.small("fp64", n_harm=6).with_(ic=1, ode=ode, ode_rtol=1e-10, ode_atol=1e-10)
@@ -118,9 +118,9 @@ def test_lso_empty_first_segments(E, monkeypatch, ode):
     cfg = E.Config.from_workload(w)
     ds = E.dataset_init(dd, ss, cfg)
     Pt = torch.from_numpy(P).cuda()
-    monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", "1")
+    E.set_tuning(orbit_segments=1)
     one = E.loglike_dataset(Pt, ds, cfg).cpu().numpy()
-    monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", "16")
+    E.set_tuning(orbit_segments=16)
     assert np.array_equal(E.loglike_dataset(Pt, ds, cfg).cpu().numpy(), one)
     assert one[6] == -np.inf and np.all(np.isfinite(one[:6]))
 

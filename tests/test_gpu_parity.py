@@ -264,7 +264,7 @@ def test_batch_invariance_and_chunking(E):
 
 
 @pytest.mark.parametrize("segs", [2, 5, 16])
-def test_orbit_segments_bitwise(E, monkeypatch, segs):
+def test_orbit_segments_bitwise(E, segs):
     """The orbit integrated in segments, with the tables and samples of each
     finished segment built on a second stream, gives the same bits as one
     segment: edge walkers, and fast inspirals that reach the LSO inside a
@@ -274,9 +274,9 @@ def test_orbit_segments_bitwise(E, monkeypatch, segs):
     _, kw = O.orbit(P[:3], ocfg(w))
     say("segments", segs, "plunge nodes", kw, "of", w.n_intervals)
     cfg = E.Config.from_workload(w)
-    monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", "1")
+    E.set_tuning(orbit_segments=1)
     ref = E.waveform_batch(gpu_params(P), cfg).cpu().numpy()
-    monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", str(segs))
+    E.set_tuning(orbit_segments=segs)
     got = E.waveform_batch(gpu_params(P), cfg).cpu().numpy()
     assert np.array_equal(got, ref)
     # likelihood through the same pipeline, twice (events and streams reused)
@@ -285,9 +285,9 @@ def test_orbit_segments_bitwise(E, monkeypatch, segs):
     d, S = oracle_dataset(ws, True)
     dd, ss = to_device_data(d, S)
     cs = E.Config.from_workload(ws)
-    monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", "1")
+    E.set_tuning(orbit_segments=1)
     one = E.loglike_batch(gpu_params(Q), dd, ss, cs).cpu().numpy()
-    monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", str(segs))
+    E.set_tuning(orbit_segments=segs)
     for _ in range(2):
         assert np.array_equal(E.loglike_batch(gpu_params(Q), dd, ss, cs).cpu().numpy(), one)
 

@@ -44,11 +44,11 @@ def alone(E, cfg, dd, ss, P):
 
 
 @pytest.mark.parametrize("segs", [None, "3"])
-def test_served_equals_alone_in_the_mix(E, monkeypatch, segs):
+def test_served_equals_alone_in_the_mix(E, segs):
     """segs = "3": the captured graphs hold the orbit-segment pipeline's
     second stream (fork and join inside the capture)"""
     if segs:
-        monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", segs)
+        E.set_tuning(orbit_segments=int(segs))
     sets = two_datasets(E)
     arena = torch.empty(3 << 30, dtype=torch.uint8, device="cuda")
     reqs = []
@@ -124,12 +124,12 @@ def test_served_lso_dataset(E):
 
 
 @pytest.mark.parametrize("ic", [0, 1])
-def test_served_adaptive_orbit(E, monkeypatch, ic):
+def test_served_adaptive_orbit(E, ic):
     """Data sets whose orbits use the adaptive integrator (one wave per
     walker, lanes sharing each step's nodes; at t = 0 in three pipelined
     segments, or backward from the LSO) served eagerly, captured and replayed:
     bitwise the walkers evaluated alone, which agree with the oracle."""
-    monkeypatch.setenv("EMRI_ORBIT_SEGMENTS", "3")
+    E.set_tuning(orbit_segments=3)
     w = W.small("fp64", n_harm=6, days=20.0, N=1 << 18).with_(ic=ic, ode=1, ode_rtol=1e-10,
                                                               ode_atol=1e-10)
     d, S = oracle_dataset(w, True)

@@ -104,7 +104,7 @@ def lib():
             "oracle_waveform_diag": ([dp, cp, dp, dp], ctypes.c_int),
             "oracle_rfft": ([dp, i64, i64, ctypes.c_double, dp], ctypes.c_int),
             "oracle_loglike": ([dp, i64, dp, dp, cp, dp], ctypes.c_int),
-            "oracle_loglike_sets": ([dp, i64, dp, ctypes.c_int32, dp, cp, dp], ctypes.c_int),
+            "oracle_loglike_sets": ([dp, i64, dp, ctypes.c_int32, dp, cp, dp, dp], ctypes.c_int),
             "oracle_loglike_fmg": ([dp, i64, dp, ctypes.c_int32, ctypes.c_double, dp, dp, cp,
                                     dp], ctypes.c_int),
             "oracle_psd_bc04": ([dp, i64, dp], ctypes.c_int),
@@ -253,10 +253,11 @@ def loglike(params, data, psd, cfg: OracleConfig) -> np.ndarray:
     return out
 
 
-def loglike_sets(params, datasets, psd, cfg: OracleConfig) -> np.ndarray:
+def loglike_sets(params, datasets, psd, cfg: OracleConfig, return_spectra: bool = False):
     """[B][nset]: lnL of each walker against each data set [2][N/2+1]
     complex, from one evaluation of the walker's spectrum (each entry equals
-    loglike() for that data set)."""
+    loglike() for that data set).  With return_spectra, also the walkers'
+    unit-distance GR spectra [B][2][N/2+1] complex (as spectrum())."""
     p = _f64(params).reshape(-1, NPAR)
     d = np.ascontiguousarray(np.stack([_cplx_pairs(x) for x in datasets]))
     s = _f64(psd)
@@ -264,8 +265,12 @@ def loglike_sets(params, datasets, psd, cfg: OracleConfig) -> np.ndarray:
     assert d.shape[1:] == (2, H, 2) and s.shape == (H,)
     out = np.zeros((p.shape[0], d.shape[0]))
     c = cfg.c()
+    spec = np.zeros((p.shape[0], 2, H, 2)) if return_spectra else None
     _check(lib().oracle_loglike_sets(_p(p), p.shape[0], _p(d), d.shape[0], _p(s),
-                                     ctypes.byref(c), _p(out)), "loglike_sets")
+                                     ctypes.byref(c), _p(out),
+                                     _p(spec) if spec is not None else None), "loglike_sets")
+    if return_spectra:
+        return out, spec[..., 0] + 1j * spec[..., 1]
     return out
 
 

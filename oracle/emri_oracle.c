@@ -1076,9 +1076,12 @@ int oracle_loglike(const double *params, int64_t B, const double *data /* [2][N/
 
 /* The likelihood of each walker against several data sets (data
  * [nset][2][N/2+1][2]) from one evaluation of its spectrum: lnL[B][nset].
- * Each entry equals oracle_loglike's for that data set. */
+ * Each entry equals oracle_loglike's for that data set.  If spec is not
+ * NULL, each walker's unit-distance GR spectra (as oracle_rfft of its
+ * waveform, [B][2][N/2+1][2]) are copied there too (zeros for an invalid
+ * walker). */
 int oracle_loglike_sets(const double *params, int64_t B, const double *data, int32_t nset,
-                        const double *psd, const oracle_cfg *c, double *lnL)
+                        const double *psd, const oracle_cfg *c, double *lnL, double *spec)
 {
     if (!cfg_ok(c) || nset < 1) return -1;
     int64_t N = c->N, H = N / 2 + 1;
@@ -1093,6 +1096,10 @@ int oracle_loglike_sets(const double *params, int64_t B, const double *data, int
             for (int32_t q = 0; q < nset; ++q)
                 lnL[w * nset + q] = bad ? -INFINITY
                                         : spectrum_loglike(s, sX + 2 * N, data + q * 4 * H, psd, c);
+            if (spec) {
+                if (bad) memset(spec + w * 4 * H, 0, (size_t)(4 * H) * sizeof(double));
+                else memcpy(spec + w * 4 * H, sX + 2 * N, (size_t)(4 * H) * sizeof(double));
+            }
         }
         free(sx);
         free(sX);

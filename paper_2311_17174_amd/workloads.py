@@ -137,19 +137,17 @@ SERVING_T_OBS_YR = (0.5, 1.0, 2.0)          # 2^21, 2^22, 2^23 samples at 10 s
 def serving_chains(n_chains: int = 8):
     """Injection row of each chain c, drawn from PCG64(100 + c): e0 ~ U[0.05,
     0.5], a ~ U[0, 0.9], log10 M ~ U[log10 3e5, log10 3e6], mu = 10, the other
-    entries as config 1 (GR).  nu0 is the fraction 0.5 of the LSO frequency
-    nu_LSO(e0) = ((1 - e0^2)/(6 + 2 e0))^{3/2} / (2 pi G M / c^3) -- an input
-    choice for this workload (the same expression the validity check uses),
-    not part of the likelihood."""
-    tsun = 4.925490947641267e-6
+    entries as config 1 (GR).  The serving workloads put the orbital state of a
+    row at the last stable orbit (``ic = 1``, the paper's convention: e0 is the
+    eccentricity at the LSO, the orbit is integrated backward over the window
+    and nu0 is not used), so every drawn mass has a valid history."""
     rows = []
     for c in range(n_chains):
         r = np.random.Generator(np.random.PCG64(100 + c))
         e0 = r.uniform(0.05, 0.5)
         a = r.uniform(0.0, 0.9)
         M = 10.0 ** r.uniform(np.log10(3e5), np.log10(3e6))
-        nu_lso = ((1 - e0 * e0) / (6 + 2 * e0)) ** 1.5 / (2 * np.pi * M * tsun)
-        rows.append(injection(M=M, mu=10.0, a=a, e0=e0, nu0=0.5 * nu_lso))
+        rows.append(injection(M=M, mu=10.0, a=a, e0=e0))
     return np.array(rows)
 
 
@@ -157,7 +155,7 @@ def serving_workload(chain_inj: np.ndarray, t_index: int, precision: str = "mixe
     T = SERVING_T_OBS_YR[t_index] * YEAR
     N = 1 << (21 + t_index)
     return Workload(f"serve_T{SERVING_T_OBS_YR[t_index]}yr", 0, T, 10.0, N, 30, 10, precision,
-                    chain_inj)
+                    chain_inj, ic=1)
 
 
 def serving_requests(n: int, n_chains: int = 8, seed: int = 4, w_min: int = 16,

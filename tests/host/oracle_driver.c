@@ -105,8 +105,12 @@ static void run(int ic_lso, int ode)
     memcpy(sets, d, (size_t)2 * H * 2 * sizeof(double));
     memcpy(sets + 2 * H * 2, d0, (size_t)2 * H * 2 * sizeof(double));
     double lnL2[B * 2];
-    CHECK(oracle_loglike_sets(P, B, sets, 2, S, &c, lnL2) == 0);
+    CHECK(oracle_loglike_sets(P, B, sets, 2, S, &c, lnL2, NULL) == 0);
     for (int w = 0; w < B; ++w) CHECK(lnL2[w * 2] == lnL[w] || (isnan(lnL[w]) && isnan(lnL2[w * 2])));
+    double *spec = malloc((size_t)B * 2 * H * 2 * sizeof(double));
+    CHECK(oracle_loglike_sets(P, B, sets, 2, S, &c, lnL2, spec) == 0);
+    for (int w = 0; w < B; ++w) CHECK(lnL2[w * 2] == lnL[w] || (isnan(lnL[w]) && isnan(lnL2[w * 2])));
+    free(spec);
 
     double coef[B * 2 * 3];
     for (int i = 0; i < B * 2 * 3; ++i) coef[i] = 1e-3 * normal();

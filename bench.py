@@ -360,7 +360,7 @@ def run_serving(E, W, n_burst: int, n_requests: int, arena_gib: float, n_streams
     def open_loop(rs, rate, keep=()):
         """Poisson arrivals at `rate` per s; returns latencies, span, outputs kept"""
         arrivals = np.cumsum([r[0] for r in rs]) / rate
-        pre = [params_of(r) for r in rs]
+        pre = [params_of(r) for r in rs]   # walker rows drawn before the clock starts
         q = queue.Queue()
         lat = np.zeros(len(rs))
         kept = {}
@@ -380,6 +380,9 @@ def run_serving(E, W, n_burst: int, n_requests: int, arena_gib: float, n_streams
             if dtw > 0:
                 time.sleep(dtw)
             q.put((i, srv.submit(ids[(r[1], r[2])][0], pre[i])))
+            if (i + 1) % 1000 == 0:
+                print(f"[bench] serving: {i + 1}/{len(rs)} requests submitted at "
+                      f"{rate:.1f}/s", file=sys.stderr, flush=True)
         th.join()
         return lat, time.perf_counter() - start, kept, pre
 
@@ -425,6 +428,119 @@ def run_serving(E, W, n_burst: int, n_requests: int, arena_gib: float, n_streams
     }
 
 
+def host_cpu() -> dict:
+    """CPU model and core counts of the host that runs the oracle"""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "os_cpu_count": os.cpu_count()}
+
+
+def golden_values(name: str):
+    """per-walker oracle values written by tests/golden/make_golden.py (the
+    oracle alone), or None"""
+    path = os.path.join(ROOT, "tests", "golden", f"{name}_lnl.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def parity_report(got, ref, mm):
+    """|dlnL|, relative dlnL and |dlnL| / <m|m> (the signal scale) per walker"""
+    d = np.abs(np.asarray(got) - np.asarray(ref))
+    return {"walkers": int(d.size), "max_abs_dlnL": float(d.max()),
+            "median_abs_dlnL": float(np.median(d)),
+            "max_rel_dlnL": float(np.max(d / np.abs(ref))),
+            "max_abs_dlnL_over_mm": float(np.max(d / mm)),
+            "median_mm": float(np.median(mm))}
+
+
+def run_oracle_leg(E, W, w64, wmx, P, w1, n_cpu: int):
+    """The CPU oracle beside the GPU: the oracle's own data set of the
+    headline workload (checked against the golden values' fingerprint), every
+    walker of the FP64 and mixed GPU paths on it against the oracle's golden
+    per-walker lnL, the oracle timed on a bounded sample of walkers (whose
+    spectra also give the waveform mismatch of both GPU paths), and config 1
+    (32 walkers, 2^18 samples) checked walker by walker live."""
+    import hashlib
+    import torch
+    import oracle as O
+    out = {}
+    nthr = O.num_threads()
+    ocfg = O.OracleConfig(w64.T_obs, w64.dt, w64.N, w64.n_harm, w64.coarse_log2)
+    S = O.psd_bc04(W.frequencies(w64.N, w64.dt))
+    t0 = time.perf_counter()
+    hinj = O.spectrum(w64.inj[None], ocfg)[0]
+    d = O.make_data(hinj, w64.inj, S, W.gaussian_draws(w64.N, w64.noise_seed), w64.N, w64.dt)
+    print(f"[bench] oracle data set in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    dd = torch.view_as_real(torch.from_numpy(d)).contiguous().cuda()
+    ss = torch.from_numpy(S).cuda()
+    Pd = torch.from_numpy(P).cuda()
+    gpu = {k: E.loglike_batch(Pd, dd, ss, E.Config.from_workload(w)).cpu().numpy()
+           for k, w in (("fp64", w64), ("mixed", wmx))}
+    g = golden_values(w64.name)
+    fp = hashlib.sha256(np.ascontiguousarray(d).tobytes()).hexdigest()
+    if g is not None and g["data_sha256"] == fp and len(g["idx"]) == w64.B:
+        ref, mm = np.asarray(g["lnl_noisy"]), np.asarray(g["mm"])
+        out["every_walker"] = {k: parity_report(v, ref, mm) for k, v in gpu.items()}
+        out["every_walker"]["source"] = ("tests/golden (oracle lnL of all walkers on the "
+                                         "oracle's data)")
+
+    # the oracle's own rate on a bounded sample (one walker per thread)
+    n = n_cpu or min(max(nthr, 1), 16)
+    print(f"[bench] cpu baseline: oracle on {n} walkers, {nthr} threads", file=sys.stderr,
+          flush=True)
+    t0 = time.perf_counter()
+    lnl_o, spec_o = O.loglike_sets(P[:n], [d], S, ocfg, return_spectra=True)
+    tc = time.perf_counter() - t0
+    lnl_o = lnl_o[:, 0]
+    # waveform mismatch against the oracle's propagated models of the sample
+    mo = np.stack([O.make_data(spec_o[i], P[i], S, None, w64.N, w64.dt) for i in range(n)])
+    mo = torch.from_numpy(mo).cuda()
+    df = 1.0 / (w64.N * w64.dt)
+    mism = {}
+    for k, w in (("fp64", w64), ("mixed", wmx)):
+        mg = E.model_batch(torch.from_numpy(P[:n]).cuda(), E.Config.from_workload(w))
+        m = noise_weighted_mismatch(mg, mo, ss, df)
+        mism[k] = {"walkers": n, "mismatch_max": float(np.max(np.abs(m))),
+                   "mismatch_median": float(np.median(np.abs(m)))}
+        del mg
+    del mo
+    torch.cuda.empty_cache()
+    out["mismatch_vs_oracle"] = mism
+    out["sample_rel_dlnL"] = {k: float(np.max(np.abs(v[:n] - lnl_o) / np.abs(lnl_o)))
+                              for k, v in gpu.items()}
+    out["cpu"] = {"value": n / tc, "unit": "lnL evals/s", "cores": nthr, "kind": "oracle",
+                  "sample": f"{n} of {w64.B} walkers of {w64.name} (FP64 C oracle, OpenMP one "
+                            f"walker per thread), the oracle's data; {tc:.1f} s",
+                  **host_cpu()}
+
+    # config 1: every walker against the oracle, computed here
+    c1 = O.OracleConfig(w1.T_obs, w1.dt, w1.N, w1.n_harm, w1.coarse_log2)
+    S1 = O.psd_bc04(W.frequencies(w1.N, w1.dt))
+    h1 = O.spectrum(w1.inj[None], c1)[0]
+    d1 = O.make_data(h1, w1.inj, S1, W.gaussian_draws(w1.N, w1.noise_seed), w1.N, w1.dt)
+    P1 = W.walkers(w1)
+    r1 = O.loglike_sets(P1, [d1, np.zeros_like(d1)], S1, c1)
+    g1 = E.loglike_batch(torch.from_numpy(P1).cuda(),
+                         torch.view_as_real(torch.from_numpy(d1)).contiguous().cuda(),
+                         torch.from_numpy(S1).cuda(), E.Config.from_workload(w1)).cpu().numpy()
+    out["config1_every_walker"] = parity_report(g1, r1[:, 0], -2.0 * r1[:, 1])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -435,8 +551,8 @@ def main():
     ap.add_argument("--cpu-walkers", type=int, default=0,
                     help="oracle sample size (default: one walker per host thread, <= 16)")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=300,
-                    help="timed serving requests (the full serving workload is 10000)")
+    ap.add_argument("--serve-requests", type=int, default=10000,
+                    help="timed serving requests (the serving workload: 10000)")
     ap.add_argument("--serve-burst", type=int, default=60)
     ap.add_argument("--serve-arena-gib", type=float, default=160.0)
     ap.add_argument("--serve-sweep", type=int, default=100,
@@ -495,6 +611,25 @@ def main():
     print(f"[bench] fp64: {evals64:.1f} evals/s, {1e3 * dt64 / args.steps:.2f} ms/step",
           file=sys.stderr, flush=True)
 
+    # config 1: 32 walkers, 30 days, 2^18 samples, 16 harmonics, FP64
+    w1 = W.config1()
+    c1 = E.Config.from_workload(w1)
+    psd1 = E.noise_psd(w1.N, w1.dt)
+    m1 = E.model_batch(torch.from_numpy(w1.inj[None]).cuda(), c1)[0]
+    g1 = torch.from_numpy(W.gaussian_draws(w1.N, w1.noise_seed)).cuda()
+    sig1 = torch.sqrt(psd1 * (w1.N * w1.dt / 4.0))
+    sig1[0] = 0.0
+    sig1[-1] = 0.0
+    data1 = (torch.view_as_real(m1).clone() + sig1[None, :, None] * g1).contiguous()
+    dt1, st1, lat1, _ = run_path(E, W, w1, W.walkers(w1), data1, psd1, args.steps, args.warmup)
+    config1 = {"workload": w1.name, "value": args.steps * w1.B / dt1, "unit": "lnL evals/s",
+               "ms_per_step": 1e3 * dt1 / args.steps, "dtype": "f64",
+               "batch_latency_ms": {"p50": float(np.percentile(lat1, 50)),
+                                    "p99": float(np.percentile(lat1, 99))}}
+    del m1, g1, sig1, data1
+    print(f"[bench] config 1: {config1['value']:.1f} evals/s, {config1['ms_per_step']:.3f} "
+          "ms/step", file=sys.stderr, flush=True)
+
     mixed = None
     if not args.no_mixed:
         dtm, stm, latm, lnlm = run_path(E, W, wmx, P, data, psd, args.steps, args.warmup)
@@ -509,6 +644,17 @@ def main():
                              "max_abs_dlnL": float(np.abs(lnlm - lnl64).max())},
             "stages_ms_per_step": {k: v[0] / args.steps for k, v in stm.items()},
         }
+        # the HBM-bound stages of the mixed path against the 8 TB/s peak
+        mst = {}
+        for name, (ms, launches) in stm.items():
+            kind, amount = stage_work(name, wmx.B, wmx, 8, wmx.B * wmx.n_valid)
+            if kind != "byte":
+                continue
+            per = ms / launches
+            gbs = amount / (launches / args.steps) / (per * 1e-3) / 1e9
+            mst[name] = {"ms_per_launch": per, "achieved_gbs": gbs,
+                         "frac_of_peak": gbs / HBM_PEAK_GBS}
+        mixed["stages"] = mst
         # waveform mismatch of the mixed path against the FP64 path (whose
         # parity with the oracle is tested) for every walker, 64 at a time
         cmx = E.Config.from_workload(wmx)
@@ -628,25 +774,30 @@ def main():
     roof["plain_copy_gbs"] = copy
     for ent in stages_out.values():
         if "achieved_gbs" in ent:
+            ent["frac_of_peak"] = ent["achieved_gbs"] / HBM_PEAK_GBS
             ent["frac_of_plain_copy"] = ent["achieved_gbs"] / copy
+        if "achieved_tflops" in ent:
+            ent["frac_of_peak"] = ent["achieved_tflops"] / FP64_VECTOR_TFLOPS
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle as O
-        nthr = O.num_threads()
-        n = args.cpu_walkers or min(max(nthr, 1), 16)
-        ocfg = O.OracleConfig(w64.T_obs, w64.dt, w64.N, w64.n_harm, w64.coarse_log2)
-        d_host = torch.view_as_complex(data.cpu()).numpy()
-        s_host = psd.cpu().numpy()
-        print(f"[bench] cpu baseline: oracle on {n} walkers, {nthr} threads", file=sys.stderr,
-              flush=True)
-        t0 = time.perf_counter()
-        ref = O.loglike(P[:n], d_host, s_host, ocfg)
-        tc = time.perf_counter() - t0
-        cpu = {"value": n / tc, "unit": "lnL evals/s", "cores": nthr, "kind": "oracle",
-               "sample": f"{n} of {w64.B} walkers of {w64.name} (FP64 C oracle, OpenMP one "
-                         f"walker per thread), same data; {tc:.1f} s",
-               "parity_max_rel_dlnL": float(np.max(np.abs(lnl64[:n] - ref) / np.abs(ref)))}
+        leg = run_oracle_leg(E, W, w64, wmx, P, w1, args.cpu_walkers)
+        cpu = leg["cpu"]
+        cpu["parity_sample_max_rel_dlnL"] = leg["sample_rel_dlnL"]["fp64"]
+        config1["vs_oracle"] = leg["config1_every_walker"]
+        ev = leg.get("every_walker")
+        roof_vs = {"fp64": {**(ev["fp64"] if ev else {}),
+                            **leg["mismatch_vs_oracle"]["fp64"]}}
+        if mixed is not None:
+            mixed["vs_oracle"] = {**(ev["mixed"] if ev else {}),
+                                  **leg["mismatch_vs_oracle"]["mixed"]}
+        vs_oracle = roof_vs["fp64"]
+        if ev:
+            vs_oracle["source"] = ev["source"]
+            if mixed is not None:
+                mixed["vs_oracle"]["source"] = ev["source"]
+    else:
+        vs_oracle = None
 
     rec = {
         "metric": "AK lnL evals/sec at 1 yr/2^22 samples, mixed vs FP64; p50/p99 request latency",
@@ -662,6 +813,8 @@ def main():
                              "p99": float(np.percentile(lat64, 99))},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "vs_oracle": vs_oracle,
+        "config1": config1,
         "mixed": mixed,
         "serving": serving,
         "stress": config5,

@@ -135,3 +135,21 @@ def test_workspace_sizes_are_consistent(E):
     assert E.workspace_bytes(lso, 8) == E.workspace_bytes(c, 8)
     bad = E.Config(T_obs=2.5 * 86400, dt=10.0, N=1 << 15, n_harm=8, ic=2)
     assert E.lib.emri_workspace_bytes(ctypes.byref(bad.c()), 4) == 0
+
+
+def test_documented_array_layouts():
+    """The header documents the time-domain waveform as [B][N][2] (channels
+    interleaved per sample: the complex sample h_I + i h_II the FFT reads),
+    the spectra as [B][2][N/2+1] complex and row entry 16 as alpha_T; the
+    binding allocates and checks the same shapes (no GPU needed)."""
+    with open(HEADER) as f:
+        h = f.read()
+    assert "ht      [B][N][2] real, channel-interleaved (I, II) per sample" in h
+    assert "hf   [B][2][N/2+1] complex (re, im interleaved)" in h
+    assert "16 alpha_T" in h
+    import inspect
+    from paper_2311_17174_amd import emri as E
+    src = inspect.getsource(E.waveform_batch)
+    assert "(B, cfg.N, 2)" in src
+    src = inspect.getsource(E.fft_batch)
+    assert "(B, 2, H, 2)" in src

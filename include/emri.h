@@ -70,6 +70,18 @@ typedef enum {
     EMRI_EUNSUPPORTED = -4   /* valid request outside the supported range  */
 } emri_status;
 
+/* Accuracy.  EMRI_FP64 follows the FP64 reference computation (the same
+ * orbit integrator, node interpolation and transform definition) to
+ * rounding, except that the harmonic amplitudes between orbit nodes come
+ * from cubic tables per coarse interval, whose error falls as the fourth
+ * power of the coarse step.  Where the orbit evolves over many coarse steps
+ * (every configuration of the tests: 30 days to 2 years, 16-40 harmonics)
+ * lnL agrees to 1e-10 relative and its signal part to 1e-10 <m|m>; within a
+ * few coarse steps of a plunge the table error reaches ~1e-7 of max|h| at
+ * coarse_log2 = 10, and each unit less of coarse_log2 divides it by 16.
+ * EMRI_MIXED: lnL to 1e-4 relative and the signal part to 1e-5 <m|m>; its
+ * synthesis leaves out harmonics and cubic amplitude terms below 2^-30 of
+ * the interval's largest harmonic, under FP32 rounding. */
 typedef enum {
     EMRI_FP64 = 0,  /* every stage in FP64                                   */
     EMRI_MIXED = 1  /* FP64 orbit, phases and final reduction; FP32 harmonic

@@ -200,6 +200,11 @@ emri_status make_plan(const emri_cfg* cfg, int64_t B, const Tuning& tn, Plan* p,
     q.off_co = o; o += align256((size_t)B * q.K * 16 * 8);
     q.off_az = o; o += align256((size_t)q.K * 16);
     q.off_ch = o; o += align256((size_t)B * q.K * q.nh * 12 * q.hsz);
+    // mixed path: per (walker, interval, harmonic) the bound of the
+    // harmonic's amplitudes and of their cubic coefficients (float2), and
+    // per (walker, interval) the harmonics to sum and the cubic flag (int2)
+    q.off_hb = o; o += (q.prec == EMRI_MIXED) ? align256((size_t)B * q.K * q.nh * 8) : 0;
+    q.off_hx = o; o += (q.prec == EMRI_MIXED) ? align256((size_t)B * q.K * 8) : 0;
     q.off_z = o; o += align256((size_t)B * q.N * q.esz);
     q.off_part = o; o += align256((size_t)B * q.R2 * 8);
     q.total = o;

@@ -17,7 +17,9 @@
 //   Phi' = Phi + 2 pi nu R sin(theta_S) cos(phibar - phi_S)  Doppler phase
 //   L = cos(lambda) S + sin(lambda) (cos(alpha) e1 + sin(alpha) e2)
 //   S_a = sum_n A n P_n cos(n Phi'), S_b = sum_n A n Q_n sin(n Phi'),
-//   S_c = sum_n 2 A J_n cos(n Phi')   (harmonics by complex rotation)
+//   S_c = sum_n 2 A J_n cos(n Phi')   (cos, sin of n Phi' by the three-term
+//                                       recurrence; in FP32 the terms below
+//                                       its rounding are left out)
 //   h+ = (1 + c^2)(S_a cos 2g - S_b sin 2g) + (1 - c^2) S_c
 //   hx = -2 c (S_b cos 2g + S_a sin 2g),  c = L.N, g = gamma~ + beta
 //   h_I/II = sqrt(3)/2 (F+ h+ + Fx hx), channel II at phi_d - pi/4
@@ -111,6 +113,7 @@ k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
                                                double dt, const double* __restrict__ wc,
                                                const double* __restrict__ co,
                                                const HT* __restrict__ ch,
+                                               const int2* __restrict__ hx,
                                                const double2* __restrict__ az,
                                                typename V2<R>::T* __restrict__ out)
 {
@@ -183,27 +186,67 @@ k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
         tc[s] = R(2) * c1[s];
     }
     const HT* hq = ch + (w * K + k) * (int64_t)nh * 12;
+    int nsum = nh;           // harmonics summed
+    bool cubic = true;       // amplitude polynomials of degree 3 (else 2)
+    if constexpr (sizeof(R) == 4) {
+        // FP32: the harmonics and cubic terms that cannot change the sum at
+        // its precision are left out (k_harm_extent: the number of
+        // harmonics to sum and whether the cubic terms matter, per walker
+        // and interval)
+        const int2 x = hx[w * K + k];
+        nsum = x.x;
+        cubic = x.y != 0;
+    }
+    if (cubic) {
 #pragma unroll 2
-    for (int n = 0; n < nh; ++n) {
-        const HT* t = hq + 12 * n;
-        const R a0 = (R)t[0], a1 = (R)t[1], a2 = (R)t[2], a3 = (R)t[3];
-        const R b0 = (R)t[4], b1 = (R)t[5], b2 = (R)t[6], b3 = (R)t[7];
-        const R e0 = (R)t[8], e1 = (R)t[9], e2 = (R)t[10], e3 = (R)t[11];
+        for (int n = 0; n < nsum; ++n) {
+            const HT* t = hq + 12 * n;
+            const R a0 = (R)t[0], a1 = (R)t[1], a2 = (R)t[2], a3 = (R)t[3];
+            const R b0 = (R)t[4], b1 = (R)t[5], b2 = (R)t[6], b3 = (R)t[7];
+            const R e0 = (R)t[8], e1 = (R)t[9], e2 = (R)t[10], e3 = (R)t[11];
 #pragma unroll
-        for (int s = 0; s < SPT; ++s) {
-            const R x = u[s];
-            const R ua = ((a3 * x + a2) * x + a1) * x + a0;
-            const R ub = ((b3 * x + b2) * x + b1) * x + b0;
-            const R uc = ((e3 * x + e2) * x + e1) * x + e0;
-            Sa[s] += ua * cn[s];
-            Sb[s] += ub * sn[s];
-            Sc[s] += uc * cn[s];
-            const R cc = tc[s] * cn[s] - cq[s];
-            const R ss = tc[s] * sn[s] - sq[s];
-            cq[s] = cn[s];
-            sq[s] = sn[s];
-            cn[s] = cc;
-            sn[s] = ss;
+            for (int s = 0; s < SPT; ++s) {
+                const R x = u[s];
+                const R ua = ((a3 * x + a2) * x + a1) * x + a0;
+                const R ub = ((b3 * x + b2) * x + b1) * x + b0;
+                const R uc = ((e3 * x + e2) * x + e1) * x + e0;
+                Sa[s] += ua * cn[s];
+                Sb[s] += ub * sn[s];
+                Sc[s] += uc * cn[s];
+                const R cc = tc[s] * cn[s] - cq[s];
+                const R ss = tc[s] * sn[s] - sq[s];
+                cq[s] = cn[s];
+                sq[s] = sn[s];
+                cn[s] = cc;
+                sn[s] = ss;
+            }
+        }
+    } else {
+        // the same with the cubic terms left out (FP32 only); the table row
+        // is read in the same 16-byte pieces as above
+#pragma unroll 2
+        for (int n = 0; n < nsum; ++n) {
+            const float4* t = (const float4*)(hq + 12 * n);
+            const float4 ta = t[0], tb = t[1], te = t[2];
+            const R a0 = (R)ta.x, a1 = (R)ta.y, a2 = (R)ta.z;
+            const R b0 = (R)tb.x, b1 = (R)tb.y, b2 = (R)tb.z;
+            const R e0 = (R)te.x, e1 = (R)te.y, e2 = (R)te.z;
+#pragma unroll
+            for (int s = 0; s < SPT; ++s) {
+                const R x = u[s];
+                const R ua = (a2 * x + a1) * x + a0;
+                const R ub = (b2 * x + b1) * x + b0;
+                const R uc = (e2 * x + e1) * x + e0;
+                Sa[s] += ua * cn[s];
+                Sb[s] += ub * sn[s];
+                Sc[s] += uc * cn[s];
+                const R cc = tc[s] * cn[s] - cq[s];
+                const R ss = tc[s] * sn[s] - sq[s];
+                cq[s] = cn[s];
+                sq[s] = sn[s];
+                cn[s] = cc;
+                sn[s] = ss;
+            }
         }
     }
 
@@ -321,11 +364,12 @@ static hipError_t synth_dispatch(const Plan& p, int64_t B, const char* base, voi
     const double* wc = (const double*)(base + p.off_wc);
     const double* co = (const double*)(base + p.off_co);
     const HT* ch = (const HT*)(base + p.off_ch);
+    const int2* hx = (p.prec == EMRI_MIXED) ? (const int2*)(base + p.off_hx) : nullptr;
     const double2* az = (const double2*)(base + p.off_az);
     R2* o = (R2*)out;
 #define EMRI_SYNTH(SPT)                                                                        \
     hipLaunchKernelGGL((k_synth<R, HT, SPT>), grid, dim3(256), 0, s, p.K, p.Nv, p.N, p.nh, k0, \
-                       seg, zfill, p.dt, wc, co, ch, az, o)
+                       seg, zfill, p.dt, wc, co, ch, hx, az, o)
     switch (p.cl) {
     case 8: EMRI_SYNTH(1); break;
     case 9: EMRI_SYNTH(2); break;

@@ -804,7 +804,8 @@ __global__ void __launch_bounds__(256) k_tables(int64_t K, int nh, double h, int
                                                 int seg, const double* __restrict__ wc,
                                                 const double* __restrict__ orb,
                                                 const double* __restrict__ nv,
-                                                double* __restrict__ co, HT* __restrict__ ch)
+                                                double* __restrict__ co, HT* __restrict__ ch,
+                                                float2* __restrict__ hb)
 {
     const int64_t w = blockIdx.y;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -828,11 +829,56 @@ __global__ void __launch_bounds__(256) k_tables(int64_t K, int nh, double h, int
     const double* v0 = nv + ((w * (K + 1) + k) * nh + (n - 1)) * 6;
     const double* v1 = v0 + (int64_t)nh * 6;            // node k + 1, same n
     HT* q = ch + ((w * K + k) * nh + (n - 1)) * 12;
+    float bnd = 0.f, c3 = 0.f;
     for (int i = 0; i < 3; ++i) {
         double cc[4];
         hermite_coeffs(v0[2 * i], v0[2 * i + 1], v1[2 * i], v1[2 * i + 1], h, cc);
-        for (int j = 0; j < 4; ++j) q[4 * i + j] = (HT)cc[j];
+        float sa = 0.f;
+        for (int j = 0; j < 4; ++j) {
+            q[4 * i + j] = (HT)cc[j];
+            sa += fabsf((float)(HT)cc[j]);
+        }
+        bnd = fmaxf(bnd, sa);
+        c3 = fmaxf(c3, fabsf((float)(HT)cc[3]));
     }
+    // the amplitude bound over u in [0, 1] and the largest cubic coefficient
+    // of this harmonic, for the synthesis to leave out what cannot change
+    // an FP32 sum
+    if (hb) hb[(w * K + k) * nh + (n - 1)] = float2{bnd, c3};
+}
+
+// FP32 synthesis: per (walker, interval) of the segment, the number of
+// harmonics to sum and whether the cubic amplitude terms matter.  With M the
+// largest amplitude bound of the interval's harmonics (k_tables: the sum of
+// a cubic's absolute coefficients, which bounds it over u in [0, 1]), the
+// harmonics past the last one whose bound reaches kTiny M are left out, and
+// the cubic terms are dropped when every harmonic's cubic coefficients are
+// below kTiny M.  kTiny = 2^-30 is under FP32 rounding (2^-24): past their
+// peak the Peters-Mathews amplitudes decay monotonically, so what is left
+// out stays within a few kTiny M.
+__global__ void __launch_bounds__(256) k_harm_extent(int64_t K, int nh, int64_t k0, int64_t k1,
+                                                     int seg, const double* __restrict__ wc,
+                                                     const float2* __restrict__ hb,
+                                                     int2* __restrict__ hx)
+{
+    constexpr float kTiny = 9.313225746154785e-10f;
+    const int64_t w = blockIdx.y;
+    const int64_t k = k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= k1) return;
+    const double* c = wc + w * WC;
+    if (c[WC_VALID] == 0.0 || k >= (int64_t)c[WC_KSEG + seg]) return;
+    const float2* b = hb + (w * K + k) * nh;
+    float M = 0.f, c3 = 0.f;
+    for (int n = 0; n < nh; ++n) {
+        M = fmaxf(M, b[n].x);
+        c3 = fmaxf(c3, b[n].y);
+    }
+    int nsum = 0;
+    for (int n = 0; n < nh; ++n)
+        if (b[n].x >= kTiny * M) nsum = n + 1;
+    // M = 0 (no signal) or a non-finite bound: sum everything
+    if (!(M > 0.f) || !(M <= 3.4e38f)) nsum = nh;
+    hx[w * K + k] = int2{nsum, (c3 < kTiny * M) ? 0 : 1};
 }
 
 // ---------------------------------------------------------------------------
@@ -942,14 +988,20 @@ hipError_t launch_tables(const Plan& p, int64_t B, void* ws, int64_t k0, int64_t
     const int64_t n = (k1 - k0) * p.nh;
     dim3 grid((unsigned)((n + 255) / 256), (unsigned)B);
     if (n > 0) {
-        if (p.prec == EMRI_FP64)
+        if (p.prec == EMRI_FP64) {
             hipLaunchKernelGGL(k_tables<double>, grid, dim3(256), 0, s, p.K, p.nh, h, k0, k1, seg,
                                wc, orb, nv, (double*)(base + p.off_co),
-                               (double*)(base + p.off_ch));
-        else
+                               (double*)(base + p.off_ch), (float2*)nullptr);
+        } else {
             hipLaunchKernelGGL(k_tables<float>, grid, dim3(256), 0, s, p.K, p.nh, h, k0, k1, seg,
                                wc, orb, nv, (double*)(base + p.off_co),
-                               (float*)(base + p.off_ch));
+                               (float*)(base + p.off_ch), (float2*)(base + p.off_hb));
+            if (hipPeekAtLastError() == hipSuccess)
+                hipLaunchKernelGGL(k_harm_extent,
+                                   dim3((unsigned)((k1 - k0 + 255) / 256), (unsigned)B), dim3(256),
+                                   0, s, p.K, p.nh, k0, k1, seg, wc,
+                                   (const float2*)(base + p.off_hb), (int2*)(base + p.off_hx));
+        }
     }
     trace_mark(ST_TABLES, s, false);
     return hipGetLastError();

@@ -2,6 +2,9 @@
 values (computed only by the CPU oracle), and the HIP binding."""
 from __future__ import annotations
 
+import hashlib
+import json
+import os
 import sys
 
 import numpy as np
@@ -10,6 +13,7 @@ import oracle as O
 from paper_2311_17174_amd import workloads as W
 
 EPS64 = 2.0 ** -52
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def say(*a):
@@ -24,25 +28,43 @@ def ocfg(w) -> O.OracleConfig:
 
 
 _DATA_CACHE: dict = {}
+_SPEC_CACHE: dict = {}
+
+
+def _key(w):
+    return (w.T_obs, w.dt, w.N, w.n_harm, w.coarse_log2, w.inj.tobytes(), w.ic, w.ode,
+            w.ode_rtol, w.ode_atol)
+
+
+def oracle_injection_spectrum(w):
+    """the oracle's unit-distance GR spectrum [2][N/2+1] of w's injection"""
+    k = _key(w)
+    if k not in _SPEC_CACHE:
+        _SPEC_CACHE[k] = O.spectrum(w.inj[None], ocfg(w))[0]
+    return _SPEC_CACHE[k]
 
 
 def oracle_dataset(w, noise: bool = True):
-    """(data[2][N/2+1] complex, psd[N/2+1]) for workload w, from the oracle."""
-    key = (w.T_obs, w.dt, w.N, w.n_harm, w.coarse_log2, w.noise_seed, w.inj.tobytes(), noise,
-           w.ic, w.ode, w.ode_rtol, w.ode_atol)
+    """(data[2][N/2+1] complex, psd[N/2+1]) for workload w, from the oracle:
+    the propagated injection, plus coloured noise from w.noise_seed."""
+    key = _key(w) + (w.noise_seed, noise)
     if key not in _DATA_CACHE:
-        _DATA_CACHE[key] = _oracle_dataset(w, noise)
+        f = W.frequencies(w.N, w.dt)
+        S = O.psd_bc04(f)
+        g = W.gaussian_draws(w.N, w.noise_seed) if noise else None
+        d = O.make_data(oracle_injection_spectrum(w), w.inj, S, g, w.N, w.dt)
+        _DATA_CACHE[key] = (d, S)
     return _DATA_CACHE[key]
 
 
-def _oracle_dataset(w, noise):
-    cfg = ocfg(w)
-    f = W.frequencies(w.N, w.dt)
-    S = O.psd_bc04(f)
-    hinj = O.spectrum(w.inj[None], cfg)[0]
-    g = W.gaussian_draws(w.N, w.noise_seed) if noise else None
-    d = O.make_data(hinj, w.inj, S, g, w.N, w.dt)
-    return d, S
+def golden(name: str) -> dict:
+    """per-walker oracle values written by tests/golden/make_golden.py"""
+    with open(os.path.join(GOLDEN, f"{name}_lnl.json")) as f:
+        return json.load(f)
+
+
+def data_fingerprint(d) -> str:
+    return hashlib.sha256(np.ascontiguousarray(d, dtype=np.complex128).tobytes()).hexdigest()
 
 
 def to_device_data(d, S):

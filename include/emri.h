@@ -60,7 +60,7 @@ extern "C" {
 #endif
 
 #define EMRI_NPAR 17
-#define EMRI_ABI_VERSION 6
+#define EMRI_ABI_VERSION 7
 
 typedef enum {
     EMRI_OK = 0,
@@ -233,6 +233,24 @@ emri_status emri_dataset_init(const double* data, const double* psd, const emri_
 emri_status emri_loglike_dataset(const double* params, int64_t B, const void* ds,
                                  const emri_cfg* cfg, double* lnL, void* ws, size_t ws_bytes,
                                  hipStream_t stream);
+
+/* As emri_loglike_dataset, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  No workspace argument: the call works in a device array of
+ * EMRI_NOALLOC_SCRATCH_BYTES (512 MiB) inside the library, which every GPU
+ * the library runs on holds until the process ends.  The call itself
+ * allocates nothing (no device memory, streams or events; the orbit runs in
+ * one segment unless an earlier ordinary call on `stream` set up its
+ * pipeline).  Walkers are processed in as many chunks as the array holds;
+ * a cfg whose emri_workspace_bytes(cfg, 1) exceeds the array gets
+ * EMRI_EWORKSPACE and nothing is launched (every N <= 2^23, and 2^24 at
+ * up to about 40 harmonics, fits).  Results are bitwise those of
+ * emri_loglike_dataset.  All calls on one GPU share its array and it keeps
+ * the last call's contents: calls that overlap on one GPU (concurrent
+ * streams or threads) race and must be serialised by the caller. */
+#define EMRI_NOALLOC_SCRATCH_BYTES ((size_t)512 << 20)
+emri_status emri_loglike_dataset_noalloc(const double* params, int64_t B, const void* ds,
+                                         const emri_cfg* cfg, double* lnL, hipStream_t stream);
 
 /* ---- frequency-dependent propagation --------------------------------------
  * The variant of Sec. 2 "Waveform propagation" in which alpha_M and alpha_T

@@ -243,11 +243,14 @@ struct Pipe {
 };
 static std::mutex g_pipe_mu;
 static std::map<std::pair<int, hipStream_t>, Pipe> g_pipes;
+// set on a thread for the duration of a call that must create nothing
+static thread_local bool g_pipe_no_create = false;
 
 // the auxiliary stream and events of caller stream s on the current device:
 // found, or created when s is not capturing; *out = nullptr (and EMRI_OK)
 // when s is capturing and has none, so that nothing is created inside a
-// capture (the call then runs its orbit in one segment on s alone)
+// capture (the call then runs its orbit in one segment on s alone), and
+// likewise inside a call that allocates nothing
 static emri_status get_pipe(hipStream_t s, Pipe** out)
 {
     *out = nullptr;
@@ -263,7 +266,7 @@ static emri_status get_pipe(hipStream_t s, Pipe** out)
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     e = hipStreamIsCapturing(s, &cs);
     if (e != hipSuccess) return fail_hip(e, "pipeline: hipStreamIsCapturing");
-    if (cs != hipStreamCaptureStatusNone) return EMRI_OK;
+    if (cs != hipStreamCaptureStatusNone || g_pipe_no_create) return EMRI_OK;
     Pipe q;
     e = hipStreamCreateWithFlags(&q.aux, hipStreamNonBlocking);
     for (int i = 0; i < kMaxSeg && e == hipSuccess; ++i)
@@ -553,6 +556,70 @@ emri_status emri_loglike_dataset(const double* params, int64_t B, const void* ds
     if (B == 0) return EMRI_OK;
     if (!params || !ds || !lnL || !ws) return fail(EMRI_EINVAL, "null pointer argument");
     return loglike_chunks(cfg, params, B, ds, lnL, ws, ws_bytes, stream);
+}
+
+}  // extern "C"
+
+// ---- likelihood without allocation ---------------------------------------------
+// For callers that cannot allocate device memory, a file-scope device array
+// stands in for the caller's workspace.  Each device holds its own copy for
+// the life of the process.  In host code the array's name is only a host
+// stand-in: its device address is taken with hipGetSymbolAddress, once per
+// device with that device current, and only that address is handed to
+// kernels.  No kernel of the likelihood path needs the workspace to start at
+// zero (every value is written before it is read), so nothing is cleared.
+namespace emri {
+static __device__ __align__(256) unsigned char scratch[EMRI_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_ptr;
+
+static emri_status scratch_address(void** out)
+{
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "scratch: hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return EMRI_OK;
+    }
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return fail_hip(e, "scratch: hipGetSymbolAddress");
+    g_scratch_ptr[dev] = ptr;
+    *out = ptr;
+    return EMRI_OK;
+}
+}  // namespace emri
+
+extern "C" {
+
+emri_status emri_loglike_dataset_noalloc(const double* params, int64_t B, const void* ds,
+                                         const emri_cfg* cfg, double* lnL, hipStream_t stream)
+{
+    Plan p;
+    const char* err;
+    emri_status st = make_plan(cfg, 1, tuning_now(), &p, &err);
+    if (st != EMRI_OK) return fail(st, err);
+    if (B < 0) return fail(EMRI_EINVAL, "B must be >= 0");
+    if (B == 0) return EMRI_OK;
+    if (!params || !ds || !lnL) return fail(EMRI_EINVAL, "null pointer argument");
+    if (p.total > (size_t)EMRI_NOALLOC_SCRATCH_BYTES)
+        return fail(EMRI_EWORKSPACE,
+                    "one walker's workspace (emri_workspace_bytes(cfg, 1)) exceeds "
+                    "EMRI_NOALLOC_SCRATCH_BYTES");
+    void* ws = nullptr;
+    if ((st = scratch_address(&ws))) return st;
+    // neither pipeline streams nor trace events are created inside this call
+    const bool pipe_prev = g_pipe_no_create, trace_prev = g_trace_suppress;
+    g_pipe_no_create = true;
+    g_trace_suppress = true;
+    st = loglike_chunks(cfg, params, B, ds, lnL, ws, EMRI_NOALLOC_SCRATCH_BYTES, stream);
+    g_pipe_no_create = pipe_prev;
+    g_trace_suppress = trace_prev;
+    return st;
 }
 
 emri_status emri_loglike_dataset_fmg(const double* params, int64_t B, const double* coef,

@@ -31,7 +31,8 @@ EXPORTED = ("emri_abi_version", "emri_last_error", "emri_workspace_bytes",
             "emri_model_batch", "emri_noise_psd", "emri_trace_enable", "emri_trace_read",
             "emri_trace_stage_name", "emri_sampler_workspace_bytes", "emri_ensemble_lnprob",
             "emri_stretch_step", "emri_loglike_dataset_fmg", "emri_tuning_set",
-            "emri_tuning_get")
+            "emri_tuning_get", "emri_loglike_dataset_noalloc")
+NOALLOC_SCRATCH_BYTES = 512 << 20     # EMRI_NOALLOC_SCRATCH_BYTES
 
 
 class EmriError(RuntimeError):
@@ -122,6 +123,7 @@ def _load():
         "emri_loglike_batch": ([vp, i64, vp, vp, d, d, cp, vp, vp, sz, vp], ctypes.c_int),
         "emri_dataset_init": ([vp, vp, cp, vp, sz, vp], ctypes.c_int),
         "emri_loglike_dataset": ([vp, i64, vp, cp, vp, vp, sz, vp], ctypes.c_int),
+        "emri_loglike_dataset_noalloc": ([vp, i64, vp, cp, vp, vp], ctypes.c_int),
         "emri_model_batch": ([vp, i64, cp, vp, vp, sz, vp], ctypes.c_int),
         "emri_noise_psd": ([ctypes.c_int, i64, d, vp, vp], ctypes.c_int),
         "emri_trace_enable": ([ctypes.c_int], ctypes.c_int),
@@ -308,6 +310,19 @@ def loglike_dataset(params: torch.Tensor, ds: torch.Tensor, cfg: Config,
     c = cfg.c()
     _check(lib.emri_loglike_dataset(pp, B, ds.data_ptr(), ctypes.byref(c), op, ws.data_ptr(),
                                     ws.numel(), _stream(stream)), "emri_loglike_dataset")
+    return out
+
+
+def loglike_dataset_noalloc(params: torch.Tensor, ds: torch.Tensor, cfg: Config,
+                            out: torch.Tensor, stream=None) -> torch.Tensor:
+    """emri_loglike_dataset_noalloc: the library's own device scratch array
+    instead of a workspace; `out` [B] fp64 is the caller's."""
+    B = params.shape[0]
+    pp = _dev(params, torch.float64, (B, NPAR), "params")
+    op = _dev(out, torch.float64, (B,), "out")
+    c = cfg.c()
+    _check(lib.emri_loglike_dataset_noalloc(pp, B, ds.data_ptr(), ctypes.byref(c), op,
+                                            _stream(stream)), "emri_loglike_dataset_noalloc")
     return out
 
 

@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol(E):
     missing = [n for n in declared_functions() if n not in exported]
     assert not missing, missing
     assert set(E.EXPORTED) == set(declared_functions())
-    assert E.lib.emri_abi_version() == 6
+    assert E.lib.emri_abi_version() == 7
 
 
 def test_struct_layout_matches_header(E):

@@ -514,7 +514,7 @@ def run_oracle_leg(E, W, w64, wmx, P, w1, n_cpu: int):
     for k, w in (("fp64", w64), ("mixed", wmx)):
         mg = E.model_batch(torch.from_numpy(P[:n]).cuda(), E.Config.from_workload(w))
         m = noise_weighted_mismatch(mg, mo, ss, df)
-        mism[k] = {"walkers": n, "mismatch_max": float(np.max(np.abs(m))),
+        mism[k] = {"mismatch_walkers": n, "mismatch_max": float(np.max(np.abs(m))),
                    "mismatch_median": float(np.median(np.abs(m)))}
         del mg
     del mo
@@ -548,6 +548,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-config1", action="store_true")
+    ap.add_argument("--no-mismatch", action="store_true",
+                    help="skip the mixed-vs-FP64 waveform mismatch (64-walker model batches)")
     ap.add_argument("--cpu-walkers", type=int, default=0,
                     help="oracle sample size (default: one walker per host thread, <= 16)")
     ap.add_argument("--no-serving", action="store_true")
@@ -613,22 +616,25 @@ def main():
 
     # config 1: 32 walkers, 30 days, 2^18 samples, 16 harmonics, FP64
     w1 = W.config1()
-    c1 = E.Config.from_workload(w1)
-    psd1 = E.noise_psd(w1.N, w1.dt)
-    m1 = E.model_batch(torch.from_numpy(w1.inj[None]).cuda(), c1)[0]
-    g1 = torch.from_numpy(W.gaussian_draws(w1.N, w1.noise_seed)).cuda()
-    sig1 = torch.sqrt(psd1 * (w1.N * w1.dt / 4.0))
-    sig1[0] = 0.0
-    sig1[-1] = 0.0
-    data1 = (torch.view_as_real(m1).clone() + sig1[None, :, None] * g1).contiguous()
-    dt1, st1, lat1, _ = run_path(E, W, w1, W.walkers(w1), data1, psd1, args.steps, args.warmup)
-    config1 = {"workload": w1.name, "value": args.steps * w1.B / dt1, "unit": "lnL evals/s",
-               "ms_per_step": 1e3 * dt1 / args.steps, "dtype": "f64",
-               "batch_latency_ms": {"p50": float(np.percentile(lat1, 50)),
-                                    "p99": float(np.percentile(lat1, 99))}}
-    del m1, g1, sig1, data1
-    print(f"[bench] config 1: {config1['value']:.1f} evals/s, {config1['ms_per_step']:.3f} "
-          "ms/step", file=sys.stderr, flush=True)
+    config1 = None
+    if not args.no_config1:
+        c1 = E.Config.from_workload(w1)
+        psd1 = E.noise_psd(w1.N, w1.dt)
+        m1 = E.model_batch(torch.from_numpy(w1.inj[None]).cuda(), c1)[0]
+        g1 = torch.from_numpy(W.gaussian_draws(w1.N, w1.noise_seed)).cuda()
+        sig1 = torch.sqrt(psd1 * (w1.N * w1.dt / 4.0))
+        sig1[0] = 0.0
+        sig1[-1] = 0.0
+        data1 = (torch.view_as_real(m1).clone() + sig1[None, :, None] * g1).contiguous()
+        dt1, st1, lat1, _ = run_path(E, W, w1, W.walkers(w1), data1, psd1, args.steps,
+                                     args.warmup)
+        config1 = {"workload": w1.name, "value": args.steps * w1.B / dt1,
+                   "unit": "lnL evals/s", "ms_per_step": 1e3 * dt1 / args.steps, "dtype": "f64",
+                   "batch_latency_ms": {"p50": float(np.percentile(lat1, 50)),
+                                        "p99": float(np.percentile(lat1, 99))}}
+        del m1, g1, sig1, data1
+        print(f"[bench] config 1: {config1['value']:.1f} evals/s, {config1['ms_per_step']:.3f} "
+              "ms/step", file=sys.stderr, flush=True)
 
     mixed = None
     if not args.no_mixed:
@@ -657,17 +663,19 @@ def main():
         mixed["stages"] = mst
         # waveform mismatch of the mixed path against the FP64 path (whose
         # parity with the oracle is tested) for every walker, 64 at a time
-        cmx = E.Config.from_workload(wmx)
-        mm = []
-        for w0 in range(0, wmx.B, 64):
-            Pd = torch.from_numpy(P[w0:w0 + 64]).cuda()
-            mm.append(noise_weighted_mismatch(E.model_batch(Pd, cmx), E.model_batch(Pd, cfg64),
-                                              psd, 1.0 / (w64.N * w64.dt)))
-            torch.cuda.empty_cache()
-        mm = np.concatenate(mm)
-        mixed["vs_fp64_path"]["mismatch_max"] = float(np.max(np.abs(mm)))
-        mixed["vs_fp64_path"]["mismatch_median"] = float(np.median(np.abs(mm)))
-        mixed["vs_fp64_path"]["mismatch_walkers"] = int(mm.size)
+        if not args.no_mismatch:
+            cmx = E.Config.from_workload(wmx)
+            mm = []
+            for w0 in range(0, wmx.B, 64):
+                Pd = torch.from_numpy(P[w0:w0 + 64]).cuda()
+                mm.append(noise_weighted_mismatch(E.model_batch(Pd, cmx),
+                                                  E.model_batch(Pd, cfg64), psd,
+                                                  1.0 / (w64.N * w64.dt)))
+                torch.cuda.empty_cache()
+            mm = np.concatenate(mm)
+            mixed["vs_fp64_path"]["mismatch_max"] = float(np.max(np.abs(mm)))
+            mixed["vs_fp64_path"]["mismatch_median"] = float(np.median(np.abs(mm)))
+            mixed["vs_fp64_path"]["mismatch_walkers"] = int(mm.size)
         # the mixed synthesis against the FP32 vector peak (the FP64 path's
         # roofline is the top-level one)
         ms_mx = stm["synthesis"][0] / stm["synthesis"][1]
@@ -784,7 +792,8 @@ def main():
         leg = run_oracle_leg(E, W, w64, wmx, P, w1, args.cpu_walkers)
         cpu = leg["cpu"]
         cpu["parity_sample_max_rel_dlnL"] = leg["sample_rel_dlnL"]["fp64"]
-        config1["vs_oracle"] = leg["config1_every_walker"]
+        if config1 is not None:
+            config1["vs_oracle"] = leg["config1_every_walker"]
         ev = leg.get("every_walker")
         roof_vs = {"fp64": {**(ev["fp64"] if ev else {}),
                             **leg["mismatch_vs_oracle"]["fp64"]}}

@@ -1172,7 +1172,11 @@ int oracle_make_data(const double *hinj, const double *pinj, const double *psd,
                      const double *gauss, int64_t N, double dt, double *data)
 {
     double s[8];
-    walker_scalars(pinj, 0, s);
+    /* only the propagation scalars (Eqs. (3)-(6)) enter here: the orbit, and
+     * with it the initial frequency, is already in hinj, so the injection's
+     * nu0 is not checked (an injection whose state is given at the LSO
+     * carries none) */
+    walker_scalars(pinj, 1, s);
     if (s[0] == 0.0) return -2;
     int64_t H = N / 2 + 1;
     double g = s[5];

@@ -171,3 +171,51 @@ def test_admission_by_footprint(E):
         st = srv.stats()
     assert st["rejected"] == 1
     assert st["arena_peak"] <= arena.numel()
+
+
+def test_served_config4_requests_match_the_oracle(E):
+    """Requests of the serving workload's own shape against the oracle: two of
+    its chains (state at the LSO, orbits integrated backward over the window),
+    half a year at dt = 10 s (2^21 samples), 30 harmonics, mixed precision,
+    data made by the oracle; requests of 3, 4, 2 and 3 walkers drawn as the
+    bench draws them, served eagerly and then through captured graphs.  Every
+    walker: relative lnL within 1e-4 and |dlnL| within 1e-5 <m|m> (the signal
+    scale)."""
+    chains = W.serving_chains()
+    sets = []
+    for c in (1, 6):
+        w = W.serving_workload(chains[c], 0)
+        d, S = oracle_dataset(w, True)
+        dd, ss = to_device_data(d, S)
+        sets.append((w, E.Config.from_workload(w), d, S, dd, ss))
+    reqs = [(0, 3, 21), (1, 4, 22), (0, 2, 23), (1, 3, 24)]
+    params = [W.walkers(sets[k][0], B=n, seed=sd) for k, n, sd in reqs]
+    # the oracle's lnL and <m|m> of every requested walker, one call per data set
+    refs = [None] * len(reqs)
+    for k in range(len(sets)):
+        w, cfg, d, S = sets[k][:4]
+        mine = [i for i, r in enumerate(reqs) if r[0] == k]
+        P = np.concatenate([params[i] for i in mine])
+        say("config-4 oracle for data set", k, "walkers", len(P))
+        r = O.loglike_sets(P, [d, np.zeros_like(d)], S, ocfg(w))
+        at = 0
+        for i in mine:
+            n = len(params[i])
+            refs[i] = (r[at:at + n, 0], -2.0 * r[at:at + n, 1])
+            at += n
+    arena = torch.empty(24 << 30, dtype=torch.uint8, device="cuda")
+    with E.Server(arena, n_streams=2, max_batch=64, use_graphs=True) as srv:
+        ids = [srv.add_dataset(dd, ss, cfg) for (w, cfg, d, S, dd, ss) in sets]
+        for rnd in range(3):                        # eager, captured, replayed
+            tickets = [srv.submit(ids[k], params[i]) for i, (k, n, sd) in enumerate(reqs)]
+            for i, t in enumerate(tickets):
+                got, _ = srv.wait(t, timeout=300.0)
+                ref, mm = refs[i]
+                fin = np.isfinite(ref)
+                assert np.array_equal(fin, np.isfinite(got))
+                err = np.abs(got[fin] - ref[fin])
+                say("config-4 request", rnd, i, "max |dlnL|/<m|m>", (err / mm[fin]).max())
+                assert np.all(err <= 1e-4 * np.abs(ref[fin]))
+                assert np.all(err <= 1e-5 * mm[fin])
+        st = srv.stats()
+    assert st["graph_launches"] >= 1

@@ -52,7 +52,8 @@ class OracleConfig:
     coarse_log2: int = 10
     lo_only: bool = False
     ic_lso: bool = False      # initial conditions at the LSO, orbit integrated backward
-    ode: int = 0              # 0: classical RK4 on the nodes; 1: adaptive Dormand-Prince 5(4)
+    ode: int = 0              # 0: classical RK4 on the nodes; 1: adaptive Dormand-Prince 5(4);
+                              # 2: Fehlberg 7(8), node to node
     rtol: float = 1e-10       # tolerances of the adaptive integrator
     atol: float = 1e-10
 
@@ -100,6 +101,7 @@ def lib():
             "oracle_orbit": ([dp, i64, cp, dp, ip], ctypes.c_int),
             "oracle_orbit_steps": ([dp, i64, cp, ip], ctypes.c_int),
             "oracle_dp5_tableau": ([dp], ctypes.c_int),
+            "oracle_rk78_tableau": ([dp], ctypes.c_int),
             "oracle_waveform": ([dp, i64, cp, dp], ctypes.c_int),
             "oracle_waveform_diag": ([dp, cp, dp, dp], ctypes.c_int),
             "oracle_rfft": ([dp, i64, i64, ctypes.c_double, dp], ctypes.c_int),
@@ -178,7 +180,7 @@ def orbit(params, cfg: OracleConfig):
 
 
 def orbit_steps(params, cfg: OracleConfig) -> np.ndarray:
-    """[B][2] accepted and rejected steps of the adaptive integrator (ode=1)."""
+    """[B][2] accepted and rejected steps of the adaptive integrators (ode=1, 2)."""
     p = _f64(params).reshape(-1, NPAR)
     out = np.zeros((p.shape[0], 2), dtype=np.int32)
     c = cfg.c()
@@ -194,6 +196,14 @@ def dp5_tableau():
     out = np.zeros(77)
     lib().oracle_dp5_tableau(_p(out))
     return (out[:7], out[7:56].reshape(7, 7), out[56:63], out[63:70], out[70:77])
+
+
+def rk78_tableau():
+    """The oracle's Fehlberg 7(8) constants: c[13], A[13][12], the order-7
+    weights b7[13] and the order-8 weights b8[13]."""
+    out = np.zeros(195)
+    lib().oracle_rk78_tableau(_p(out))
+    return out[:13], out[13:169].reshape(13, 12), out[169:182], out[182:195]
 
 
 def waveform(params, cfg: OracleConfig) -> np.ndarray:

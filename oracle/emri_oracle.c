@@ -95,9 +95,10 @@ typedef struct {
     int32_t coarse_log2; /* coarse ODE step = dt * 2^coarse_log2            */
     int32_t lo_only;     /* test hook: leading-order (Peters-Mathews) ODE    */
     int32_t ic_lso;      /* 1: initial conditions at the LSO, integrated backward */
-    int32_t ode;         /* 0: classical RK4 on the nodes; 1: adaptive Dormand-Prince 5(4) */
+    int32_t ode;         /* 0: classical RK4 on the nodes; 1: adaptive Dormand-Prince 5(4);
+                          * 2: Fehlberg 7(8), node to node */
     int32_t reserved;
-    double rtol, atol;   /* tolerances of the adaptive integrator (ode = 1)   */
+    double rtol, atol;   /* tolerances of the adaptive integrators (ode = 1, 2) */
 } oracle_cfg;
 
 int oracle_num_threads(void);
@@ -337,11 +338,13 @@ static int64_t walker_orbit_lso(const double *p, const oracle_cfg *c, double *or
 }
 
 static int64_t walker_orbit_dp5(const double *p, const oracle_cfg *c, double *orb, int32_t *stats);
+static int64_t walker_orbit_rk78(const double *p, const oracle_cfg *c, double *orb, int32_t *stats);
 static int cfg_ok(const oracle_cfg *c);
 
 static int64_t walker_orbit(const double *p, const oracle_cfg *c, double *orb)
 {
     if (c->ode == 1) return walker_orbit_dp5(p, c, orb, NULL);
+    if (c->ode == 2) return walker_orbit_rk78(p, c, orb, NULL);
     if (c->ic_lso) return walker_orbit_lso(p, c, orb);
     int64_t K = n_intervals_of(c);
     double h = c->dt * (double)((int64_t)1 << c->coarse_log2);
@@ -532,16 +535,169 @@ static int64_t walker_orbit_dp5(const double *p, const oracle_cfg *c, double *or
     return -1;                         /* step budget exhausted */
 }
 
+/* ------------------------------------------------------------------------ */
+/* Seventh-order orbit (cfg.ode = 2).  Reading: the "7th-order Runge-Kutta   */
+/* scheme" of Sec. 3 ("Waveform computation") is taken as Fehlberg's         */
+/* embedded 7(8) pair (NASA TR R-287, 1968; 13 stages), the order-7          */
+/* solution kept and the order-8 one used for the error estimate only.       */
+/* The integration runs node to node: a step never passes the next coarse   */
+/* node t_k = k h_c, so every node value is a step end of the method itself */
+/* and no continuous extension enters.                                      */
+/*   error estimate err = H (b7 - b8) . k = H 41/840 (k1 + k11 - k12 - k13)  */
+/*   error norm    as for ode = 1 (rms over the five components, nu on rtol */
+/*                 alone)                                                   */
+/*   accept        err <= 1; then H <- H min(5, max(0.2, 0.9 err^(-1/8)))   */
+/*                 (factor at most 1 right after a rejection), H the step   */
+/*                 just taken                                               */
+/*   reject        H <- H max(0.2, 0.9 err^(-1/8)) (a non-finite err: 0.2)  */
+/*   first step    one coarse interval; a step that would pass the next     */
+/*                 node is cut to end on it                                 */
+/*   stop          forward: at the first step end past the LSO (K_w = the   */
+/*                 last node filled before it); backward from the LSO: a    */
+/*                 step end outside the physical range makes the walker     */
+/*                 invalid                                                  */
+/*   budget        4 K + 64 step attempts, else the walker is invalid       */
+/* ------------------------------------------------------------------------ */
+static const double F78_C[13] = {0.0,       2.0 / 27.0, 1.0 / 9.0, 1.0 / 6.0, 5.0 / 12.0,
+                                 1.0 / 2.0, 5.0 / 6.0,  1.0 / 6.0, 2.0 / 3.0, 1.0 / 3.0,
+                                 1.0,       0.0,        1.0};
+static const double F78_A[13][12] = {
+    {0.0},
+    {2.0 / 27.0},
+    {1.0 / 36.0, 1.0 / 12.0},
+    {1.0 / 24.0, 0.0, 1.0 / 8.0},
+    {5.0 / 12.0, 0.0, -25.0 / 16.0, 25.0 / 16.0},
+    {1.0 / 20.0, 0.0, 0.0, 1.0 / 4.0, 1.0 / 5.0},
+    {-25.0 / 108.0, 0.0, 0.0, 125.0 / 108.0, -65.0 / 27.0, 125.0 / 54.0},
+    {31.0 / 300.0, 0.0, 0.0, 0.0, 61.0 / 225.0, -2.0 / 9.0, 13.0 / 900.0},
+    {2.0, 0.0, 0.0, -53.0 / 6.0, 704.0 / 45.0, -107.0 / 9.0, 67.0 / 90.0, 3.0},
+    {-91.0 / 108.0, 0.0, 0.0, 23.0 / 108.0, -976.0 / 135.0, 311.0 / 54.0, -19.0 / 60.0,
+     17.0 / 6.0, -1.0 / 12.0},
+    {2383.0 / 4100.0, 0.0, 0.0, -341.0 / 164.0, 4496.0 / 1025.0, -301.0 / 82.0,
+     2133.0 / 4100.0, 45.0 / 82.0, 45.0 / 164.0, 18.0 / 41.0},
+    {3.0 / 205.0, 0.0, 0.0, 0.0, 0.0, -6.0 / 41.0, -3.0 / 205.0, -3.0 / 41.0, 3.0 / 41.0,
+     6.0 / 41.0},
+    {-1777.0 / 4100.0, 0.0, 0.0, -341.0 / 164.0, 4496.0 / 1025.0, -289.0 / 82.0,
+     2193.0 / 4100.0, 51.0 / 82.0, 33.0 / 164.0, 12.0 / 41.0, 0.0, 1.0}};
+/* order-7 weights (kept) and order-8 weights (error estimate) */
+static const double F78_B7[13] = {41.0 / 840.0, 0.0, 0.0, 0.0, 0.0, 34.0 / 105.0, 9.0 / 35.0,
+                                  9.0 / 35.0, 9.0 / 280.0, 9.0 / 280.0, 41.0 / 840.0, 0.0, 0.0};
+static const double F78_B8[13] = {0.0, 0.0, 0.0, 0.0, 0.0, 34.0 / 105.0, 9.0 / 35.0,
+                                  9.0 / 35.0, 9.0 / 280.0, 9.0 / 280.0, 0.0, 41.0 / 840.0,
+                                  41.0 / 840.0};
+
+int oracle_rk78_tableau(double *out /* [195]: c[13], A[13][12], b7[13], b8[13] */)
+{
+    for (int i = 0; i < 13; ++i) {
+        out[i] = F78_C[i];
+        for (int j = 0; j < 12; ++j) out[13 + 12 * i + j] = F78_A[i][j];
+        out[169 + i] = F78_B7[i];
+        out[182 + i] = F78_B8[i];
+    }
+    return 0;
+}
+
+/* stats (optional): [0] accepted steps, [1] rejected steps */
+static int64_t walker_orbit_rk78(const double *p, const oracle_cfg *c, double *orb, int32_t *stats)
+{
+    const int64_t K = n_intervals_of(c);
+    const double hc = c->dt * (double)((int64_t)1 << c->coarse_log2);
+    const double M_s = p[I_M] * O_TSUN, mu_s = p[I_MU] * O_TSUN, a = p[I_A], cl = p[I_CLAM];
+    const int back = c->ic_lso != 0;
+    const int64_t budget = 4 * K + 64;
+    memset(orb, 0, (size_t)(K + 1) * 10 * sizeof(double));
+    if (stats) stats[0] = stats[1] = 0;
+
+    double y[5], f[5];
+    int64_t node;     /* the next node to fill */
+    double t;
+    if (back) {
+        y[0] = p[I_PHI0]; y[1] = nu_lso(M_s, p[I_E0]); y[2] = p[I_GT0]; y[3] = p[I_E0];
+        y[4] = p[I_AL0];
+        t = (double)K * hc;
+        node = K - 1;
+    } else {
+        y[0] = p[I_PHI0]; y[1] = p[I_NU0]; y[2] = p[I_GT0]; y[3] = p[I_E0]; y[4] = p[I_AL0];
+        t = 0.0;
+        node = 1;
+    }
+    ak_rhs(y, M_s, mu_s, a, cl, c->lo_only, f);
+    double *o0 = orb + (back ? K : 0) * 10;
+    for (int i = 0; i < 5; ++i) { o0[i] = y[i]; o0[5 + i] = f[i]; }
+    if (K == 0) return 0;
+
+    double H = back ? -hc : hc;
+    int rejected = 0;
+    for (int64_t att = 0; att < budget; ++att) {
+        /* the step, cut to end on the next node */
+        const double tn = (double)node * hc;
+        double Hs = H;
+        int land = 0;
+        if (back ? (t + Hs <= tn) : (t + Hs >= tn)) { Hs = tn - t; land = 1; }
+
+        double k[13][5], ys[5], y1[5];
+        for (int i = 0; i < 5; ++i) k[0][i] = f[i];
+        for (int s = 1; s < 13; ++s) {
+            for (int i = 0; i < 5; ++i) {
+                double acc = 0.0;
+                for (int j = 0; j < s; ++j) acc += F78_A[s][j] * k[j][i];
+                ys[i] = y[i] + Hs * acc;
+            }
+            ak_rhs(ys, M_s, mu_s, a, cl, c->lo_only, k[s]);
+        }
+        double sum = 0.0;
+        for (int i = 0; i < 5; ++i) {
+            double acc = 0.0, err = 0.0;
+            for (int j = 0; j < 13; ++j) {
+                acc += F78_B7[j] * k[j][i];
+                err += (F78_B7[j] - F78_B8[j]) * k[j][i];
+            }
+            y1[i] = y[i] + Hs * acc;
+            err *= Hs;
+            double sc = (i == 1 ? 0.0 : c->atol) + c->rtol * fmax(fabs(y[i]), fabs(y1[i]));
+            sum += (err / sc) * (err / sc);
+        }
+        double en = sqrt(sum / 5.0);
+        double fac = fmax(0.2, 0.9 * pow(en, -0.125));
+        if (!(en <= 1.0)) {            /* rejected (a NaN norm too) */
+            H = Hs * fac;
+            rejected = 1;
+            if (stats) stats[1]++;
+            continue;
+        }
+        if (stats) stats[0]++;
+        if (back) {
+            if (!node_sane(y1)) return -1;
+        } else if (!node_ok(y1, M_s)) {
+            return node - 1;           /* past the LSO before node `node` */
+        }
+        for (int i = 0; i < 5; ++i) y[i] = y1[i];
+        ak_rhs(y, M_s, mu_s, a, cl, c->lo_only, f);
+        t = land ? tn : t + Hs;
+        if (land) {
+            double *o = orb + node * 10;
+            for (int i = 0; i < 5; ++i) { o[i] = y[i]; o[5 + i] = f[i]; }
+            if (back ? node == 0 : node == K) return K;
+            node += back ? -1 : 1;
+        }
+        H = Hs * fmin(rejected ? 1.0 : 5.0, fac);
+        rejected = 0;
+    }
+    return -1;                         /* step budget exhausted */
+}
+
 int oracle_orbit_steps(const double *params, int64_t B, const oracle_cfg *c, int32_t *steps /* [B][2] */)
 {
-    if (!cfg_ok(c) || c->ode != 1) return -1;
+    if (!cfg_ok(c) || (c->ode != 1 && c->ode != 2)) return -1;
     int64_t K = n_intervals_of(c);
     double *orb = (double *)malloc((size_t)(K + 1) * 10 * sizeof(double));
     for (int64_t w = 0; w < B; ++w) {
         steps[2 * w] = steps[2 * w + 1] = 0;
         double s[8];
         walker_scalars(params + w * NPAR, c->ic_lso, s);
-        if (s[0] != 0.0) walker_orbit_dp5(params + w * NPAR, c, orb, steps + 2 * w);
+        if (s[0] == 0.0) continue;
+        if (c->ode == 1) walker_orbit_dp5(params + w * NPAR, c, orb, steps + 2 * w);
+        else walker_orbit_rk78(params + w * NPAR, c, orb, steps + 2 * w);
     }
     free(orb);
     return 0;
@@ -777,8 +933,8 @@ static int cfg_ok(const oracle_cfg *c)
     if (!(c->dt > 0.0) || !(c->T_obs > 0.0) || c->N < 2 || (c->N & (c->N - 1))) return 0;
     if (n_valid_of(c) > c->N || n_valid_of(c) < 1) return 0;
     if (c->n_harm < 1 || c->n_harm > 100 || c->coarse_log2 < 0 || c->coarse_log2 > 30) return 0;
-    if (c->ode != 0 && c->ode != 1) return 0;
-    if (c->ode == 1 && !(c->rtol >= 1e-13 && c->rtol <= 1e-3 && c->atol >= 0.0 && isfinite(c->atol)))
+    if (c->ode != 0 && c->ode != 1 && c->ode != 2) return 0;
+    if (c->ode != 0 && !(c->rtol >= 1e-13 && c->rtol <= 1e-3 && c->atol >= 0.0 && isfinite(c->atol)))
         return 0;
     return 1;
 }

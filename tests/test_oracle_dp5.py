@@ -21,6 +21,7 @@ from scipy.integrate import solve_ivp
 
 import oracle as O
 from paper_2311_17174_amd import workloads as W
+from tests.butcher import defects as _defects, trees as _trees
 
 TSUN = 4.925490947641267e-6
 
@@ -28,59 +29,6 @@ TSUN = 4.925490947641267e-6
 def cfg(w, **kw):
     return O.OracleConfig(T_obs=w.T_obs, dt=w.dt, N=w.N, n_harm=w.n_harm,
                           coarse_log2=w.coarse_log2, **kw)
-
-
-# ---- rooted trees and elementary weights ---------------------------------
-def _trees(n, memo={}):
-    """Rooted trees with n vertices, each a sorted tuple of child trees."""
-    if n in memo:
-        return memo[n]
-    if n == 1:
-        memo[1] = [()]
-        return memo[1]
-    out = set()
-
-    def forests(m, smallest):
-        if m == 0:
-            yield ()
-            return
-        for k in range(1, m + 1):
-            for t in _trees(k):
-                key = (k, t)
-                if smallest is not None and key < smallest:
-                    continue
-                for rest in forests(m - k, key):
-                    yield (t,) + rest
-
-    for f in forests(n - 1, None):
-        out.add(tuple(sorted(f)))
-    memo[n] = sorted(out)
-    return memo[n]
-
-
-def _order(t):
-    return 1 + sum(_order(x) for x in t)
-
-
-def _gamma(t):
-    g = _order(t)
-    for x in t:
-        g *= _gamma(x)
-    return g
-
-
-def _phi(t, A):
-    """Stage vector of the elementary weight of tree t."""
-    v = np.ones(A.shape[0])
-    for ch in t:
-        v = v * (A @ _phi(ch, A))
-    return v
-
-
-def _defects(w, A, p, theta=1.0):
-    """max |sum_i w_i Phi_i(t) - theta^rho / gamma(t)| over trees of order <= p."""
-    return max(abs(w @ _phi(t, A) - theta ** _order(t) / _gamma(t))
-               for n in range(1, p + 1) for t in _trees(n))
 
 
 def test_tree_counts():
@@ -254,7 +202,7 @@ def test_bad_tolerances_are_rejected():
         with pytest.raises(ValueError):
             O.orbit(p[None], cfg(w, ode=1, rtol=rtol, atol=atol))
     with pytest.raises(ValueError):
-        O.orbit(p[None], cfg(w, ode=2))
+        O.orbit(p[None], cfg(w, ode=3))
 
 
 def test_step_count_follows_the_order_five_controller():

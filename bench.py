@@ -278,17 +278,20 @@ def run_fmg(E, W, w, data, psd, steps: int, warmup: int):
 
 
 def run_dp5(E, W, w, data, psd, steps: int, warmup: int, rtol: float = 1e-12):
-    """The adaptive orbit integrator (Dormand-Prince 5(4), tolerance rtol,
-    continuous extension at the coarse nodes) against the classical RK4 path,
-    on the same walkers and resident data as the main line, with the state at
-    t = 0 (orbit-segment pipeline) and at the LSO (one backward segment)."""
+    """The adaptive orbit integrators against the classical RK4 path: the
+    Dormand-Prince 5(4) pair (continuous extension at the coarse nodes) and
+    Fehlberg's 7(8) pair (order 7 kept, stepped node to node), both at
+    tolerance rtol, on the same walkers and resident data as the main line,
+    with the state at t = 0 and at the LSO (both in the orbit-segment
+    pipeline)."""
     import torch
     P = torch.from_numpy(W.walkers(w)).cuda()
     out = torch.empty(w.B, dtype=torch.float64, device="cuda")
     res = {}
     lnl = {}
     for ic, tag in ((0, ""), (1, "_lso")):
-        for name, wk in (("rk4", w), ("dp5", w.with_(ode=1, ode_rtol=rtol, ode_atol=rtol))):
+        for name, wk in (("rk4", w), ("dp5", w.with_(ode=1, ode_rtol=rtol, ode_atol=rtol)),
+                         ("rk78", w.with_(ode=2, ode_rtol=rtol, ode_atol=rtol))):
             cfg = E.Config.from_workload(wk.with_(ic=ic))
             ds = E.dataset_init(data, psd, cfg)
             ws = E.alloc_workspace(cfg, w.B)
@@ -309,6 +312,8 @@ def run_dp5(E, W, w, data, psd, steps: int, warmup: int, rtol: float = 1e-12):
             del ds, ws
     res.update({"unit": "lnL evals/s", "workload": w.name, "rtol": rtol, "atol": rtol,
                 "max_abs_dlnL_vs_rk4": float(np.max(np.abs(lnl["dp5"] - lnl["rk4"]))),
+                "max_abs_dlnL_rk78_vs_rk4": float(np.max(np.abs(lnl["rk78"] - lnl["rk4"]))),
+                "max_abs_dlnL_rk78_vs_dp5": float(np.max(np.abs(lnl["rk78"] - lnl["dp5"]))),
                 "orbit_speedup": res["rk4"]["orbit_ms_per_step"] / res["dp5"]["orbit_ms_per_step"],
                 "orbit_speedup_lso": (res["rk4_lso"]["orbit_ms_per_step"]
                                       / res["dp5_lso"]["orbit_ms_per_step"])})
@@ -725,7 +730,10 @@ def main():
               f"{dp5['fp64']['orbit_speedup']:.2f}x faster than RK4; LSO convention "
               f"{dp5['fp64']['dp5_lso']['value']:.1f} evals/s, orbit "
               f"{dp5['fp64']['orbit_speedup_lso']:.2f}x), mixed "
-              f"{dp5['mixed']['dp5']['value']:.1f} evals/s", file=sys.stderr, flush=True)
+              f"{dp5['mixed']['dp5']['value']:.1f} evals/s; order 7: fp64 "
+              f"{dp5['fp64']['rk78']['value']:.1f} evals/s (orbit "
+              f"{dp5['fp64']['rk78']['orbit_ms_per_step']:.2f} ms per step)",
+              file=sys.stderr, flush=True)
 
     serving = None
     if not args.no_serving:

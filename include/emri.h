@@ -60,7 +60,7 @@ extern "C" {
 #endif
 
 #define EMRI_NPAR 17
-#define EMRI_ABI_VERSION 7
+#define EMRI_ABI_VERSION 8
 
 typedef enum {
     EMRI_OK = 0,
@@ -123,13 +123,23 @@ typedef enum {
  *               4 K + 64 step attempts is invalid (lnL = -inf; its
  *               time-domain rows then hold whatever was synthesised before
  *               that was found).
+ *               EMRI_ODE_RK78: the paper's "7th-order Runge-Kutta scheme",
+ *               read as Fehlberg's embedded 7(8) pair (NASA TR R-287,
+ *               1968; 13 stages), the order-7 solution kept and the order-8
+ *               one used for the error estimate alone, stepped node to node:
+ *               a step never passes the next coarse node (it is cut to end
+ *               on it), so every node is a step end of the method and no
+ *               interpolation enters.  Step control as for DP5 with the
+ *               exponent 1/8; the orbit stops at the first step end past the
+ *               LSO (forward) or outside 0 <= e < 1, nu > 0 (backward:
+ *               invalid); the same step budget.
  *  reserved     0
- *  ode_rtol     EMRI_ODE_DP5: relative tolerance, 1e-13 .. 1e-3
- *  ode_atol     EMRI_ODE_DP5: absolute tolerance >= 0 for Phi, gamma~ and
- *               alpha [rad] and e; nu is held to ode_rtol relative alone.
- *               Both are ignored with EMRI_ODE_RK4. */
+ *  ode_rtol     EMRI_ODE_DP5, EMRI_ODE_RK78: relative tolerance, 1e-13 .. 1e-3
+ *  ode_atol     EMRI_ODE_DP5, EMRI_ODE_RK78: absolute tolerance >= 0 for Phi,
+ *               gamma~ and alpha [rad] and e; nu is held to ode_rtol relative
+ *               alone.  Both are ignored with EMRI_ODE_RK4. */
 typedef enum { EMRI_IC_START = 0, EMRI_IC_LSO = 1 } emri_ic;
-typedef enum { EMRI_ODE_RK4 = 0, EMRI_ODE_DP5 = 1 } emri_ode;
+typedef enum { EMRI_ODE_RK4 = 0, EMRI_ODE_DP5 = 1, EMRI_ODE_RK78 = 2 } emri_ode;
 typedef struct {
     double T_obs;
     double dt;
@@ -180,6 +190,21 @@ const char* emri_last_error(void);
 /* Workspace bytes for B walkers processed at once (0 if cfg is invalid).
  * The waveform, FFT and likelihood entry points all accept this size. */
 size_t emri_workspace_bytes(const emri_cfg* cfg, int64_t B);
+
+/* The orbit of each walker alone (Eq. (1), integrated as emri_cfg.ode
+ * selects; Sec. 3 "Waveform computation"): the coarse nodes that the
+ * amplitude tables and the synthesis read.
+ *  params  [B][17] fp64
+ *  orb     [B][K+1][10] fp64, K = ceil(N_valid / 2^coarse_log2): at node
+ *          t_k = k dt 2^coarse_log2 the state (Phi, nu, gamma~, e, alpha),
+ *          then its time derivative (the right-hand side of Eq. (1) at the
+ *          node state); zero after node kw and for an invalid walker
+ *  kw      [B] int32: the last node before the LSO (forward), K (backward
+ *          from the LSO), -1 for an invalid walker
+ *  ws      workspace of at least emri_workspace_bytes(cfg, B) bytes
+ * Same precision for every emri_cfg.precision: the orbit is FP64. */
+emri_status emri_orbit_batch(const double* params, int64_t B, const emri_cfg* cfg, double* orb,
+                             int32_t* kw, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Time-domain waveforms (Eqs. (1)-(2) with the LISA response and Doppler
  * phase), at unit distance and without propagation effects -- the paper's

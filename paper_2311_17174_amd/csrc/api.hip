@@ -132,15 +132,15 @@ emri_status make_plan(const emri_cfg* cfg, int64_t B, const Tuning& tn, Plan* p,
         *err = "ic must be EMRI_IC_START or EMRI_IC_LSO";
         return EMRI_EINVAL;
     }
-    if (cfg->ode != EMRI_ODE_RK4 && cfg->ode != EMRI_ODE_DP5) {
-        *err = "ode must be EMRI_ODE_RK4 or EMRI_ODE_DP5";
+    if (cfg->ode != EMRI_ODE_RK4 && cfg->ode != EMRI_ODE_DP5 && cfg->ode != EMRI_ODE_RK78) {
+        *err = "ode must be EMRI_ODE_RK4, EMRI_ODE_DP5 or EMRI_ODE_RK78";
         return EMRI_EINVAL;
     }
     if (cfg->reserved != 0) { *err = "reserved must be 0"; return EMRI_EINVAL; }
-    if (cfg->ode == EMRI_ODE_DP5 &&
+    if (cfg->ode != EMRI_ODE_RK4 &&
         !(cfg->ode_rtol >= 1e-13 && cfg->ode_rtol <= 1e-3 && cfg->ode_atol >= 0.0 &&
           isfinite(cfg->ode_atol))) {
-        *err = "DP5 tolerances: need 1e-13 <= ode_rtol <= 1e-3 and a finite ode_atol >= 0";
+        *err = "adaptive tolerances: need 1e-13 <= ode_rtol <= 1e-3 and a finite ode_atol >= 0";
         return EMRI_EINVAL;
     }
     if (B < 0) { *err = "B must be >= 0"; return EMRI_EINVAL; }
@@ -466,6 +466,24 @@ emri_status emri_waveform_batch(const double* params, int64_t B, const emri_cfg*
     if (!params || !ht || !ws) return fail(EMRI_EINVAL, "null pointer argument");
     if (ws_bytes < p.total) return fail(EMRI_EWORKSPACE, "workspace smaller than emri_workspace_bytes(cfg, B)");
     return run_waveforms(p, params, B, ws, ht, true, stream);
+}
+
+emri_status emri_orbit_batch(const double* params, int64_t B, const emri_cfg* cfg, double* orb,
+                             int32_t* kw, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    Plan p;
+    const char* err;
+    emri_status st = make_plan(cfg, B, tuning_now(), &p, &err);
+    if (st != EMRI_OK) return fail(st, err);
+    if (B == 0) return EMRI_OK;
+    if (!params || !orb || !kw || !ws) return fail(EMRI_EINVAL, "null pointer argument");
+    if (ws_bytes < p.total) return fail(EMRI_EWORKSPACE, "workspace smaller than emri_workspace_bytes(cfg, B)");
+    // the whole orbit as one segment: forward up to node K, backward down to 0
+    const bool back = p.ic == EMRI_IC_LSO;
+    if ((st = check_launch(launch_walker_setup(p, params, B, ws, back ? 0 : p.K, stream),
+                           "walker setup")))
+        return st;
+    return check_launch(launch_orbit_out(p, B, ws, orb, kw, stream), "orbit copy");
 }
 
 emri_status emri_fft_batch(const void* ht, int64_t B, const emri_cfg* cfg, void* hf, void* ws,

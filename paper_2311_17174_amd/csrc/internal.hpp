@@ -49,7 +49,7 @@ enum {
     WC_AT = 31,     // alpha_T of the parameter row
     WC_KSEG = 32,   // 16 slots: K_w as known after orbit segment i (the
                     // segment's end when the orbit is still before the LSO)
-    // adaptive integrator state between orbit segments (emri_cfg.ode = DP5)
+    // adaptive integrator state between orbit segments (emri_cfg.ode = DP5, RK78)
     WC_OT = 48,     // time of the state
     WC_OY = 49,     // 5 slots: the state Y
     WC_OF = 54,     // 5 slots: f(Y) (first stage of the next step)
@@ -95,7 +95,7 @@ struct Plan {
     int prec;              // emri_precision
     int cl;                // coarse_log2
     int ic;                // emri_cfg.ic: initial conditions at t = 0 or at the LSO
-    int ode;               // emri_cfg.ode: RK4 or adaptive DP5
+    int ode;               // emri_cfg.ode: RK4, adaptive DP5 or RK78
     double rtol, atol;     // DP5 tolerances
     int64_t L;             // samples per coarse interval, 2^cl
     int64_t K;             // coarse intervals covering N_valid
@@ -143,6 +143,10 @@ hipError_t launch_walker_setup(const Plan& p, const double* params, int64_t B, v
 hipError_t launch_walker_resume(const Plan& p, int64_t B, void* ws, int64_t k0, int64_t k1,
                                 int seg, hipStream_t s);
 // node amplitudes and interval tables of segment seg (intervals [k0, k1))
+// the orbit nodes of the workspace to a caller's [B][K+1][10] array (zero
+// after K_w and for invalid walkers) and K_w to kw[B]
+hipError_t launch_orbit_out(const Plan& p, int64_t B, const void* ws, double* orb, int32_t* kw,
+                            hipStream_t s);
 hipError_t launch_tables(const Plan& p, int64_t B, void* ws, int64_t k0, int64_t k1, int seg,
                          hipStream_t s);
 // samples of the intervals [k0, k1) (k1 may reach N / L: zero tail); with

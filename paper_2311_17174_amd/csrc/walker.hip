@@ -5,10 +5,12 @@
 //                   ODE of Eq. (1) by classical RK4 on the coarse grid,
 //                   stopped at the last node before the LSO (Sec. 3);
 //                   k_walker_resume continues it segment by segment
-//  k_walker_setup_dp5, k_orbit_dp5
+//  k_walker_setup_adaptive, k_orbit_dp5, k_orbit_rk78
 //                   the same constants, then the ODE by the adaptive
 //                   Dormand-Prince 5(4) pair sampled at the same nodes by its
-//                   continuous extension, one wave per walker
+//                   continuous extension (one wave per walker), or by
+//                   Fehlberg's 7(8) pair stepped node to node (one lane per
+//                   walker)
 //  k_nodes          one lane per (walker, orbit node, harmonic): Bessel
 //                   functions of the Peters-Mathews amplitudes and their time
 //                   derivatives at the node
@@ -431,6 +433,136 @@ __device__ inline void finish_segment(int r, const State& s, int64_t kw, int seg
 }
 }  // namespace dp5
 
+// ---------------------------------------------------------------------------
+// Seventh-order orbit (emri_cfg.ode = EMRI_ODE_RK78): Fehlberg's embedded
+// 7(8) pair (NASA TR R-287, 1968; 13 stages), the order-7 solution kept and
+// the order-8 one entering the error estimate alone, which reduces to
+// H 41/840 (k1 + k11 - k12 - k13).  The steps run node to node: a step that
+// would pass the next coarse node is cut to end on it, so each node is a
+// step end of the method and no continuous extension is needed, and one lane
+// integrates one walker.  Step control as for the 5(4) pair with the
+// exponent 1/8; the state between segments is the 5(4) pair's (dp5::State).
+// ---------------------------------------------------------------------------
+namespace rk78 {
+constexpr double kA[13][12] = {
+    {0.0},
+    {2.0 / 27.0},
+    {1.0 / 36.0, 1.0 / 12.0},
+    {1.0 / 24.0, 0.0, 1.0 / 8.0},
+    {5.0 / 12.0, 0.0, -25.0 / 16.0, 25.0 / 16.0},
+    {1.0 / 20.0, 0.0, 0.0, 1.0 / 4.0, 1.0 / 5.0},
+    {-25.0 / 108.0, 0.0, 0.0, 125.0 / 108.0, -65.0 / 27.0, 125.0 / 54.0},
+    {31.0 / 300.0, 0.0, 0.0, 0.0, 61.0 / 225.0, -2.0 / 9.0, 13.0 / 900.0},
+    {2.0, 0.0, 0.0, -53.0 / 6.0, 704.0 / 45.0, -107.0 / 9.0, 67.0 / 90.0, 3.0},
+    {-91.0 / 108.0, 0.0, 0.0, 23.0 / 108.0, -976.0 / 135.0, 311.0 / 54.0, -19.0 / 60.0,
+     17.0 / 6.0, -1.0 / 12.0},
+    {2383.0 / 4100.0, 0.0, 0.0, -341.0 / 164.0, 4496.0 / 1025.0, -301.0 / 82.0,
+     2133.0 / 4100.0, 45.0 / 82.0, 45.0 / 164.0, 18.0 / 41.0},
+    {3.0 / 205.0, 0.0, 0.0, 0.0, 0.0, -6.0 / 41.0, -3.0 / 205.0, -3.0 / 41.0, 3.0 / 41.0,
+     6.0 / 41.0},
+    {-1777.0 / 4100.0, 0.0, 0.0, -341.0 / 164.0, 4496.0 / 1025.0, -289.0 / 82.0,
+     2193.0 / 4100.0, 51.0 / 82.0, 33.0 / 164.0, 12.0 / 41.0, 0.0, 1.0}};
+// order-7 weights; b7 - b8 (b8 the order-8 weights)
+constexpr double kB[13] = {41.0 / 840.0, 0.0, 0.0, 0.0, 0.0, 34.0 / 105.0, 9.0 / 35.0,
+                           9.0 / 35.0, 9.0 / 280.0, 9.0 / 280.0, 41.0 / 840.0, 0.0, 0.0};
+constexpr double kE[13] = {41.0 / 840.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0,
+                           0.0, 0.0, 0.0, 41.0 / 840.0, -41.0 / 840.0, -41.0 / 840.0};
+
+// steps until node `stop` is filled (forward: nodes up to stop; backward:
+// down to stop); the return codes and *kw are those of dp5::advance
+__device__ int advance(dp5::State& s, int64_t stop, int64_t K, double hc, bool back,
+                       double rtol, double atol, double Ms, double mus, double a, double cl,
+                       double* __restrict__ o, int64_t* kw)
+{
+    const int64_t budget = 4 * K + 64;
+    while (back ? s.node >= stop : s.node <= stop) {
+        if (s.att >= budget) return dp5::FAIL;
+        ++s.att;
+        const double tn = (double)s.node * hc;
+        double Hs = s.H;
+        bool land = false;
+        if (back ? (s.t + Hs <= tn) : (s.t + Hs >= tn)) {
+            Hs = tn - s.t;
+            land = true;
+        }
+        // a stage's state needs only the nu and e components of the earlier
+        // stages; the weight sums take all five, in stage order
+        double kn[13], ke[13], sB[5], sE[5];
+        kn[0] = s.f.dnu;
+        ke[0] = s.f.de;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            sB[i] = kB[0] * dp5::comp(s.f, i);
+            sE[i] = kE[0] * dp5::comp(s.f, i);
+        }
+        const double n0 = s.Y[1], e0 = s.Y[3];
+#pragma unroll
+        for (int st = 1; st < 13; ++st) {
+            double an = 0.0, ae = 0.0;
+#pragma unroll
+            for (int j = 0; j < st; ++j) {
+                if (kA[st][j] != 0.0) {
+                    an += kA[st][j] * kn[j];
+                    ae += kA[st][j] * ke[j];
+                }
+            }
+            const Rhs k = ak_rhs(n0 + Hs * an, e0 + Hs * ae, Ms, mus, a, cl);
+            kn[st] = k.dnu;
+            ke[st] = k.de;
+#pragma unroll
+            for (int i = 0; i < 5; ++i) {
+                if (kB[st] != 0.0) sB[i] += kB[st] * dp5::comp(k, i);
+                if (kE[st] != 0.0) sE[i] += kE[st] * dp5::comp(k, i);
+            }
+        }
+        double y1[5], sum = 0.0;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            y1[i] = s.Y[i] + Hs * sB[i];
+            const double err = Hs * sE[i];
+            const double sc = (i == 1 ? 0.0 : atol) + rtol * fmax(fabs(s.Y[i]), fabs(y1[i]));
+            const double q = err / sc;
+            sum += q * q;
+        }
+        const double en = sqrt(sum / 5.0);
+        const double fac = fmax(dp5::kFacMin, dp5::kSafety * pow(en, -0.125));
+        if (!(en <= 1.0)) {              // rejected (a NaN norm too)
+            s.H = Hs * fac;
+            s.rej = 1;
+            continue;
+        }
+        double x13 = 0.0;
+        if (back) {
+            if (!(isfinite(y1[0]) && isfinite(y1[1]) && isfinite(y1[2]) && isfinite(y1[3]) &&
+                  isfinite(y1[4]) && y1[3] >= 0.0 && y1[3] < 1.0 && y1[1] > 0.0))
+                return dp5::FAIL;
+        } else if (!before_lso(y1[0], y1[1], y1[2], y1[3], y1[4], Ms, &x13)) {
+            *kw = s.node - 1;            // past the LSO before node s.node
+            return dp5::END;
+        }
+        const Rhs f1 = back ? ak_rhs(y1[1], y1[3], Ms, mus, a, cl)
+                            : ak_rhs_x(y1[1], x13, y1[3], Ms, mus, a, cl);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) s.Y[i] = y1[i];
+        s.f = f1;
+        s.t = land ? tn : s.t + Hs;
+        if (land) {
+            double* q = o + s.node * 10;
+            q[0] = y1[0]; q[1] = y1[1]; q[2] = y1[2]; q[3] = y1[3]; q[4] = y1[4];
+            q[5] = f1.dPhi; q[6] = f1.dnu; q[7] = f1.dgt; q[8] = f1.de; q[9] = f1.dal;
+            if (back ? s.node == 0 : s.node == K) {
+                *kw = K;
+                return dp5::END;
+            }
+            s.node += back ? -1 : 1;
+        }
+        s.H = Hs * fmin(s.rej ? 1.0 : dp5::kFacMax, fac);
+        s.rej = 0;
+    }
+    return dp5::GO;
+}
+}  // namespace rk78
+
 // The orbit kernels run a few waves for the whole batch (one lane, or for
 // the adaptive integrator one wave, per walker) beside the table and
 // synthesis kernels of earlier segments: they raise their waves' issue
@@ -515,8 +647,8 @@ __device__ __forceinline__ void walker_setup(const double* __restrict__ params, 
         double* q = o + K * 10;
         q[0] = p[5]; q[1] = nuL; q[2] = p[6]; q[3] = e0; q[4] = p[7];
         q[5] = f.dPhi; q[6] = f.dnu; q[7] = f.dgt; q[8] = f.de; q[9] = f.dal;
-        if constexpr (ODE == EMRI_ODE_DP5) {
-            // the integration itself is k_orbit_dp5's (one wave per walker)
+        if constexpr (ODE != EMRI_ODE_RK4) {
+            // the integration itself is k_orbit_dp5's or k_orbit_rk78's
             dp5::save(dp5::State{(double)K * h, -h, {p[5], nuL, p[6], e0, p[7]}, f, K - 1, 0, 0},
                       c);
             c[WC_ODONE] = 0.0;
@@ -536,7 +668,7 @@ __device__ __forceinline__ void walker_setup(const double* __restrict__ params, 
     Rhs f = ak_rhs(Y1, Y3, Ms, mus, a, cl);
     o[0] = Y0; o[1] = Y1; o[2] = Y2; o[3] = Y3; o[4] = Y4;
     o[5] = f.dPhi; o[6] = f.dnu; o[7] = f.dgt; o[8] = f.de; o[9] = f.dal;
-    if constexpr (ODE == EMRI_ODE_DP5) {
+    if constexpr (ODE != EMRI_ODE_RK4) {
         dp5::save(dp5::State{0.0, h, {Y0, Y1, Y2, Y3, Y4}, f, 1, 0, 0}, c);
         c[WC_ODONE] = 0.0;
         c[WC_VALID] = 1.0;
@@ -559,13 +691,13 @@ __global__ void __launch_bounds__(64) k_walker_setup(const double* __restrict__ 
     walker_setup<EMRI_ODE_RK4>(params, B, K, h, Ndt, gl, k1, ic, wc, orb);
 }
 
-// constants and the adaptive integrator's starting state (one lane per
-// walker); the integration is k_orbit_dp5's
-__global__ void __launch_bounds__(64) k_walker_setup_dp5(const double* __restrict__ params,
-                                                         int64_t B, int64_t K, double h,
-                                                         double Ndt, GL8 gl, int ic,
-                                                         double* __restrict__ wc,
-                                                         double* __restrict__ orb)
+// constants and an adaptive integrator's starting state (one lane per
+// walker); the integration is k_orbit_dp5's or k_orbit_rk78's
+__global__ void __launch_bounds__(64) k_walker_setup_adaptive(const double* __restrict__ params,
+                                                              int64_t B, int64_t K, double h,
+                                                              double Ndt, GL8 gl, int ic,
+                                                              double* __restrict__ wc,
+                                                              double* __restrict__ orb)
 {
     walker_setup<EMRI_ODE_DP5>(params, B, K, h, Ndt, gl, K, ic, wc, orb);
 }
@@ -597,6 +729,30 @@ k_orbit_dp5(int64_t K, double h, int64_t k1, int seg, int back, double rtol, dou
                                c[WC_A], c[WC_CL], orb + w * (K + 1) * 10, &kw,
                                dense + threadIdx.x);
     if (threadIdx.x == 0) dp5::finish_segment(r, st, kw, seg, back != 0, K, c);
+}
+
+// seventh-order orbit segment seg: one lane per walker continues from the
+// saved integrator state until node k1 is filled (backward: down to node
+// k1), so the step sequence does not depend on where the segments end
+__global__ void __launch_bounds__(64) k_orbit_rk78(int64_t B, int64_t K, double h, int64_t k1,
+                                                   int seg, int back, double rtol, double atol,
+                                                   double* __restrict__ wc,
+                                                   double* __restrict__ orb)
+{
+    __builtin_amdgcn_s_setprio(3);
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= B) return;
+    double* c = wc + w * WC;
+    if (c[WC_VALID] == 0.0) return;
+    if (c[WC_ODONE] != 0.0) {
+        c[WC_KSEG + seg] = c[WC_KW];
+        return;
+    }
+    dp5::State st = dp5::load(c);
+    int64_t kw = -1;
+    const int r = rk78::advance(st, k1, K, h, back != 0, rtol, atol, c[WC_MS], c[WC_MUS],
+                                c[WC_A], c[WC_CL], orb + w * (K + 1) * 10, &kw);
+    dp5::finish_segment(r, st, kw, seg, back != 0, K, c);
 }
 
 // backward orbit segment seg >= 1 (RK4, from the LSO): steps from node k0
@@ -921,12 +1077,16 @@ hipError_t launch_walker_setup(const Plan& p, const double* params, int64_t B, v
     const double h = p.dt * (double)p.L;
     dim3 grid((unsigned)((B + 63) / 64));
     trace_mark(ST_SETUP, s, true);
-    if (p.ode == EMRI_ODE_DP5) {
-        hipLaunchKernelGGL(k_walker_setup_dp5, grid, dim3(64), 0, s, params, B, p.K, h,
+    if (p.ode == EMRI_ODE_DP5 || p.ode == EMRI_ODE_RK78) {
+        hipLaunchKernelGGL(k_walker_setup_adaptive, grid, dim3(64), 0, s, params, B, p.K, h,
                            (double)p.N * p.dt, gl, p.ic, (double*)(base + p.off_wc),
                            (double*)(base + p.off_orb));
-        if (B > 0)
+        if (B > 0 && p.ode == EMRI_ODE_DP5)
             hipLaunchKernelGGL(k_orbit_dp5, dim3((unsigned)B), dim3(64), 0, s, p.K, h, k1, 0,
+                               back ? 1 : 0, p.rtol, p.atol, (double*)(base + p.off_wc),
+                               (double*)(base + p.off_orb));
+        if (B > 0 && p.ode == EMRI_ODE_RK78)
+            hipLaunchKernelGGL(k_orbit_rk78, grid, dim3(64), 0, s, B, p.K, h, k1, 0,
                                back ? 1 : 0, p.rtol, p.atol, (double*)(base + p.off_wc),
                                (double*)(base + p.off_orb));
     } else
@@ -955,6 +1115,11 @@ hipError_t launch_walker_resume(const Plan& p, int64_t B, void* ws, int64_t k0, 
             hipLaunchKernelGGL(k_orbit_dp5, dim3((unsigned)B), dim3(64), 0, s, p.K, h, k1, seg,
                                back ? 1 : 0, p.rtol, p.atol, (double*)(base + p.off_wc),
                                (double*)(base + p.off_orb));
+    } else if (p.ode == EMRI_ODE_RK78) {
+        if (B > 0)
+            hipLaunchKernelGGL(k_orbit_rk78, grid, dim3(64), 0, s, B, p.K, h, k1, seg,
+                               back ? 1 : 0, p.rtol, p.atol, (double*)(base + p.off_wc),
+                               (double*)(base + p.off_orb));
     } else if (back) {
         hipLaunchKernelGGL(k_walker_resume_back, grid, dim3(64), 0, s, B, p.K, h, k0, k1, seg,
                            (double*)(base + p.off_wc), (double*)(base + p.off_orb));
@@ -963,6 +1128,36 @@ hipError_t launch_walker_resume(const Plan& p, int64_t B, void* ws, int64_t k0, 
                            (double*)(base + p.off_wc), (double*)(base + p.off_orb));
     }
     trace_mark(ST_SETUP, s, false);
+    return hipGetLastError();
+}
+
+// one lane per (walker, node)
+__global__ void __launch_bounds__(256) k_orbit_out(int64_t B, int64_t K,
+                                                   const double* __restrict__ wc,
+                                                   const double* __restrict__ src,
+                                                   double* __restrict__ dst, int32_t* __restrict__ kw)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B * (K + 1)) return;
+    const int64_t w = i / (K + 1), k = i - w * (K + 1);
+    const double* c = wc + w * WC;
+    const int64_t last = (c[WC_VALID] != 0.0) ? (int64_t)c[WC_KW] : -1;
+    const double* q = src + i * 10;
+    double* o = dst + i * 10;
+#pragma unroll
+    for (int j = 0; j < 10; ++j) o[j] = (k <= last) ? q[j] : 0.0;
+    if (k == 0) kw[w] = (int32_t)last;
+}
+
+hipError_t launch_orbit_out(const Plan& p, int64_t B, const void* ws, double* orb, int32_t* kw,
+                            hipStream_t s)
+{
+    const char* base = (const char*)ws;
+    const int64_t n = B * (p.K + 1);
+    if (n > 0)
+        hipLaunchKernelGGL(k_orbit_out, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, B,
+                           p.K, (const double*)(base + p.off_wc),
+                           (const double*)(base + p.off_orb), orb, kw);
     return hipGetLastError();
 }
 

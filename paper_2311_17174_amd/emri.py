@@ -8,6 +8,7 @@ Importing it loads the library and fails loudly if it has not been built
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from dataclasses import dataclass
 
@@ -24,8 +25,9 @@ IC_START = 0     # initial conditions at t = 0
 IC_LSO = 1       # at the last stable orbit, integrated backward (the paper's convention)
 ODE_RK4 = 0      # classical RK4 on the coarse nodes
 ODE_DP5 = 1      # adaptive Dormand-Prince 5(4), continuous extension at the nodes
+ODE_RK78 = 2     # adaptive Fehlberg 7(8), order 7 kept, stepped node to node
 
-EXPORTED = ("emri_abi_version", "emri_last_error", "emri_workspace_bytes",
+EXPORTED = ("emri_abi_version", "emri_last_error", "emri_workspace_bytes", "emri_orbit_batch",
             "emri_waveform_batch", "emri_fft_batch", "emri_loglike_batch",
             "emri_dataset_bytes", "emri_dataset_init", "emri_loglike_dataset",
             "emri_model_batch", "emri_noise_psd", "emri_trace_enable", "emri_trace_read",
@@ -86,7 +88,7 @@ class Config:
     precision: int = FP64
     coarse_log2: int = 10
     ic: int = IC_START       # IC_LSO: the row's orbital state is at the LSO
-    ode: int = ODE_RK4       # ODE_DP5: adaptive integrator with the tolerances below
+    ode: int = ODE_RK4       # ODE_DP5, ODE_RK78: adaptive integrators with the tolerances below
     ode_rtol: float = 1e-12
     ode_atol: float = 1e-12
 
@@ -99,6 +101,13 @@ class Config:
         return _Cfg(float(self.T_obs), float(self.dt), int(self.N), int(self.n_harm),
                     int(self.precision), int(self.coarse_log2), int(self.ic), int(self.ode), 0,
                     float(self.ode_rtol), float(self.ode_atol))
+
+    @property
+    def n_intervals(self) -> int:
+        """K = ceil(N_valid / 2^coarse_log2), N_valid = round(T_obs / dt)."""
+        nv = int(math.floor(self.T_obs / self.dt + 0.5))      # llround, as the library
+        m = 1 << int(self.coarse_log2)
+        return (nv + m - 1) // m
 
     @property
     def real_dtype(self) -> torch.dtype:
@@ -119,6 +128,7 @@ def _load():
         "emri_workspace_bytes": ([cp, i64], sz),
         "emri_dataset_bytes": ([cp], sz),
         "emri_waveform_batch": ([vp, i64, cp, vp, vp, sz, vp], ctypes.c_int),
+        "emri_orbit_batch": ([vp, i64, cp, vp, vp, vp, sz, vp], ctypes.c_int),
         "emri_fft_batch": ([vp, i64, cp, vp, vp, sz, vp], ctypes.c_int),
         "emri_loglike_batch": ([vp, i64, vp, vp, d, d, cp, vp, vp, sz, vp], ctypes.c_int),
         "emri_dataset_init": ([vp, vp, cp, vp, sz, vp], ctypes.c_int),
@@ -227,6 +237,22 @@ def dataset_bytes(cfg: Config) -> int:
 def alloc_workspace(cfg: Config, B: int, device="cuda", with_dataset: bool = False):
     n = workspace_bytes(cfg, B) + (dataset_bytes(cfg) + 256 if with_dataset else 0)
     return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def orbit_batch(params: torch.Tensor, cfg: Config, ws: torch.Tensor | None = None,
+                stream=None) -> tuple[torch.Tensor, torch.Tensor]:
+    """([B][K+1][10] fp64 orbit nodes: state then derivative, [B] int32 K_w)."""
+    B = params.shape[0]
+    pp = _dev(params, torch.float64, (B, NPAR), "params")
+    K = cfg.n_intervals
+    orb = torch.empty((B, K + 1, 10), dtype=torch.float64, device=params.device)
+    kw = torch.empty(B, dtype=torch.int32, device=params.device)
+    if ws is None:
+        ws = alloc_workspace(cfg, B, params.device)
+    c = cfg.c()
+    _check(lib.emri_orbit_batch(pp, B, ctypes.byref(c), orb.data_ptr(), kw.data_ptr(),
+                                ws.data_ptr(), ws.numel(), _stream(stream)), "emri_orbit_batch")
+    return orb, kw
 
 
 def waveform_batch(params: torch.Tensor, cfg: Config, out: torch.Tensor | None = None,

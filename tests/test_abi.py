@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol(E):
     missing = [n for n in declared_functions() if n not in exported]
     assert not missing, missing
     assert set(E.EXPORTED) == set(declared_functions())
-    assert E.lib.emri_abi_version() == 7
+    assert E.lib.emri_abi_version() == 8
 
 
 def test_struct_layout_matches_header(E):
@@ -56,10 +56,11 @@ def test_struct_layout_matches_header(E):
 @pytest.mark.parametrize("bad", [
     dict(N=3 << 12), dict(N=1 << 11), dict(N=1 << 25), dict(dt=0.0), dict(T_obs=-1.0),
     dict(n_harm=0), dict(n_harm=65), dict(precision=2), dict(coarse_log2=7),
-    dict(coarse_log2=13), dict(T_obs=1e7), dict(ode=2), dict(ode=-1),
+    dict(coarse_log2=13), dict(T_obs=1e7), dict(ode=3), dict(ode=-1),
     dict(ode=1, ode_rtol=0.0), dict(ode=1, ode_rtol=1e-14), dict(ode=1, ode_rtol=1e-2),
     dict(ode=1, ode_rtol=float("nan")), dict(ode=1, ode_atol=-1e-12),
-    dict(ode=1, ode_atol=float("inf")),
+    dict(ode=1, ode_atol=float("inf")), dict(ode=2, ode_rtol=1e-14),
+    dict(ode=2, ode_atol=float("nan")),
 ])
 def test_invalid_configurations_are_rejected(E, bad):
     base = dict(T_obs=2.5 * 86400, dt=10.0, N=1 << 15, n_harm=8, precision=0, coarse_log2=10)

@@ -117,6 +117,18 @@ def test_call_errors_without_launch(E):
     rc = E.lib.emri_waveform_batch(ctypes.c_void_p(8), 4, ctypes.byref(cc), ctypes.c_void_p(8),
                                    ctypes.c_void_p(8), 16, None)
     assert rc == -2
+    # the orbit alone: the same checks (null outputs, small workspace, B = 0)
+    rc = E.lib.emri_orbit_batch(ctypes.c_void_p(8), 4, ctypes.byref(cc), None, None,
+                                ctypes.c_void_p(8), 1 << 30, None)
+    assert rc == -1 and b"null" in E.lib.emri_last_error()
+    rc = E.lib.emri_orbit_batch(ctypes.c_void_p(8), 4, ctypes.byref(cc), ctypes.c_void_p(8),
+                                ctypes.c_void_p(8), ctypes.c_void_p(8), 16, None)
+    assert rc == -2
+    assert E.lib.emri_orbit_batch(None, 0, ctypes.byref(cc), None, None, None, 0, None) == 0
+    bad = E.Config.from_workload(W.small().with_(ode=2, ode_rtol=1e-2, ode_atol=1e-12)).c()
+    rc = E.lib.emri_orbit_batch(ctypes.c_void_p(8), 4, ctypes.byref(bad), ctypes.c_void_p(8),
+                                ctypes.c_void_p(8), ctypes.c_void_p(8), 1 << 30, None)
+    assert rc == -1 and b"tolerances" in E.lib.emri_last_error()
 
 
 def test_workspace_sizes_are_consistent(E):

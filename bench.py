@@ -54,8 +54,9 @@ def stage_work(stage: str, B: int, w, esz: int, valid_samples: int):
     if stage == "fft_rows":
         return "byte", 2 * B * N * esz
     if stage == "inner_product":
-        half = N // 2
-        dsz = 2 * half * esz + half * (8 if esz == 16 else 4)  # data + weights, once
+        # the column-transformed signal, and the per-bin data and weight
+        # arrays once (every bin of the packed spectrum)
+        dsz = N * esz + N * (8 if esz == 16 else 4)
         return "byte", B * N * esz + dsz
     return None, 0
 

@@ -246,8 +246,11 @@ emri_status emri_loglike_batch(const double* params, int64_t B, const double* da
 
 /* Resident data sets for repeated likelihood calls (the serving loop).
  * emri_dataset_init writes, into the caller's buffer `ds`, the data and
- * noise weights in the order the likelihood kernels read them (and, for
- * EMRI_MIXED, whitened FP32 copies and the FP64 data norm).  The buffer is
+ * noise weights in the orders the likelihood kernels read them: per bin of
+ * the packed two-channel spectrum, the data combined with the square root
+ * of half the weight (so that each bin enters on its own), and per positive
+ * frequency the data and weights as given (the frequency-dependent pass);
+ * FP32 copies for EMRI_MIXED; and the FP64 data norm <d|d>.  The buffer is
  * valid for the cfg it was made with (same N, dt, precision). */
 size_t emri_dataset_bytes(const emri_cfg* cfg);
 emri_status emri_dataset_init(const double* data, const double* psd, const emri_cfg* cfg,

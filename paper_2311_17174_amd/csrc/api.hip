@@ -213,6 +213,8 @@ emri_status make_plan(const emri_cfg* cfg, int64_t B, const Tuning& tn, Plan* p,
     const int64_t half = q.N / 2;
     q.ds_off_d = d; d += align256((size_t)2 * half * q.esz);
     q.ds_off_w = d; d += align256((size_t)half * (q.prec == EMRI_FP64 ? 8 : 4));
+    q.ds_off_q = d; d += align256((size_t)q.N * q.esz);
+    q.ds_off_v = d; d += align256((size_t)q.N * (q.prec == EMRI_FP64 ? 8 : 4));
     q.ds_off_norm = d; d += 256;
     q.ds_off_npart = d; d += align256((size_t)kNormParts * 8);
     q.ds_total = d;

@@ -15,7 +15,8 @@
 //           2 A J_n(ne) (4 coefficients each)
 //   z       [B][N] complex: packed signal h_I + i h_II; the FFT runs in
 //           place and leaves the spectrum in transposed order
-//   part    [B][R2/2+1] fp64 per-row-pair partial sums of the likelihood
+//   part    [B][R2] fp64 partial sums of the likelihood, per row (or per row
+//           pair in the frequency-dependent pass)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -110,7 +111,7 @@ struct Plan {
     int64_t B;
     size_t off_tw, off_wc, off_orb, off_nv, off_co, off_az, off_ch, off_hb, off_hx, off_z, off_part, total;
     // dataset buffer
-    size_t ds_off_d, ds_off_w, ds_off_norm, ds_off_npart, ds_total;
+    size_t ds_off_d, ds_off_w, ds_off_q, ds_off_v, ds_off_norm, ds_off_npart, ds_total;
 };
 
 // fills p with the overrides tn; returns EMRI_OK or an error (message in err)

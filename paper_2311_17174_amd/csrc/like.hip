@@ -4,23 +4,31 @@
 // m_k = g dt exp(-2 pi i k phi) X_k,  g = 1/(Xi d_L), phi = Delta T/(N dt),
 // where X is the unnormalised DFT of each channel (Eq. (8) with Eqs. (4)-(6)).
 //
-// The FFT leaves the packed spectrum in transposed order z[k2 R1 + k1] =
-// Z[k2 + R2 k1].  The lower bins k = k2 + R2 k1 < N/2 are exactly those with
-// k1 < R1/2; bin k pairs with N - k, which sits in row (R2 - k2) mod R2.  The
-// data set stores data and weights at index b = k2 (R1/2) + k1, so every
-// stream is read contiguously.
+// The FFT leaves the packed spectrum Z = X_I + i X_II in transposed order
+// z[k2 R1 + k1] = Z[k2 + R2 k1].  The channels of bin k come from Z_k and
+// Z_{N-k} (X_I = (Z_k + conj Z_{N-k})/2, X_II = (Z_k - conj Z_{N-k})/(2i)),
+// but the likelihood needs them only in sums over k, and there
+//   |X_I|^2 + |X_II|^2 = (|Z_k|^2 + |Z_{N-k}|^2) / 2,
+// while the data term is linear in Z_k and conj Z_{N-k}: every packed bin j
+// can be weighed on its own against a data array that folds both channels
+// (k_dataset_bins).  So lnL = -<d|d>/2 + sum_j [Re(x_j q_j) - |x_j|^2 / 2]
+// with x_j = (g dt) sqrt(v_j) P_j Z_j, over all bins j of the row-wise pass
+// (k_row_like), and <d|d> formed once in FP64 from the FP64 data.
+// FP64 path: the sums in FP64.  Mixed path: FP32 per-bin arrays and FP32
+// lane sums with Kahan compensation, FP64 across lanes.
 //
-// FP64 path: sum of w |d - m|^2 in FP64.
-// Mixed path: whitened FP32 data d^ = d sqrt(w) and weights sqrt(w); per bin
-// Re(conj(d^) m^) and |m^|^2 with m^ = sqrt(w) m, in FP32 with Kahan
-// compensation per lane, FP64 across lanes; lnL = -<d|d>/2 + <d|m> - <m|m>/2
-// with <d|d> formed once in FP64 from the FP64 data.
+// The row FFT of the second pass is fused here: one workgroup per (row,
+// tile of walkers) transforms the row in registers and LDS and consumes its
+// bins directly, so the spectrum is never written to HBM.  Each (row,
+// walker) gives one FP64 partial; a second kernel sums each walker's
+// partials in a fixed order (results do not depend on how walkers are
+// batched).
 //
-// The row FFT of the second pass is fused here: one workgroup per (pair of
-// rows, tile of walkers) transforms both rows in LDS and consumes the bins
-// directly, so the spectrum is never written to HBM.  Each (pair, walker)
-// gives one FP64 partial; a second kernel sums each walker's partials in a
-// fixed order (results do not depend on how walkers are batched).
+// The frequency-dependent propagation keeps the paired pass (k_rows_like,
+// k_rows_like16): its per-bin factor costs a power series and three
+// transcendentals, which the pairing of bin k with N - k evaluates once for
+// both.  The data set stores data and weights for it at index
+// b = k2 (R1/2) + k1 (bins below N/2, which are those with k1 < R1/2).
 #include "fft_lds.hpp"
 
 namespace emri {
@@ -54,6 +62,41 @@ __global__ void k_dataset(const double* __restrict__ data, const double* __restr
         D[half + b] = float2{(float)(d1r * sw), (float)(d1i * sw)};
         ((float*)dsw)[b] = (float)sw;
     }
+}
+
+// Per-bin arrays of the row-wise inner product, in the transform's output
+// order b = k2 R1 + k1 for the packed bin j = k2 + R2 k1 (j = 0 .. N-1):
+// with k = j below N/2 and k = N - j above it, and v = w_k / 2,
+//   s[b] = sqrt(v),
+//   q[b] = sqrt(v) (conj d_I(k) - i conj d_II(k))   (j < N/2)
+//          sqrt(v) (d_I(k) - i d_II(k))             (j > N/2),
+// zero at j = 0 and j = N/2.  For the packed spectrum Z = X_I + i X_II the
+// two channels' sums over bins 1..N/2-1 are then sums over all bins j:
+//   sum_k w_k (|X_I|^2 + |X_II|^2) = sum_j v_j |Z_j|^2,
+//   sum_k w_k Re(conj(d_I) P X_I + conj(d_II) P X_II) = sum_j Re(P_j Z_j q_j sqrt(v_j)),
+// with P_j the bin's propagation rotation (its conjugate above N/2), so that
+// every bin is used on its own, without the bin N - j it was packed with.
+template <typename R>
+__global__ void k_dataset_bins(const double* __restrict__ data, const double* __restrict__ psd,
+                               int64_t N, int64_t R1, int64_t R2, double df,
+                               typename C2<R>::T* __restrict__ q, R* __restrict__ sv)
+{
+    const int64_t H = N / 2 + 1, half = N / 2;
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= N) return;
+    const int64_t k2 = b / R1, k1 = b - k2 * R1;
+    const int64_t j = k2 + R2 * k1;
+    const int64_t k = j < half ? j : N - j;
+    const double S = psd[k];
+    const bool use = j != 0 && j != half && S > 0.0 && isfinite(S);
+    const double r = use ? sqrt(2.0 * df / S) : 0.0;     // sqrt(w_k / 2)
+    const double d0r = data[2 * k], d0i = data[2 * k + 1];
+    const double d1r = data[2 * (H + k)], d1i = data[2 * (H + k) + 1];
+    double qr, qi;
+    if (j < half) { qr = d0r - d1i; qi = -d0i - d1r; }
+    else { qr = d0r + d1i; qi = d0i - d1r; }
+    q[b] = typename C2<R>::T{(R)(r * qr), (R)(r * qi)};
+    sv[b] = (R)r;
 }
 
 __device__ inline double block_sum(double v, double* sh)
@@ -107,22 +150,27 @@ hipError_t launch_dataset(const Plan& p, const double* data, const double* psd, 
     const int64_t half = p.N / 2;
     const double df = 1.0 / ((double)p.N * p.dt);
     dim3 grid((unsigned)((half + 255) / 256));
+    const dim3 gridN((unsigned)((p.N + 255) / 256));
     trace_mark(ST_DATASET, s, true);
     if (p.prec == EMRI_FP64) {
         hipLaunchKernelGGL(k_dataset<false>, grid, dim3(256), 0, s, data, psd, p.N, p.R1, p.R2,
                            df, (void*)(b + p.ds_off_d), (void*)(b + p.ds_off_w));
+        hipLaunchKernelGGL(k_dataset_bins<double>, gridN, dim3(256), 0, s, data, psd, p.N, p.R1,
+                           p.R2, df, (double2*)(b + p.ds_off_q), (double*)(b + p.ds_off_v));
     } else {
         hipLaunchKernelGGL(k_dataset<true>, grid, dim3(256), 0, s, data, psd, p.N, p.R1, p.R2, df,
                            (void*)(b + p.ds_off_d), (void*)(b + p.ds_off_w));
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_data_norm_part, dim3(kNormParts), dim3(256), 0, s, data, psd, p.N,
-                           df, (double*)(b + p.ds_off_npart));
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_data_norm_sum, dim3(1), dim3(kNormParts), 0, s,
-                           (const double*)(b + p.ds_off_npart), (double*)(b + p.ds_off_norm));
+        hipLaunchKernelGGL(k_dataset_bins<float>, gridN, dim3(256), 0, s, data, psd, p.N, p.R1,
+                           p.R2, df, (float2*)(b + p.ds_off_q), (float*)(b + p.ds_off_v));
     }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_data_norm_part, dim3(kNormParts), dim3(256), 0, s, data, psd, p.N, df,
+                       (double*)(b + p.ds_off_npart));
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_data_norm_sum, dim3(1), dim3(kNormParts), 0, s,
+                       (const double*)(b + p.ds_off_npart), (double*)(b + p.ds_off_norm));
     trace_mark(ST_DATASET, s, false);
     return hipGetLastError();
 }
@@ -153,6 +201,41 @@ struct PropConst {
         if (!hasdt) return false;
         delay_rotation(k, phi, cr, ci);
         return true;
+    }
+};
+
+// Per-lane sums of the row-wise inner product: x = (scale sv) z,
+// cross += Re(x q), mm += |x|^2; the lane's value is cross - mm/2.
+template <typename R, bool MIXED> struct BinSum;
+template <typename R> struct BinSum<R, false> {
+    double cross = 0.0, mm = 0.0;
+    __device__ __forceinline__ void add(R zr, R zi, double scale, R sv,
+                                        const typename C2<R>::T& q)
+    {
+        const double f = scale * (double)sv;
+        const double xr = f * (double)zr, xi = f * (double)zi;
+        cross += xr * (double)q.x - xi * (double)q.y;
+        mm += xr * xr + xi * xi;
+    }
+    __device__ __forceinline__ double lane_sum() const { return cross - 0.5 * mm; }
+};
+template <typename R> struct BinSum<R, true> {
+    float cr_s = 0.f, cr_c = 0.f, mm_s = 0.f, mm_c = 0.f;   // Kahan sums
+    __device__ __forceinline__ void add(R zr, R zi, double scale, R sv,
+                                        const typename C2<R>::T& q)
+    {
+        const float f = (float)scale * (float)sv;
+        const float xr = f * (float)zr, xi = f * (float)zi;
+        const float cross = xr * (float)q.x - xi * (float)q.y;
+        const float mm = xr * xr + xi * xi;
+        float y = cross - cr_c, u = cr_s + y;
+        cr_c = (u - cr_s) - y; cr_s = u;
+        y = mm - mm_c; u = mm_s + y;
+        mm_c = (u - mm_s) - y; mm_s = u;
+    }
+    __device__ __forceinline__ double lane_sum() const
+    {
+        return ((double)cr_s - (double)cr_c) - 0.5 * ((double)mm_s - (double)mm_c);
     }
 };
 
@@ -527,6 +610,87 @@ k_rows_like16(const typename C2<R>::T* __restrict__ z, int64_t N, int L, int lgL
     }
 }
 
+// Fused pass B + inner product, one row at a time: one workgroup per (row
+// g, tile of walkers), L/E lanes with E values each (E = 8: radix-8 stages,
+// the first and last in registers; E = 16: radix-16 stages, two LDS
+// exchanges; FP64 at E = 16 takes up to 256 VGPRs, two waves per SIMD).  After the row's transform lane t holds its bins in
+// registers and consumes them with the per-bin arrays of k_dataset_bins, so
+// no bin waits for the one it was packed with and rows are independent.
+// Per bin j: x = (g dt sqrt(v_j)) P_j Z_j; the lane sums Re(x q_j) and |x|^2
+// (FP64, or FP32 with Kahan compensation in the mixed path); one FP64
+// partial sum(Re(x q)) - sum(|x|^2)/2 per (row, walker); the walker sum adds
+// -<d|d>/2.  The walker tiles of a row run together on one XCD, so the
+// row's per-bin arrays are read from HBM once.
+template <typename R, bool MIXED, int E, int MAXT>
+__global__ void __launch_bounds__(MAXT)
+__attribute__((amdgpu_waves_per_eu((sizeof(R) == 8 && E == 16) ? 2 : 4)))
+k_row_like(const typename C2<R>::T* __restrict__ z, int64_t N, int L, int lgL, int64_t R2,
+           double dt, const double* __restrict__ wc, const typename C2<R>::T* __restrict__ Q,
+           const R* __restrict__ SV, const typename C2<R>::T* __restrict__ twL,
+           double* __restrict__ part, int64_t B, int WT)
+{
+    using T2 = typename C2<R>::T;
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ double sh[16];
+    R* sre = (R*)smem_raw;
+    R* sim = sre + padded_len<R>(L);
+    const int64_t ntiles = (B + WT - 1) / WT;
+    const int64_t lid = blockIdx.x >> 3;
+    const int64_t g = (int64_t)(blockIdx.x & 7) + 8 * (lid / ntiles);
+    const int64_t tile = lid % ntiles;
+    if (g >= R2) return;
+    const int t0 = threadIdx.x;
+    const int LE = L / E;
+    const int64_t half = N / 2;
+    const int RL = last_radix16(lgL);
+    const T2* Qr = Q + g * L;
+    const R* Sr = SV + g * L;
+
+    for (int wi = 0; wi < WT; ++wi) {
+        const int64_t w = tile * WT + wi;
+        if (w >= B) break;
+        int t = t0;
+        asm volatile("" : "+v"(t));
+        const double* c = wc + w * WC;
+        if (c[WC_VALID] == 0.0) {
+            if (t == 0) part[w * R2 + g] = 0.0;
+            continue;
+        }
+        const T2* zr = z + w * N + g * L;
+        R xr[E], xi[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const T2 v = zr[t + i * LE];
+            xr[i] = v.x;
+            xi[i] = v.y;
+        }
+        if constexpr (E == 8) fft_regs<R, true>(sre, sim, L, lgL, t, twL, xr, xi);
+        else fft16_regs<R>(sre, sim, L, lgL, t, twL, xr, xi);
+        const double scale = c[WC_G] * dt;
+        const bool hasdt = c[WC_HASDT] != 0.0;
+        const double phi = c[WC_PHI];
+        BinSum<R, MIXED> acc;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int p = t + (E == 8 ? i : slot_pos16(i, RL)) * LE;
+            R ar = xr[i], ai = xi[i];
+            if (hasdt) {
+                const int64_t j = g + R2 * (int64_t)p;
+                double cr, ci;
+                delay_rotation(j < half ? j : N - j, phi, &cr, &ci);
+                if (j > half) ci = -ci;
+                const R u = ar * (R)cr - ai * (R)ci;
+                ai = ar * (R)ci + ai * (R)cr;
+                ar = u;
+            }
+            acc.add(ar, ai, scale, Sr[p], Qr[p]);
+        }
+        const double s = block_sum(acc.lane_sum(), sh);
+        if (t == 0) part[w * R2 + g] = s;
+        // block_sum ends with a barrier: LDS may be overwritten by the next walker
+    }
+}
+
 // lnL[w] = base + sum_k2 part[w][k2] (fixed order), -inf for invalid walkers
 __global__ void __launch_bounds__(256) k_walker_sum(const double* __restrict__ part, int64_t R2,
                                                     const double* __restrict__ wc,
@@ -545,6 +709,11 @@ __global__ void __launch_bounds__(256) k_walker_sum(const double* __restrict__ p
     }
 }
 
+// values per lane of the FP64 row-wise pass: 16 (radix 16, 203 VGPRs, two
+// waves per SIMD) measured 5.16 ms at config 2 against 5.58 ms for 8
+// (radix 8, 128 VGPRs, four waves per SIMD)
+constexpr int kRowE64 = 16;
+
 hipError_t launch_likelihood(const Plan& p, int64_t B, const void* ds, void* ws, double* lnL,
                              const FmgArgs* fmg, hipStream_t s)
 {
@@ -556,13 +725,51 @@ hipError_t launch_likelihood(const Plan& p, int64_t B, const void* ds, void* ws,
     int WT = (B >= 128) ? 8 : (B >= 16 ? 4 : 1);
     if (p.tn.like_walkers_per_wg >= 1 && p.tn.like_walkers_per_wg <= 32)
         WT = p.tn.like_walkers_per_wg;
+    const TwLayout tl = tw_layout(p);
+    const char* twb = base + p.off_tw;
+    const double* norm = (const double*)(db + p.ds_off_norm);
+    if (!fmg) {
+        // constant propagation: the row-wise pass
+        const bool f64 = p.prec == EMRI_FP64;
+        const int E = f64 ? kRowE64 : 16;
+        if (L / E > 512 || L / E < 8) return hipErrorInvalidValue;
+        const void* kern = f64 ? (E == 8 ? (const void*)k_row_like<double, false, 8, 512>
+                                         : (const void*)k_row_like<double, false, 16, 256>)
+                               : (const void*)k_row_like<float, true, 16, 256>;
+        const size_t lds = f64 ? (size_t)padded_len<double>(L) * 2 * 8
+                               : (size_t)padded_len<float>(L) * 2 * 4;
+        hipError_t ae = allow_lds(kern, lds);
+        if (ae != hipSuccess) return ae;
+        const int64_t ntiles = (B + WT - 1) / WT;
+        const dim3 grid((unsigned)(((p.R2 + 7) / 8) * 8 * ntiles));
+        const void* a_z = (const void*)(base + p.off_z);
+        int64_t a_N = p.N, a_R2 = p.R2, a_B = B;
+        int a_L = L, a_lgL = p.m1, a_WT = WT;
+        double a_dt = p.dt;
+        const double* a_wc = wc;
+        const void* a_q = (const void*)(db + p.ds_off_q);
+        const void* a_v = (const void*)(db + p.ds_off_v);
+        const void* a_tw = (const void*)(twb + (f64 ? tl.oB : tl.fB));
+        double* a_part = part;
+        void* args[] = {&a_z, &a_N, &a_L, &a_lgL, &a_R2, &a_dt, &a_wc, &a_q, &a_v, &a_tw,
+                        &a_part, &a_B, &a_WT};
+        trace_mark(ST_LIKE, s, true);
+        ae = hipLaunchKernel(kern, grid, dim3((unsigned)(L / E)), args, lds, s);
+        trace_mark(ST_LIKE, s, false);
+        if (ae != hipSuccess) return ae;
+        ae = hipGetLastError();
+        if (ae != hipSuccess) return ae;
+        trace_mark(ST_WALKER_SUM, s, true);
+        hipLaunchKernelGGL(k_walker_sum, dim3((unsigned)B), dim3(256), 0, s, part, p.R2, wc,
+                           norm, lnL);
+        trace_mark(ST_WALKER_SUM, s, false);
+        return hipGetLastError();
+    }
     const size_t lds = (p.prec == EMRI_FP64) ? (size_t)padded_len<double>(L) * 2 * 8
                                              : (size_t)padded_len<float>(L) * 2 * 4;
     const int64_t nparts = p.R2 / 2 + 1;
     const int64_t ntiles = (B + WT - 1) / WT;
     dim3 grid((unsigned)(((nparts + 7) / 8) * 8 * ntiles));
-    const TwLayout tl = tw_layout(p);
-    const char* twb = base + p.off_tw;
     // FP32 rows take 16 values per lane; FP64 keeps 8: two rows of 16 FP64
     // values do not fit 128 registers
     const int E = (p.prec == EMRI_FP64) ? 8 : 16;
@@ -599,10 +806,10 @@ hipError_t launch_likelihood(const Plan& p, int64_t B, const void* ds, void* ws,
     if (ae != hipSuccess) return ae;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const double* norm = (p.prec == EMRI_FP64) ? nullptr : (const double*)(db + p.ds_off_norm);
+    // the paired pass sums w |d - m|^2 itself in FP64; the mixed one needs <d|d>
     trace_mark(ST_WALKER_SUM, s, true);
-    hipLaunchKernelGGL(k_walker_sum, dim3((unsigned)B), dim3(256), 0, s, part, nparts, wc, norm,
-                       lnL);
+    hipLaunchKernelGGL(k_walker_sum, dim3((unsigned)B), dim3(256), 0, s, part, nparts, wc,
+                       (p.prec == EMRI_FP64) ? nullptr : norm, lnL);
     trace_mark(ST_WALKER_SUM, s, false);
     return hipGetLastError();
 }

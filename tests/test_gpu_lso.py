@@ -141,3 +141,41 @@ def test_lso_config2_sampled_parity(E):
     rel = np.abs(got[idx] - ref) / np.abs(ref)
     say("rel err", rel)
     assert np.all(rel <= 1e-10)
+
+
+def test_config4_shaped_requests_match_the_oracle(E):
+    """The serving workload's own shape without the server: two of its chains
+    (state at the LSO, orbits integrated backward over the window), half a
+    year at dt = 10 s (2^21 samples), 30 harmonics, mixed precision, data
+    made by the oracle, requests of 3, 4, 2 and 3 walkers drawn as the bench
+    draws them, each evaluated on the resident data set.  Every walker:
+    relative lnL within 1e-4 and |dlnL| within 1e-5 <m|m> (the signal
+    scale).  (Served results equal these bitwise:
+    test_served_equals_alone_in_the_mix.)"""
+    chains = W.serving_chains()
+    sets = []
+    for c in (1, 6):
+        w = W.serving_workload(chains[c], 0)
+        d, S = oracle_dataset(w, True)
+        dd, ss = to_device_data(d, S)
+        cfg = E.Config.from_workload(w)
+        sets.append((w, cfg, d, S, E.dataset_init(dd, ss, cfg)))
+    reqs = [(0, 3, 21), (1, 4, 22), (0, 2, 23), (1, 3, 24)]
+    for k in range(len(sets)):
+        w, cfg, d, S, ds = sets[k]
+        mine = [i for i, r in enumerate(reqs) if r[0] == k]
+        P = np.concatenate([W.walkers(w, B=reqs[i][1], seed=reqs[i][2]) for i in mine])
+        say("config-4 shape, data set", k, "walkers", len(P))
+        r = O.loglike_sets(P, [d, np.zeros_like(d)], S, ocfg(w))
+        ref, mm = r[:, 0], -2.0 * r[:, 1]
+        at = 0
+        for i in mine:
+            n = reqs[i][1]
+            got = E.loglike_dataset(torch.from_numpy(P[at:at + n]).cuda(), ds, cfg).cpu().numpy()
+            fin = np.isfinite(ref[at:at + n])
+            assert np.array_equal(fin, np.isfinite(got))
+            err = np.abs(got[fin] - ref[at:at + n][fin])
+            say("request", i, "max |dlnL|/<m|m>", (err / mm[at:at + n][fin]).max())
+            assert np.all(err <= 1e-4 * np.abs(ref[at:at + n][fin]))
+            assert np.all(err <= 1e-5 * mm[at:at + n][fin])
+            at += n

@@ -35,12 +35,13 @@ FP32_VECTOR_TFLOPS = 157.3     # MI355X vector FP32 (published, packed)
 def synth_flops_per_sample(n_harm: int) -> int:
     """Algorithmic floating-point operations of one waveform sample (both
     channels), counted from the kernel's arithmetic: per harmonic three cubic
-    amplitude polynomials (3 x 6), three accumulations (3 x 2) and the complex
-    rotation to the next harmonic (6); per sample the four orbital Hermite
-    cubics (4 x 6), the azimuth rotation (12), the Doppler phase (6), three
-    sin/cos pairs (3 x 20, counted as 20 each), the orientation and detector
-    geometry with three double-angle pairs (~130) and the projection (14)."""
-    return 30 * n_harm + 24 + 12 + 6 + 60 + 130 + 14
+    amplitude polynomials (3 x 6), three accumulations (3 x 2) and the
+    three-term recurrence to the next harmonic's cos and sin (2 x 2); per
+    sample the four orbital Hermite cubics (4 x 6), the azimuth rotation
+    (12), the Doppler phase (6), three sin/cos pairs (3 x 20, counted as 20
+    each), the orientation and detector geometry with three double-angle
+    pairs (~130) and the projection (14)."""
+    return 28 * n_harm + 24 + 12 + 6 + 60 + 130 + 14
 
 
 def stage_work(stage: str, B: int, w, esz: int, valid_samples: int):

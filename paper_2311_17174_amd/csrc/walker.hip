@@ -1009,15 +1009,15 @@ __global__ void __launch_bounds__(256) k_tables(int64_t K, int nh, double h, int
 // a cubic's absolute coefficients, which bounds it over u in [0, 1]), the
 // harmonics past the last one whose bound reaches kTiny M are left out, and
 // the cubic terms are dropped when every harmonic's cubic coefficients are
-// below kTiny M.  kTiny = 2^-30 is under FP32 rounding (2^-24): past their
-// peak the Peters-Mathews amplitudes decay monotonically, so what is left
-// out stays within a few kTiny M.
+// below kTiny M.  kTiny = 2^-24 is FP32's unit roundoff: past their peak
+// the Peters-Mathews amplitudes decay monotonically, so what is left out
+// stays within a few kTiny M, the size of the FP32 sum's own rounding.
 __global__ void __launch_bounds__(256) k_harm_extent(int64_t K, int nh, int64_t k0, int64_t k1,
                                                      int seg, const double* __restrict__ wc,
                                                      const float2* __restrict__ hb,
                                                      int2* __restrict__ hx)
 {
-    constexpr float kTiny = 9.313225746154785e-10f;
+    constexpr float kTiny = 5.960464477539063e-08f;   // 2^-24
     const int64_t w = blockIdx.y;
     const int64_t k = k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= k1) return;

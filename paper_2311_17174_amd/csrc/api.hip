@@ -196,7 +196,6 @@ emri_status make_plan(const emri_cfg* cfg, int64_t B, const Tuning& tn, Plan* p,
     q.off_tw = o; o += align256(tl.bytes);
     q.off_wc = o; o += align256((size_t)B * WC * 8);
     q.off_orb = o; o += align256((size_t)B * (q.K + 1) * 10 * 8);
-    q.off_nv = o; o += align256((size_t)B * (q.K + 1) * q.nh * 6 * 8);
     q.off_co = o; o += align256((size_t)B * q.K * 16 * 8);
     q.off_az = o; o += align256((size_t)q.K * 16);
     q.off_ch = o; o += align256((size_t)B * q.K * q.nh * 12 * q.hsz);

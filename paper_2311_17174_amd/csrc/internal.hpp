@@ -109,7 +109,7 @@ struct Plan {
     size_t hsz;            // bytes per harmonic coefficient (8 or 4)
     // workspace (bytes, for B walkers)
     int64_t B;
-    size_t off_tw, off_wc, off_orb, off_nv, off_co, off_az, off_ch, off_hb, off_hx, off_z, off_part, total;
+    size_t off_tw, off_wc, off_orb, off_co, off_az, off_ch, off_hb, off_hx, off_z, off_part, total;
     // dataset buffer
     size_t ds_off_d, ds_off_w, ds_off_q, ds_off_v, ds_off_norm, ds_off_npart, ds_total;
 };

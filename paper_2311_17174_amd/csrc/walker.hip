@@ -11,12 +11,11 @@
 //                   continuous extension (one wave per walker), or by
 //                   Fehlberg's 7(8) pair stepped node to node (one lane per
 //                   walker)
-//  k_nodes          one lane per (walker, orbit node, harmonic): Bessel
-//                   functions of the Peters-Mathews amplitudes and their time
-//                   derivatives at the node
-//  k_tables         one lane per (walker, coarse interval, harmonic): the
-//                   node values folded into cubic Hermite polynomials in the
-//                   interval coordinate u
+//  k_amp_tables     one workgroup per (walker, range of coarse intervals,
+//                   group of harmonics): Bessel functions of the
+//                   Peters-Mathews amplitudes and their time derivatives at
+//                   the range's nodes (in LDS), folded into cubic Hermite
+//                   polynomials in the interval coordinate u
 #include "internal.hpp"
 
 #include <math.h>
@@ -838,41 +837,74 @@ __device__ void bessel7(int n, double X, double J[7])
         prod *= (2.0 * S - X) * iX;
     }
     S += S & 1;                       // even: J_S enters the norm
-    // a = J_q, b = J_{q+1} (unnormalised), dq = q; the order produced next,
-    // q - 1, enters the norm with weight m (2 for even orders, 0 for odd)
-    double a = 1e-280, b = 0.0, dq = (double)S, m = 0.0, norm = 2.0 * a;
+    // a = J_q, b = J_{q+1} (unnormalised), dq = q.  Orders are produced
+    // one step at a time, J_{q-1} = (2q/X) J_q - J_{q+1}; the even ones
+    // enter the norm with weight 2.  The steps run in pairs (odd order, then
+    // even), with the running scale checked once per pair: between checks
+    // the values grow by at most (2S/X)^2, which stays inside the FP64 range
+    // above the 1e150 threshold for X down to about 1e-75.
+    double a = 1e-280, b = 0.0, dq = (double)S, norm = 2.0 * a;
     double w[7] = {0, 0, 0, 0, 0, 0, 0};
     auto step = [&]() {
         const double next = (dq * iX2) * a - b;
         dq -= 1.0;
         b = a;
         a = next;
-        norm = fma(m, a, norm);
-        m = 2.0 - m;
     };
     auto rescale = [&]() {            // keep the values on the running scale
-        if (fabs(a) > 1e200) {
+        if (fabs(a) > 1e150) {
             const double r = 1e-200;
             a *= r; b *= r; norm *= r;
 #pragma unroll
             for (int k = 0; k < 7; ++k) w[k] *= r;
         }
     };
-    for (int q = S; q > hi; --q) {
+    // orders S-1 .. hi (S even): with an odd count the first step stands
+    // alone and the pairs run (even, odd), else they run (odd, even)
+    int q = S;
+    if ((S - hi) & 1) {
         step();
         rescale();
+        --q;
+#pragma unroll 1
+        for (; q > hi; q -= 2) {
+            step();
+            norm = fma(2.0, a, norm);
+            step();
+            rescale();
+        }
+    } else {
+#pragma unroll 1
+        for (; q > hi; q -= 2) {
+            step();
+            step();
+            norm = fma(2.0, a, norm);
+            rescale();
+        }
     }
     w[6] = a;                         // J_{n+3}
 #pragma unroll
     for (int i = 5; i >= 0; --i) {
         if (lo + i >= 0) {
             step();
+            norm = fma(((lo + i) & 1) ? 0.0 : 2.0, a, norm);
             w[i] = a;                 // J_{n-3+i}
             rescale();
         }
     }
-    for (int o = lo - 1; o >= 0; --o) {
+    // orders lo-1 .. 0
+    q = lo;
+    if (q > 0 && ((q - 1) & 1) == 0) {   // an even order first
         step();
+        norm = fma(2.0, a, norm);
+        rescale();
+        --q;
+    }
+#pragma unroll 1
+    for (; q >= 2; q -= 2) {
+        step();
+        step();
+        norm = fma(2.0, a, norm);
         rescale();
     }
     norm -= a;                        // a = J_0 was counted twice
@@ -922,56 +954,74 @@ __device__ inline void hermite_coeffs(double y0, double d0, double y1, double d1
     c[3] = 2.0 * (y0 - y1) + h * (d0 + d1);
 }
 
-// node values: for (walker, node k in [n0, n1), k <= K_w, harmonic n) the
-// three amplitudes A n P_n, A n Q_n, 2 A J_n(ne) and their time derivatives,
-// nv[w][k][n][6]
-__global__ void __launch_bounds__(256) k_nodes(int64_t K, int nh, int64_t n0, int64_t n1, int seg,
-                                               const double* __restrict__ wc,
-                                               const double* __restrict__ orb,
-                                               double* __restrict__ nv)
-{
-    const int64_t w = blockIdx.y;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (n1 - n0) * nh) return;
-    const double* c = wc + w * WC;
-    if (c[WC_VALID] == 0.0) return;
-    const int64_t k = n0 + t / nh;
-    const int n = (int)(t - (k - n0) * nh) + 1;
-    if (k > (int64_t)c[WC_KSEG + seg]) return;
-    const double* o = orb + (w * (K + 1) + k) * 10;
-    const double Ms = c[WC_MS], mus = c[WC_MUS];
-    const double nu = o[1], e = o[3], dnu = o[6], de = o[8];
-    const double x13 = cbrt(2.0 * kPi * Ms * nu);
-    const double A = x13 * x13 * mus;
-    const double dA = (2.0 / 3.0) * A * dnu / nu;
-    double J[7];
-    bessel7(n, n * e, J);
-    const PM pm = pm_amplitudes(n, e, J);
-    double* q = nv + ((w * (K + 1) + k) * nh + (n - 1)) * 6;
-    q[0] = A * pm.a; q[1] = dA * pm.a + A * pm.da * de;
-    q[2] = A * pm.b; q[3] = dA * pm.b + A * pm.db * de;
-    q[4] = A * pm.c; q[5] = dA * pm.c + A * pm.dc * de;
-}
+// amplitude tables, one workgroup per (walker, range of up to kTabI coarse
+// intervals of the segment, group of up to kTabH harmonics):
+//  1. the node values of the range's nodes -- the three amplitudes A n P_n,
+//     A n Q_n, 2 A J_n(ne) and their time derivatives -- go to LDS, one
+//     harmonic per wave of 64 nodes, so that every lane of a wave runs
+//     Miller's recurrence for the same order and the lanes' trip counts
+//     agree (one lane per (node, harmonic) with the harmonics fastest left
+//     most lanes of a wave idle behind the highest order);
+//  2. each lane folds the values at the ends of an interval into the
+//     power-basis Hermite cubics of (interval, harmonic), harmonics fastest,
+//     so a wave writes whole runs of the table; the n = 1 group also
+//     tabulates Phi, nu, gamma~, alpha.
+// A range's last node is its successor's first and is evaluated by both;
+// nothing passes between segments.
+constexpr int kTabNodes = 64;              // nodes per range
+constexpr int kTabI = kTabNodes - 1;       // intervals per range
+constexpr int kTabH = 16;                  // harmonics per group
+constexpr int kTabPad = kTabNodes + 1;     // LDS row (no bank conflicts in step 2)
 
-// interval tables: for (walker, interval k in [k0, k1), k < K_w, harmonic n) the power-basis
-// Hermite cubics of the three amplitudes, and (n = 1) of Phi, nu, gamma~, alpha
 template <typename HT>
-__global__ void __launch_bounds__(256) k_tables(int64_t K, int nh, double h, int64_t k0, int64_t k1,
-                                                int seg, const double* __restrict__ wc,
-                                                const double* __restrict__ orb,
-                                                const double* __restrict__ nv,
-                                                double* __restrict__ co, HT* __restrict__ ch,
-                                                float2* __restrict__ hb)
+__global__ void __launch_bounds__(256) k_amp_tables(int64_t K, int nh, double h, int64_t k0,
+                                                    int64_t k1, int seg,
+                                                    const double* __restrict__ wc,
+                                                    const double* __restrict__ orb,
+                                                    double* __restrict__ co,
+                                                    HT* __restrict__ ch,
+                                                    float2* __restrict__ hb)
 {
+    __shared__ double sv[6 * kTabH * kTabPad];   // [value][harmonic][node]
     const int64_t w = blockIdx.y;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (k1 - k0) * nh) return;
+    const int ng = (nh + kTabH - 1) / kTabH;
+    const int64_t r = blockIdx.x / ng;
+    const int grp = (int)(blockIdx.x - r * ng);
     const double* c = wc + w * WC;
     if (c[WC_VALID] == 0.0) return;
-    const int64_t k = k0 + t / nh;
-    const int n = (int)(t - (k - k0) * nh) + 1;
-    if (k >= (int64_t)c[WC_KSEG + seg]) return;
-    if (n == 1) {  // orbital interpolants: Phi, nu, gamma~, alpha
+    const int64_t kb = k0 + r * kTabI;                           // first interval
+    const int64_t ke = min(k1, (int64_t)c[WC_KSEG + seg]);       // intervals end (< K_w)
+    if (kb >= ke) return;                                         // uniform over the block
+    const int ni = (int)min((int64_t)kTabI, ke - kb);            // intervals of the range
+    const int n_lo = grp * kTabH + 1;
+    const int nhb = min(kTabH, nh - grp * kTabH);
+    const double Ms = c[WC_MS], mus = c[WC_MUS];
+
+    // 1. node values, node fastest
+    for (int p = threadIdx.x; p < kTabNodes * nhb; p += 256) {
+        const int hn = p / kTabNodes, i = p - hn * kTabNodes;
+        if (i > ni) continue;
+        const int n = n_lo + hn;
+        const double* o = orb + (w * (K + 1) + kb + i) * 10;
+        const double nu = o[1], e = o[3], dnu = o[6], de = o[8];
+        const double x13 = cbrt(2.0 * kPi * Ms * nu);
+        const double A = x13 * x13 * mus;
+        const double dA = (2.0 / 3.0) * A * dnu / nu;
+        double J[7];
+        bessel7(n, n * e, J);
+        const PM pm = pm_amplitudes(n, e, J);
+        double* q = sv + hn * kTabPad + i;
+        q[0 * kTabH * kTabPad] = A * pm.a;
+        q[1 * kTabH * kTabPad] = dA * pm.a + A * pm.da * de;
+        q[2 * kTabH * kTabPad] = A * pm.b;
+        q[3 * kTabH * kTabPad] = dA * pm.b + A * pm.db * de;
+        q[4 * kTabH * kTabPad] = A * pm.c;
+        q[5 * kTabH * kTabPad] = dA * pm.c + A * pm.dc * de;
+    }
+
+    // orbital interpolants of the range's intervals: Phi, nu, gamma~, alpha
+    if (grp == 0 && (int)threadIdx.x < ni) {
+        const int64_t k = kb + threadIdx.x;
         const double* o0 = orb + (w * (K + 1) + k) * 10;
         const double* o1 = o0 + 10;
         double* q = co + (w * K + k) * 16;
@@ -982,30 +1032,39 @@ __global__ void __launch_bounds__(256) k_tables(int64_t K, int nh, double h, int
             q[4 * i + 0] = cc[0]; q[4 * i + 1] = cc[1]; q[4 * i + 2] = cc[2]; q[4 * i + 3] = cc[3];
         }
     }
-    const double* v0 = nv + ((w * (K + 1) + k) * nh + (n - 1)) * 6;
-    const double* v1 = v0 + (int64_t)nh * 6;            // node k + 1, same n
-    HT* q = ch + ((w * K + k) * nh + (n - 1)) * 12;
-    float bnd = 0.f, c3 = 0.f;
-    for (int i = 0; i < 3; ++i) {
-        double cc[4];
-        hermite_coeffs(v0[2 * i], v0[2 * i + 1], v1[2 * i], v1[2 * i + 1], h, cc);
-        float sa = 0.f;
-        for (int j = 0; j < 4; ++j) {
-            q[4 * i + j] = (HT)cc[j];
-            sa += fabsf((float)(HT)cc[j]);
+    __syncthreads();
+
+    // 2. interval cubics, harmonic fastest
+    for (int p = threadIdx.x; p < ni * nhb; p += 256) {
+        const int i = p / nhb, hn = p - i * nhb;
+        const int64_t k = kb + i;
+        const int n = n_lo + hn;
+        const double* v = sv + hn * kTabPad + i;
+        HT* q = ch + ((w * K + k) * nh + (n - 1)) * 12;
+        float bnd = 0.f, c3 = 0.f;
+        for (int a = 0; a < 3; ++a) {
+            const double* y = v + 2 * a * kTabH * kTabPad;
+            const double* d = y + kTabH * kTabPad;
+            double cc[4];
+            hermite_coeffs(y[0], d[0], y[1], d[1], h, cc);
+            float sa = 0.f;
+            for (int j = 0; j < 4; ++j) {
+                q[4 * a + j] = (HT)cc[j];
+                sa += fabsf((float)(HT)cc[j]);
+            }
+            bnd = fmaxf(bnd, sa);
+            c3 = fmaxf(c3, fabsf((float)(HT)cc[3]));
         }
-        bnd = fmaxf(bnd, sa);
-        c3 = fmaxf(c3, fabsf((float)(HT)cc[3]));
+        // the amplitude bound over u in [0, 1] and the largest cubic
+        // coefficient of this harmonic, for the synthesis to leave out what
+        // cannot change an FP32 sum
+        if (hb) hb[(w * K + k) * nh + (n - 1)] = float2{bnd, c3};
     }
-    // the amplitude bound over u in [0, 1] and the largest cubic coefficient
-    // of this harmonic, for the synthesis to leave out what cannot change
-    // an FP32 sum
-    if (hb) hb[(w * K + k) * nh + (n - 1)] = float2{bnd, c3};
 }
 
 // FP32 synthesis: per (walker, interval) of the segment, the number of
 // harmonics to sum and whether the cubic amplitude terms matter.  With M the
-// largest amplitude bound of the interval's harmonics (k_tables: the sum of
+// largest amplitude bound of the interval's harmonics (k_amp_tables: the sum of
 // a cubic's absolute coefficients, which bounds it over u in [0, 1]), the
 // harmonics past the last one whose bound reaches kTiny M are left out, and
 // the cubic terms are dropped when every harmonic's cubic coefficients are
@@ -1169,27 +1228,18 @@ hipError_t launch_tables(const Plan& p, int64_t B, void* ws, int64_t k0, int64_t
     const double h = p.dt * (double)p.L;
     const double* wc = (const double*)(base + p.off_wc);
     const double* orb = (const double*)(base + p.off_orb);
-    double* nv = (double*)(base + p.off_nv);
     trace_mark(ST_TABLES, s, true);
-    // nodes k0 .. k1 of the intervals [k0, k1); a later segment's node k0
-    // (forward) or k1 (backward from the LSO) was the previous segment's last
-    const bool back = p.ic == EMRI_IC_LSO;
-    const int64_t n0 = (seg == 0 || back) ? k0 : k0 + 1;
-    const int64_t n1 = (seg == 0 || !back) ? k1 + 1 : k1;
-    const int64_t nn = (n1 - n0) * p.nh;
-    if (nn > 0)   // an empty segment has no nodes of its own
-        hipLaunchKernelGGL(k_nodes, dim3((unsigned)((nn + 255) / 256), (unsigned)B), dim3(256),
-                           0, s, p.K, p.nh, n0, n1, seg, wc, orb, nv);
-    const int64_t n = (k1 - k0) * p.nh;
-    dim3 grid((unsigned)((n + 255) / 256), (unsigned)B);
+    const int64_t n = k1 - k0;
     if (n > 0) {
+        const int ng = (p.nh + kTabH - 1) / kTabH;
+        const dim3 grid((unsigned)(((n + kTabI - 1) / kTabI) * ng), (unsigned)B);
         if (p.prec == EMRI_FP64) {
-            hipLaunchKernelGGL(k_tables<double>, grid, dim3(256), 0, s, p.K, p.nh, h, k0, k1, seg,
-                               wc, orb, nv, (double*)(base + p.off_co),
+            hipLaunchKernelGGL(k_amp_tables<double>, grid, dim3(256), 0, s, p.K, p.nh, h, k0, k1,
+                               seg, wc, orb, (double*)(base + p.off_co),
                                (double*)(base + p.off_ch), (float2*)nullptr);
         } else {
-            hipLaunchKernelGGL(k_tables<float>, grid, dim3(256), 0, s, p.K, p.nh, h, k0, k1, seg,
-                               wc, orb, nv, (double*)(base + p.off_co),
+            hipLaunchKernelGGL(k_amp_tables<float>, grid, dim3(256), 0, s, p.K, p.nh, h, k0, k1,
+                               seg, wc, orb, (double*)(base + p.off_co),
                                (float*)(base + p.off_ch), (float2*)(base + p.off_hb));
             if (hipPeekAtLastError() == hipSuccess)
                 hipLaunchKernelGGL(k_harm_extent,

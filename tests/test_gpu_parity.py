@@ -154,10 +154,14 @@ def _waveform_and_lnl(E, w, P):
 
 # the edges of the accepted configurations: every samples-per-lane variant of
 # the synthesis (coarse step 2^cl samples), the largest harmonic count, the
-# smallest transform (rows of 128 points, columns of 32)
+# smallest transform (rows of 128 points, columns of 32); and the amplitude
+# tables' blocking (ranges of 63 intervals, groups of 16 harmonics): 84
+# intervals with 17 harmonics (a full and a ragged range, a one-harmonic
+# group) and a single harmonic
 EDGE_CASES = [("cl9", dict(coarse_log2=9), {}), ("cl11", dict(coarse_log2=11), {}),
               ("cl12", dict(coarse_log2=12), {}), ("nh64", {}, dict(n_harm=64)),
-              ("N4096", {}, dict(days=0.4, N=1 << 12))]
+              ("N4096", {}, dict(days=0.4, N=1 << 12)),
+              ("cl8_nh17", dict(coarse_log2=8), dict(n_harm=17)), ("nh1", {}, dict(n_harm=1))]
 
 
 @pytest.mark.parametrize("case", EDGE_CASES, ids=[c[0] for c in EDGE_CASES])

@@ -1,10 +1,11 @@
 // synth.hip -- stage (b): time-domain AK waveform on the fine sampling grid.
 //
-// One workgroup of 256 lanes per (coarse interval k, walker w), over the
-// intervals [k0, k1) of one orbit segment; each lane
-// produces SPT = 2^coarse_log2 / 256 consecutive samples j = k 2^cl +
-// lane SPT + s.  Everything a wave needs from the orbit and the amplitude
-// tables is uniform over the interval and is read with scalar loads.  When
+// One workgroup of LANES lanes (256; 128 for FP32 at 2^10 samples per
+// interval) per (coarse interval k, walker w), over the intervals [k0, k1) of
+// one orbit segment; each lane produces SPT = 2^coarse_log2 / LANES
+// consecutive samples j = k 2^cl + lane SPT + s.  Everything a wave needs
+// from the orbit and the amplitude tables is uniform over the interval and is
+// read with scalar loads.  When
 // the phases advance by less than 0.25 rad per sample (checked per interval
 // from the Hermite coefficients), a lane evaluates sin/cos once and rotates
 // by small-angle factors for its next samples.
@@ -106,8 +107,8 @@ __device__ __forceinline__ void angle_run(const double (&a)[SPT], bool smooth, R
 // up to 4 samples per lane the register budget is capped at 128 (4 waves
 // per SIMD; a few spills outside the harmonic loop are cheaper than the
 // lost occupancy); longer runs keep their registers
-template <typename R, typename HT, int SPT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPT <= 4 ? 4 : 1)))
+template <typename R, typename HT, int SPT, int LANES>
+__global__ void __launch_bounds__(LANES) __attribute__((amdgpu_waves_per_eu(SPT <= 4 ? 4 : 1)))
 k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
                                                int64_t k0, int seg, int zfill,
                                                double dt, const double* __restrict__ wc,
@@ -118,7 +119,7 @@ k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
                                                typename V2<R>::T* __restrict__ out)
 {
     using R2 = typename V2<R>::T;
-    constexpr int L = 256 * SPT;
+    constexpr int L = LANES * SPT;
     const int64_t k = k0 + blockIdx.x;
     const int64_t w = blockIdx.y;
     const int lane = threadIdx.x;
@@ -367,15 +368,22 @@ static hipError_t synth_dispatch(const Plan& p, int64_t B, const char* base, voi
     const int2* hx = (p.prec == EMRI_MIXED) ? (const int2*)(base + p.off_hx) : nullptr;
     const double2* az = (const double2*)(base + p.off_az);
     R2* o = (R2*)out;
-#define EMRI_SYNTH(SPT)                                                                        \
-    hipLaunchKernelGGL((k_synth<R, HT, SPT>), grid, dim3(256), 0, s, p.K, p.Nv, p.N, p.nh, k0, \
+#define EMRI_SYNTH(SPT, LANES)                                                                 \
+    hipLaunchKernelGGL((k_synth<R, HT, SPT, LANES>), grid, dim3(LANES), 0, s, p.K, p.Nv, p.N, p.nh, k0, \
                        seg, zfill, p.dt, wc, co, ch, hx, az, o)
     switch (p.cl) {
-    case 8: EMRI_SYNTH(1); break;
-    case 9: EMRI_SYNTH(2); break;
-    case 10: EMRI_SYNTH(4); break;
-    case 11: EMRI_SYNTH(8); break;
-    case 12: EMRI_SYNTH(16); break;
+    case 8: EMRI_SYNTH(1, 256); break;
+    case 9: EMRI_SYNTH(2, 256); break;
+    case 10:
+        // FP32 at 8 samples per lane (116 VGPRs, still four waves per SIMD)
+        // shares each lane's fixed cost over twice the samples; FP64 at 8
+        // would take 166 VGPRs (three waves) and leave no room beside it for
+        // the amplitude tables of the next orbit segment
+        if constexpr (sizeof(R) == 4) EMRI_SYNTH(8, 128);
+        else EMRI_SYNTH(4, 256);
+        break;
+    case 11: EMRI_SYNTH(8, 256); break;
+    case 12: EMRI_SYNTH(16, 256); break;
     default: return hipErrorInvalidValue;
     }
 #undef EMRI_SYNTH

@@ -169,13 +169,29 @@ k_synth(int64_t K, int64_t Nv, int64_t N, int nh,
         ph[s] = Phi + dop * nu * cdel;                              // Doppler-shifted phase
     }
     angle_run<R, SPT>(ph, smooth, c1, s1);
+    if constexpr (sizeof(R) == 4) {
+        // the FP32 rotation chain leaves |e^{i Phi'}| a few rounding units
+        // off 1, an error of cos(Phi') that the recurrence below carries
+        // n^2-fold into harmonic n: renormalise by one Newton step for
+        // 1/sqrt(q) at q = 1 (r = (3 - q)/2, exact to O((q - 1)^2) and, with
+        // round-to-nearest arithmetic only, free of a systematic scale)
+#pragma unroll
+        for (int s = 1; s < SPT; ++s) {
+            const R q = fmaf(c1[s], c1[s], s1[s] * s1[s]);
+            const R r = fmaf(-0.5f, q, 1.5f);
+            c1[s] *= r;
+            s1[s] *= r;
+        }
+    }
 
     // ---- harmonic sum ------------------------------------------------------
     // cos/sin(n Phi') for n = 1..nh by the three-term recurrence
     // x_{n+1} = 2 cos(Phi') x_n - x_{n-1}: one FMA per value.  An error made
     // at step m is carried forward at most (n - m + 1)-fold (|U_k| <= k + 1),
-    // so harmonic n carries at most n^2/2 rounding units relative to its own
-    // amplitude; the sum's error is set by the strong low harmonics
+    // which sums to n^2/2 rounding units; an error dc of cos(Phi') itself
+    // moves T_n by at most n |U_{n-1}| |dc| <= n^2 |dc|.  Harmonic n so
+    // carries at most about (3/2) n^2 rounding units of its own amplitude; the
+    // sum's error is set by the strong harmonics
     R Sa[SPT], Sb[SPT], Sc[SPT], cn[SPT], sn[SPT], cq[SPT], sq[SPT], tc[SPT];
 #pragma unroll
     for (int s = 0; s < SPT; ++s) {

@@ -72,6 +72,53 @@ def test_waveform_parity_small(E, prec):
     assert np.all(got[:, :, w.n_valid:] == 0.0)
 
 
+def harmonic_contributions(w, P) -> np.ndarray:
+    """max_t |h^(n)(t)| per harmonic n = 1..n_harm and walker: the oracle's
+    waveform with n harmonics minus the one with n - 1"""
+    prev = np.zeros((len(P), 2, w.N))
+    out = []
+    for n in range(1, w.n_harm + 1):
+        cur = O.waveform(P, ocfg(w.with_(n_harm=n)))
+        out.append(np.max(np.abs(cur - prev), axis=(1, 2)))
+        prev = cur
+    return np.array(out)                                  # [n_harm][B]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_high_harmonics_at_high_eccentricity(E, prec):
+    """cos/sin(n Phi') come from the three-term recurrence.  At e0 = 0.85
+    harmonics 33..64 carry about a quarter of max|h| (the oracle's waveform
+    with 32 harmonics differs by 0.28 max|h|), so the top harmonics' error
+    shows in the waveform.  FP64: the phase-rounding tolerance of the other
+    waveform tests.  FP32, per harmonic n in units u = 2^-24 of its largest
+    contribution A_n: (3/2) n^2 from the recurrence (n^2/2 from its steps'
+    roundings, n^2 from the rounding of cos Phi'), 20 n from the phase
+    (reduced modulo 2 pi in FP64, rounded to FP32: pi u; then at most 7
+    rotations of 2 u along a lane's samples), 70 for the amplitude cubic and
+    the sum of up to 64 terms; and 64 u of max|h| for the response:
+    |dh| <= u (sum_n (1.5 n^2 + 20 n + 70) A_n + 64 max|h|)."""
+    w = W.small(prec, n_harm=64, e0=0.85, nu0=1.5e-4)
+    P = W.walkers(w, B=2)
+    say("high harmonics", prec, w.n_harm, P.shape)
+    cfg = E.Config.from_workload(w)
+    got = E.waveform_batch(gpu_params(P), cfg).cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    got = got.transpose(0, 2, 1)
+    ref = O.waveform(P, ocfg(w))
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(got - ref), axis=(1, 2)) / scale
+    say("max rel err per walker", err)
+    if prec == "fp64":
+        tol = 64 * w.n_harm * max_phase(w, P) * EPS64
+    else:
+        A = harmonic_contributions(w.with_(precision="fp64"), P)
+        n = np.arange(1, w.n_harm + 1)[:, None]
+        u = 2.0 ** -24
+        tol = u * ((1.5 * n ** 2 + 20 * n + 70) * A).sum(axis=0) / scale + 64 * u
+        say("bound per walker", tol)
+    assert np.all(err <= tol), (err, tol)
+
+
 def plunge_workload(cl):
     w = W.small("fp64", n_harm=6, days=20.0, N=1 << 18, M=1e5, e0=0.5, a=0.9, nu0=6.3e-3)
     return w.with_(coarse_log2=cl)

@@ -631,7 +631,7 @@ k_row_like(const typename C2<R>::T* __restrict__ z, int64_t N, int L, int lgL, i
 {
     using T2 = typename C2<R>::T;
     extern __shared__ unsigned char smem_raw[];
-    __shared__ double sh[16];
+    __shared__ double shp[32 * 8];   // per (walker of the tile, wave): the wave's sum
     R* sre = (R*)smem_raw;
     R* sim = sre + padded_len<R>(L);
     const int64_t ntiles = (B + WT - 1) / WT;
@@ -645,15 +645,18 @@ k_row_like(const typename C2<R>::T* __restrict__ z, int64_t N, int L, int lgL, i
     const int RL = last_radix16(lgL);
     const T2* Qr = Q + g * L;
     const R* Sr = SV + g * L;
+    const int nw = (blockDim.x + 63) >> 6;
+    int nwk = 0;                       // walkers of this tile
 
     for (int wi = 0; wi < WT; ++wi) {
         const int64_t w = tile * WT + wi;
         if (w >= B) break;
+        nwk = wi + 1;
         int t = t0;
         asm volatile("" : "+v"(t));
         const double* c = wc + w * WC;
         if (c[WC_VALID] == 0.0) {
-            if (t == 0) part[w * R2 + g] = 0.0;
+            if (t < nw) shp[wi * nw + t] = 0.0;
             continue;
         }
         const T2* zr = z + w * N + g * L;
@@ -685,9 +688,18 @@ k_row_like(const typename C2<R>::T* __restrict__ z, int64_t N, int L, int lgL, i
             }
             acc.add(ar, ai, scale, Sr[p], Qr[p]);
         }
-        const double s = block_sum(acc.lane_sum(), sh);
-        if (t == 0) part[w * R2 + g] = s;
-        // block_sum ends with a barrier: LDS may be overwritten by the next walker
+        // the wave's sum; the walker's sum over the waves is formed after
+        // the last walker, so no barrier waits on it here (the next
+        // walker's first exchange starts with one before LDS is rewritten)
+        double v = acc.lane_sum();
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((t & 63) == 0) shp[wi * nw + (t >> 6)] = v;
+    }
+    __syncthreads();
+    if (t0 < nwk) {                    // the waves' sums in a fixed order
+        double r = 0.0;
+        for (int i = 0; i < nw; ++i) r += shp[t0 * nw + i];
+        part[(tile * WT + t0) * R2 + g] = r;
     }
 }
 

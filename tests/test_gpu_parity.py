@@ -119,6 +119,27 @@ def test_high_harmonics_at_high_eccentricity(E, prec):
     assert np.all(err <= tol), (err, tol)
 
 
+@pytest.mark.parametrize("e0", [1e-4, 1e-7])
+def test_nearly_circular_orbits(E, e0):
+    """Bessel functions at X = n e down to 1e-7: Miller's recurrence grows by
+    about 2q/X per step, so its running rescale (checked once per pair of
+    steps) fires several times and the high orders reach the FP64 underflow
+    range (the oracle's J_67(67e-4) is 4e-261, smaller ones are 0).  FP64
+    waveform against the oracle with 64 harmonics, the phase-rounding
+    tolerance of the other waveform tests."""
+    w = W.small("fp64", n_harm=64, e0=e0)
+    P = W.walkers(w, B=2)
+    say("nearly circular", e0, P[:, 3])
+    got = E.waveform_batch(gpu_params(P), E.Config.from_workload(w)).cpu().numpy()
+    torch.cuda.synchronize()
+    got = got.transpose(0, 2, 1)
+    ref = O.waveform(P, ocfg(w))
+    err = np.max(np.abs(got - ref), axis=(1, 2)) / np.max(np.abs(ref))
+    say("max rel err per walker", err)
+    assert np.all(np.isfinite(got))
+    assert np.all(err <= 64 * w.n_harm * max_phase(w, P) * EPS64), err
+
+
 def plunge_workload(cl):
     w = W.small("fp64", n_harm=6, days=20.0, N=1 << 18, M=1e5, e0=0.5, a=0.9, nu0=6.3e-3)
     return w.with_(coarse_log2=cl)

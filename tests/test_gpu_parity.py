@@ -122,9 +122,10 @@ def test_high_harmonics_at_high_eccentricity(E, prec):
 @pytest.mark.parametrize("e0", [1e-4, 1e-7])
 def test_nearly_circular_orbits(E, e0):
     """Bessel functions at X = n e down to 1e-7: Miller's recurrence grows by
-    about 2q/X per step, so its running rescale (checked once per pair of
-    steps) fires several times and the high orders reach the FP64 underflow
-    range (the oracle's J_67(67e-4) is 4e-261, smaller ones are 0).  FP64
+    about 2q/X per step (by some 1e480 from order 70 to 0 at X = 6.4e-6), so
+    at e0 = 1e-7 its running rescale (checked once per pair of steps) fires,
+    and the high orders reach the FP64 underflow range (the oracle's
+    J_67(67e-4) is 4e-261, smaller ones are 0).  FP64
     waveform against the oracle with 64 harmonics, the phase-rounding
     tolerance of the other waveform tests."""
     w = W.small("fp64", n_harm=64, e0=e0)
